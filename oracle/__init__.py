@@ -1,0 +1,218 @@
+"""FP64 CPU oracle for the WETSAND hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path
+(``paper_2404_12134_amd``) never imports, links or calls it, and the two share
+no code: the C source ``wts_oracle.c`` is a plain transcription of the
+paper's definitions (Sec. III, Eq. 1-8) in FP64, and ``brute.py`` enumerates
+every alignment path of tiny inputs to pin it.
+
+``build()`` compiles ``wts_oracle.c`` with gcc (-O2 -ffp-contract=off,
+OpenMP); ``lib()`` loads it, building it first if no library is there.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "wts_oracle.c")
+SO = os.path.join(HERE, "libwts_oracle.so")
+
+SQEUCLID, EUCLID = 0, 1
+
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle shared library (always recompiles)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-o", SO + ".tmp", SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(SO + ".tmp", SO)
+    return SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            build()
+        L = ctypes.CDLL(SO)
+        P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        L.wts_o_cost.restype = D
+        L.wts_o_cost.argtypes = [P, P, I32, I32]
+        L.wts_o_dtw.argtypes = [P, I64, P, I64, I32, I32, P, P, P, P]
+        L.wts_o_dtw_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P]
+        L.wts_o_score_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P, P]
+        L.wts_o_dba_iterate.argtypes = [P, I64, P, P, I32, I32, P, P, P, P, P]
+        L.wts_o_softdtw.argtypes = [P, I64, P, I64, I32, D, P, P]
+        L.wts_o_softdtw_grad.argtypes = [P, I64, P, I64, I32, D, P, P, P, P]
+        L.wts_o_softdtw_batch.argtypes = [P, I64, P, P, I32, I32, D, P, P, P, P]
+        L.wts_o_medoid.argtypes = [P, P, I32, I32, P, P]
+        L.wts_o_resample.argtypes = [P, I64, I32, I64, P]
+        L.wts_o_resample.restype = None
+        L.wts_o_euclid_mean.argtypes = [P, P, I32, I32, I64, P]
+        L.wts_o_nearest_init.argtypes = [P, P, I32, I32, I64, P]
+        for f in ("wts_o_dtw", "wts_o_dtw_batch", "wts_o_score_batch", "wts_o_dba_iterate",
+                  "wts_o_softdtw", "wts_o_softdtw_grad", "wts_o_softdtw_batch", "wts_o_medoid",
+                  "wts_o_euclid_mean", "wts_o_nearest_init", "wts_o_num_threads"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _series(x):
+    x = _f64(x)
+    return x if x.ndim == 2 else x.reshape(-1, 1)
+
+
+def _packed(cycles):
+    cyc = [_series(c) for c in cycles]
+    off = np.zeros(len(cyc) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([c.shape[0] for c in cyc])
+    return _f64(np.concatenate(cyc, axis=0)), off
+
+
+def _check(rc):
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+
+
+def num_threads() -> int:
+    return int(lib().wts_o_num_threads())
+
+
+def cost(x, y, kind=SQEUCLID) -> float:
+    x, y = _f64(x).ravel(), _f64(y).ravel()
+    return float(lib().wts_o_cost(_p(x), _p(y), x.size, kind))
+
+
+def dtw(X, Y, kind=SQEUCLID, with_path=True, with_codes=False):
+    """Eq. 1: returns (dist, |pi|, path [|pi|][2] or None, codes [M][N] or None)."""
+    X, Y = _series(X), _series(Y)
+    M, N, d = X.shape[0], Y.shape[0], X.shape[1]
+    dist = np.zeros(1)
+    plen = np.zeros(1, dtype=np.int64)
+    path = np.zeros((M + N - 1, 2), dtype=np.int32) if with_path else None
+    codes = np.zeros((M, N), dtype=np.uint8) if with_codes else None
+    _check(lib().wts_o_dtw(_p(X), M, _p(Y), N, d, kind, _p(dist), _p(plen), _p(path),
+                           _p(codes)))
+    k = int(plen[0])
+    return float(dist[0]), k, (path[:k].copy() if with_path else None), codes
+
+
+def dtw_batch(X, cycles, kind=SQEUCLID):
+    X = _series(X)
+    Y, off = _packed(cycles)
+    n = len(cycles)
+    dist = np.zeros(n)
+    plen = np.zeros(n, dtype=np.int64)
+    _check(lib().wts_o_dtw_batch(_p(X), X.shape[0], _p(Y), _p(off), n, X.shape[1], kind,
+                                 _p(dist), _p(plen)))
+    return dist, plen
+
+
+def score_batch(B, cycles, kind=SQEUCLID):
+    """Eq. 8 for every cycle: returns (score, dist, |pi|)."""
+    B = _series(B)
+    Y, off = _packed(cycles)
+    n = len(cycles)
+    score, dist = np.zeros(n), np.zeros(n)
+    plen = np.zeros(n, dtype=np.int64)
+    _check(lib().wts_o_score_batch(_p(B), B.shape[0], _p(Y), _p(off), n, B.shape[1], kind,
+                                   _p(score), _p(dist), _p(plen)))
+    return score, dist, plen
+
+
+def dba_iterate(B, cycles, weights=None):
+    """One DBA iteration: returns (B', K counts, dist, |pi|)."""
+    B = _series(B)
+    Y, off = _packed(cycles)
+    n, L, d = len(cycles), B.shape[0], B.shape[1]
+    w = None if weights is None else _f64(weights)
+    Bout = np.zeros((L, d))
+    counts = np.zeros(L, dtype=np.int64)
+    dist = np.zeros(n)
+    plen = np.zeros(n, dtype=np.int64)
+    _check(lib().wts_o_dba_iterate(_p(B), L, _p(Y), _p(off), n, d, _p(w), _p(Bout), _p(counts),
+                                   _p(dist), _p(plen)))
+    return Bout, counts, dist, plen
+
+
+def softdtw(X, Y, gamma, with_R=False):
+    X, Y = _series(X), _series(Y)
+    M, N = X.shape[0], Y.shape[0]
+    v = np.zeros(1)
+    R = np.zeros((M, N)) if with_R else None
+    _check(lib().wts_o_softdtw(_p(X), M, _p(Y), N, X.shape[1], float(gamma), _p(v), _p(R)))
+    return (float(v[0]), R) if with_R else float(v[0])
+
+
+def softdtw_grad(X, Y, gamma, with_E=False):
+    """Eq. 6: returns (value, grad [M][d], rowmass [M], E [M][N] or None)."""
+    X, Y = _series(X), _series(Y)
+    M, N, d = X.shape[0], Y.shape[0], X.shape[1]
+    v = np.zeros(1)
+    g = np.zeros((M, d))
+    h = np.zeros(M)
+    E = np.zeros((M, N)) if with_E else None
+    _check(lib().wts_o_softdtw_grad(_p(X), M, _p(Y), N, d, float(gamma), _p(v), _p(g), _p(h),
+                                    _p(E)))
+    return float(v[0]), g, h, E
+
+
+def softdtw_batch(X, cycles, gamma, weights=None, grad=True):
+    """Values [n] and, if grad, (sum_i w_i dSDTW_i/dX [M][d], sum_i w_i rowmass_i [M])."""
+    X = _series(X)
+    Y, off = _packed(cycles)
+    n, M, d = len(cycles), X.shape[0], X.shape[1]
+    w = None if weights is None else _f64(weights)
+    vals = np.zeros(n)
+    g = np.zeros((M, d)) if grad else None
+    h = np.zeros(M) if grad else None
+    _check(lib().wts_o_softdtw_batch(_p(X), M, _p(Y), _p(off), n, d, float(gamma), _p(w),
+                                     _p(vals), _p(g), _p(h)))
+    return (vals, g, h) if grad else vals
+
+
+def medoid(cycles):
+    Y, off = _packed(cycles)
+    n, d = len(cycles), Y.shape[1]
+    D = np.zeros((n, n))
+    k = np.zeros(1, dtype=np.int32)
+    _check(lib().wts_o_medoid(_p(Y), _p(off), n, d, _p(D), _p(k)))
+    return int(k[0]), D
+
+
+def resample(Y, L):
+    Y = _series(Y)
+    out = np.zeros((L, Y.shape[1]))
+    lib().wts_o_resample(_p(Y), Y.shape[0], Y.shape[1], L, _p(out))
+    return out
+
+
+def euclid_mean(cycles, L):
+    Y, off = _packed(cycles)
+    out = np.zeros((L, Y.shape[1]))
+    _check(lib().wts_o_euclid_mean(_p(Y), _p(off), len(cycles), Y.shape[1], L, _p(out)))
+    return out
+
+
+def nearest_init(cycles, L):
+    Y, off = _packed(cycles)
+    out = np.zeros((L, Y.shape[1]))
+    k = lib().wts_o_nearest_init(_p(Y), _p(off), len(cycles), Y.shape[1], L, _p(out))
+    return int(k), out

@@ -1,0 +1,154 @@
+"""Brute force over every complete alignment path -- pins the oracle.
+
+TEST INFRASTRUCTURE ONLY.  Pure Python, for series of length <= 6 or so.
+It does not run a dynamic program: it lists every alignment path of
+Def. 1 (steps (0,1), (1,0), (1,1) from (1,1) to (M,N)) and evaluates the
+definitions directly:
+
+* DTW (Eq. 1): the minimum over paths of <A, Delta>.
+* Soft-DTW (Eq. 4): -gamma log sum_paths exp(-<A, Delta> / gamma).
+* E (the matrix of Eq. 6): the Gibbs expectation of the alignment matrix,
+  sum_paths A * p(path) with p proportional to exp(-<A, Delta> / gamma).
+  This is the derivative of Soft-DTW with respect to Delta.
+* the optimal path under the tie-break that the oracle's backtrack applies:
+  among the paths of minimal cost, the one whose backward step sequence
+  (from (M, N) towards (1, 1)) is lexicographically smallest with
+  diag < up < left.
+
+The number of complete paths of an M x N grid is the Delannoy number
+D(M-1, N-1) = sum_k C(M-1, k) C(N-1, k) 2^k.
+"""
+
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+from functools import lru_cache
+from typing import List, Tuple
+
+import numpy as np
+
+DIAG, UP, LEFT = 0, 1, 2
+
+
+def delannoy(m: int, n: int) -> int:
+    return sum(math.comb(m, k) * math.comb(n, k) * (1 << k) for k in range(min(m, n) + 1))
+
+
+def all_paths(M: int, N: int) -> List[List[Tuple[int, int]]]:
+    """Every complete alignment path of an M x N grid, 0-based, forward order."""
+
+    @lru_cache(maxsize=None)
+    def from_cell(i, j):
+        if i == M - 1 and j == N - 1:
+            return [((i, j),)]
+        out = []
+        for di, dj in ((0, 1), (1, 0), (1, 1)):
+            a, b = i + di, j + dj
+            if a < M and b < N:
+                out.extend(((i, j),) + rest for rest in from_cell(a, b))
+        return out
+
+    return [list(p) for p in from_cell(0, 0)]
+
+
+def fma(a: float, b: float, c: float) -> float:
+    """a*b + c rounded once (exact rational arithmetic, then one rounding)."""
+    return float(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def delta(x, y, kind="sq"):
+    """Def. 3, squared Euclidean (or its square root), same operation order
+    as the oracle: e_0*e_0, then fma(e_c, e_c, s)."""
+    x = np.asarray(x, dtype=np.float64).ravel()
+    y = np.asarray(y, dtype=np.float64).ravel()
+    e = float(x[0] - y[0])
+    s = e * e
+    for c in range(1, x.size):
+        e = float(x[c] - y[c])
+        s = fma(e, e, s)
+    return math.sqrt(s) if kind == "l2" else s
+
+
+def path_cost(X, Y, path, kind="sq") -> float:
+    """<A, Delta> accumulated along the path from (1,1), c = delta + c."""
+    c = 0.0
+    for i, j in path:
+        c = delta(X[i], Y[j], kind) + c
+    return c
+
+
+def backward_steps(path) -> Tuple[int, ...]:
+    steps = []
+    for (i0, j0), (i1, j1) in zip(path[-2::-1], path[::-1]):
+        di, dj = i1 - i0, j1 - j0
+        steps.append(DIAG if (di, dj) == (1, 1) else UP if (di, dj) == (1, 0) else LEFT)
+    return tuple(steps)
+
+
+def _series(a):
+    a = np.asarray(a, dtype=np.float64)
+    return a.reshape(-1, 1) if a.ndim == 1 else a
+
+
+def dtw(X, Y, kind="sq"):
+    """Returns (min cost, tie-broken optimal path, number of optimal paths)."""
+    X, Y = _series(X), _series(Y)
+    paths = all_paths(X.shape[0], Y.shape[0])
+    costs = [path_cost(X, Y, p, kind) for p in paths]
+    best = min(costs)
+    opt = [p for p, c in zip(paths, costs) if c == best]
+    chosen = min(opt, key=backward_steps)
+    return best, chosen, len(opt)
+
+
+def softdtw(X, Y, gamma):
+    X, Y = _series(X), _series(Y)
+    costs = np.array([path_cost(X, Y, p) for p in all_paths(X.shape[0], Y.shape[0])])
+    m = costs.min()
+    return float(m - gamma * math.log(math.fsum(np.exp(-(costs - m) / gamma))))
+
+
+def gibbs_E(X, Y, gamma):
+    """E = sum over paths of A(path) * p(path)."""
+    X, Y = _series(X), _series(Y)
+    M, N = X.shape[0], Y.shape[0]
+    paths = all_paths(M, N)
+    costs = np.array([path_cost(X, Y, p) for p in paths])
+    wts = np.exp(-(costs - costs.min()) / gamma)
+    wts = wts / math.fsum(wts)
+    E = np.zeros((M, N))
+    for p, w in zip(paths, wts):
+        for i, j in p:
+            E[i, j] += w
+    return E
+
+
+def dba_iterate(B, cycles, weights=None):
+    """One DBA step computed from brute-force optimal paths, summed in the
+    order a backtrack visits each row (descending j), then ascending cycle."""
+    B = _series(B)
+    L, d = B.shape
+    n = len(cycles)
+    w = [1.0] * n if weights is None else [float(v) for v in weights]
+    psum = np.zeros((n, L, d))
+    pcnt = np.zeros((n, L), dtype=np.int64)
+    for p, Y in enumerate(cycles):
+        Y = _series(Y)
+        _, path, _ = dtw(B, Y)
+        for i, j in reversed(path):
+            for c in range(d):
+                psum[p, i, c] = psum[p, i, c] + Y[j, c]
+            pcnt[p, i] += 1
+    out = np.zeros((L, d))
+    K = pcnt.sum(axis=0)
+    for l in range(L):
+        C = 0.0
+        for p in range(n):
+            C = C + w[p] * float(pcnt[p, l])
+        for c in range(d):
+            S = 0.0
+            for p in range(n):
+                S = S + w[p] * psum[p, l, c]
+            out[l, c] = S / C
+    return out, K

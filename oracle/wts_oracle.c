@@ -1,0 +1,465 @@
+/*
+ * wts_oracle.c -- plain FP64 CPU oracle for the WETSAND hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only tests/, the smoke check and the bench's CPU baseline
+ * leg do.  It shares no code with the HIP path (paper_2404_12134_amd/csrc).
+ *
+ * Everything is the textbook dynamic program written out, in FP64, compiled
+ * with -O2 -ffp-contract=off (no FMA contraction, no fast-math), one
+ * single-threaded row-major DP per pair, OpenMP across pairs.  The notation
+ * follows the paper (Sec. III):
+ *   X in R^{d x M} (here: the barycenter B, M = L rows), Y in R^{d x N},
+ *   delta_{ij} = delta(x_i, y_j)                              (Def. 3)
+ *   r_{0,0} = 0, r_{i,0} = r_{0,j} = inf,
+ *   r_{ij} = delta_{ij} + min^gamma(r_{i-1,j-1}, r_{i-1,j}, r_{i,j-1})   (Eq. 5)
+ *   gamma = 0 is DTW (Eq. 1), gamma > 0 Soft-DTW (Eq. 4); soft-min Eq. 3.
+ * Arrays are 0-based here: cell (i, j) of the code is cell (i+1, j+1) of the
+ * paper.  Series are time-major: x_i is X[i*d .. i*d+d-1].
+ *
+ * Readings of the paper taken here (each is listed in the design notes):
+ *  - delta is the squared Euclidean distance by default; the plain l2 norm is
+ *    available for DTW values and scores (Def. 3 names "Euclidean distance,
+ *    or l2 norm").
+ *  - the soft-min of Eq. 3 is -gamma log sum exp(-a_i / gamma) (the printed
+ *    exponent is garbled; this is the only form that tends to min as
+ *    gamma -> 0).
+ *  - the optimal path of a DTW alignment (Eq. 8 needs "their optimal
+ *    alignment path") is the one found by backtracking from (M, N) and taking,
+ *    at each cell, the first predecessor in the order diag, up (i-1, j),
+ *    left (i, j-1) whose cumulative cost equals the minimum.
+ *  - the DBA update (cited by the paper, Petitjean et al. 2011) averages, for
+ *    each barycenter row, every cycle sample aligned to it by that path.
+ *  - the E matrix of Eq. 6 is derived from Eq. 5 by the chain rule (the paper
+ *    does not print it), with the boundary values 0 and 1 of its backward
+ *    buffers (Fig. "gpu-buffers").
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define O_SQEUCLID 0
+#define O_EUCLID 1
+
+#define CODE_DIAG 0
+#define CODE_UP 1
+#define CODE_LEFT 2
+
+/* Def. 3: delta(x, y).  Squared Euclidean in a fixed order:
+ * e_c = x_c - y_c; s = e_0 * e_0; s = fma(e_c, e_c, s) for c = 1..d-1.
+ * The l2 norm is sqrt(s) (correctly rounded). */
+double wts_o_cost(const double* x, const double* y, int d, int kind) {
+  double e = x[0] - y[0];
+  double s = e * e;
+  for (int c = 1; c < d; ++c) {
+    e = x[c] - y[c];
+    s = fma(e, e, s);
+  }
+  return kind == O_EUCLID ? sqrt(s) : s;
+}
+
+/* Eq. 1 / Eq. 5 with gamma = 0, plus the optimal path.
+ *   dist  <- r_{M,N}
+ *   plen  <- |pi|, the number of index pairs on the optimal path
+ *   path  <- the path in forward order as (i, j) int32 pairs, or NULL
+ *   codes <- M*N argmin codes (0 diag, 1 up, 2 left), or NULL
+ * Returns 0, or -1 on allocation failure. */
+int wts_o_dtw(const double* X, int64_t M, const double* Y, int64_t N, int d, int kind,
+              double* dist, int64_t* plen, int32_t* path, uint8_t* codes_out) {
+  uint8_t* code = codes_out ? codes_out : (uint8_t*)malloc((size_t)(M * N));
+  double* prev = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* cur = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  if (!code || !prev || !cur) {
+    free(prev); free(cur);
+    if (!codes_out) free(code);
+    return -1;
+  }
+  /* row "0" of the paper: r_{0,0} = 0, r_{0,j} = inf.  prev[j+1] = r(i-1, j),
+   * prev[0] = r(i-1, -1). */
+  prev[0] = 0.0;
+  for (int64_t j = 0; j < N; ++j) prev[j + 1] = INFINITY;
+  for (int64_t i = 0; i < M; ++i) {
+    cur[0] = INFINITY;
+    for (int64_t j = 0; j < N; ++j) {
+      double dg = prev[j], up = prev[j + 1], lf = cur[j];
+      double m = dg;
+      uint8_t c = CODE_DIAG;
+      if (up < m) { m = up; c = CODE_UP; }
+      if (lf < m) { m = lf; c = CODE_LEFT; }
+      cur[j + 1] = wts_o_cost(X + i * d, Y + j * d, d, kind) + m;
+      code[i * N + j] = c;
+    }
+    double* t = prev; prev = cur; cur = t;
+    prev[0] = INFINITY;
+  }
+  *dist = prev[N];
+  /* backtrack from (M-1, N-1) to (0, 0) */
+  int64_t i = M - 1, j = N - 1, k = 0;
+  int64_t cap = M + N - 1;
+  int32_t* rev = path ? (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)cap) : NULL;
+  for (;;) {
+    if (rev) { rev[2 * k] = (int32_t)i; rev[2 * k + 1] = (int32_t)j; }
+    ++k;
+    if (i == 0 && j == 0) break;
+    uint8_t c = code[i * N + j];
+    if (c == CODE_DIAG) { --i; --j; }
+    else if (c == CODE_UP) { --i; }
+    else { --j; }
+  }
+  *plen = k;
+  if (rev) {
+    for (int64_t q = 0; q < k; ++q) {
+      path[2 * q] = rev[2 * (k - 1 - q)];
+      path[2 * q + 1] = rev[2 * (k - 1 - q) + 1];
+    }
+    free(rev);
+  }
+  free(prev); free(cur);
+  if (!codes_out) free(code);
+  return 0;
+}
+
+/* Eq. 1 for a whole batch against one X; OpenMP across cycles. */
+int wts_o_dtw_batch(const double* X, int64_t M, const double* Yall, const int64_t* off, int n,
+                    int d, int kind, double* dist, int64_t* plen) {
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int p = 0; p < n; ++p) {
+    int64_t len = 0;
+    err |= wts_o_dtw(X, M, Yall + off[p] * d, off[p + 1] - off[p], d, kind, &dist[p], &len, NULL,
+                     NULL);
+    if (plen) plen[p] = len;
+  }
+  return err ? -1 : 0;
+}
+
+/* Eq. 8: d_score = DTW(B, C_k) / |pi| for every cycle. */
+int wts_o_score_batch(const double* B, int64_t L, const double* Yall, const int64_t* off, int n,
+                      int d, int kind, double* score, double* dist, int64_t* plen) {
+  int err = wts_o_dtw_batch(B, L, Yall, off, n, d, kind, dist, plen);
+  for (int p = 0; p < n; ++p) score[p] = dist[p] / (double)plen[p];
+  return err;
+}
+
+/* Per-pair part of one DBA iteration: backtrack the optimal path of (B, Y)
+ * and, for every barycenter row l, sum the aligned samples y_j in the order
+ * the backtrack visits them (descending j), starting from +0.0.
+ *   psum[l*d + c], pcnt[l] are overwritten. */
+static int dba_pair(const double* B, int64_t L, const double* Y, int64_t N, int d,
+                    double* psum, int64_t* pcnt, double* dist, int64_t* plen) {
+  uint8_t* code = (uint8_t*)malloc((size_t)(L * N));
+  if (!code) return -1;
+  int64_t len = 0;
+  if (wts_o_dtw(B, L, Y, N, d, O_SQEUCLID, dist, &len, NULL, code)) { free(code); return -1; }
+  *plen = len;
+  for (int64_t l = 0; l < L * d; ++l) psum[l] = 0.0;
+  for (int64_t l = 0; l < L; ++l) pcnt[l] = 0;
+  int64_t i = L - 1, j = N - 1;
+  for (;;) {
+    for (int c = 0; c < d; ++c) psum[i * d + c] = psum[i * d + c] + Y[j * d + c];
+    pcnt[i] += 1;
+    if (i == 0 && j == 0) break;
+    uint8_t c = code[i * N + j];
+    if (c == CODE_DIAG) { --i; --j; }
+    else if (c == CODE_UP) { --i; }
+    else { --j; }
+  }
+  free(code);
+  return 0;
+}
+
+/* One DBA iteration (Petitjean et al. 2011, cited by the paper as the DBA
+ * barycenter it compares against).  With the paths pi_i of (B, Y_i):
+ *   S_l = sum_{i ascending} w_i * (sum of y_ij aligned to row l)
+ *   C_l = sum_{i ascending} w_i * |run_i(l)|
+ *   K_l = sum_i |run_i(l)|              (integer alignment counts)
+ *   B'_l = S_l / C_l
+ * w = NULL means every w_i = 1.  counts <- K, dist/plen <- per-cycle DTW
+ * value and path length (either may be NULL). */
+int wts_o_dba_iterate(const double* B, int64_t L, const double* Yall, const int64_t* off, int n,
+                      int d, const double* w, double* Bout, int64_t* counts, double* dist,
+                      int64_t* plen) {
+  double* psum = (double*)malloc(sizeof(double) * (size_t)(n * L * d));
+  int64_t* pcnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n * L));
+  double* pd = (double*)malloc(sizeof(double) * (size_t)n);
+  int64_t* pl = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  if (!psum || !pcnt || !pd || !pl) { free(psum); free(pcnt); free(pd); free(pl); return -1; }
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int p = 0; p < n; ++p)
+    err |= dba_pair(B, L, Yall + off[p] * d, off[p + 1] - off[p], d, psum + (int64_t)p * L * d,
+                    pcnt + (int64_t)p * L, &pd[p], &pl[p]);
+  if (!err) {
+    for (int64_t l = 0; l < L; ++l) {
+      double C = 0.0;
+      int64_t K = 0;
+      for (int c = 0; c < d; ++c) {
+        double S = 0.0;
+        for (int p = 0; p < n; ++p) {
+          double wp = w ? w[p] : 1.0;
+          S = S + wp * psum[((int64_t)p * L + l) * d + c];
+        }
+        Bout[l * d + c] = S;
+      }
+      for (int p = 0; p < n; ++p) {
+        double wp = w ? w[p] : 1.0;
+        C = C + wp * (double)pcnt[(int64_t)p * L + l];
+        K += pcnt[(int64_t)p * L + l];
+      }
+      for (int c = 0; c < d; ++c) Bout[l * d + c] = Bout[l * d + c] / C;
+      if (counts) counts[l] = K;
+    }
+    for (int p = 0; p < n; ++p) {
+      if (dist) dist[p] = pd[p];
+      if (plen) plen[p] = pl[p];
+    }
+  }
+  free(psum); free(pcnt); free(pd); free(pl);
+  return err ? -1 : 0;
+}
+
+/* Eq. 3 for three arguments, gamma > 0:
+ *   min^gamma(a) = m - gamma * log(sum_k exp(-(a_k - m) / gamma)),  m = min_k a_k,
+ * which is -gamma log sum exp(-a_k / gamma) shifted by m for range; +inf if
+ * every argument is +inf. */
+static double softmin3(double a, double b, double c, double gamma) {
+  double m = a;
+  if (b < m) m = b;
+  if (c < m) m = c;
+  if (m == INFINITY) return INFINITY;
+  double s = exp(-(a - m) / gamma) + exp(-(b - m) / gamma) + exp(-(c - m) / gamma);
+  return m - gamma * log(s);
+}
+
+/* Eq. 4-5: Soft-DTW^gamma(X, Y) = r_{M,N} with the soft-min recursion (squared
+ * Euclidean delta).  R (M*N, row-major, r(i, j) of the 0-based grid) is
+ * filled when non-NULL. */
+int wts_o_softdtw(const double* X, int64_t M, const double* Y, int64_t N, int d, double gamma,
+                  double* value, double* R) {
+  double* prev = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* cur = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  if (!prev || !cur) { free(prev); free(cur); return -1; }
+  prev[0] = 0.0;
+  for (int64_t j = 0; j < N; ++j) prev[j + 1] = INFINITY;
+  for (int64_t i = 0; i < M; ++i) {
+    cur[0] = INFINITY;
+    for (int64_t j = 0; j < N; ++j) {
+      double r = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID) +
+                 softmin3(prev[j], prev[j + 1], cur[j], gamma);
+      cur[j + 1] = r;
+      if (R) R[i * N + j] = r;
+    }
+    double* t = prev; prev = cur; cur = t;
+    prev[0] = INFINITY;
+  }
+  *value = prev[N];
+  free(prev); free(cur);
+  return 0;
+}
+
+/* Eq. 6: gradient of Soft-DTW^gamma(X, Y) with respect to X.
+ * E is obtained from Eq. 5 by the chain rule.  On the grid extended by one
+ * row and one column:
+ *   r(M, j) = r(i, N) = -inf except r(M, N) = r(M-1, N-1); delta = 0 outside;
+ *   e(M, N) = 1; every other e outside the grid = 0;
+ *   e(i, j) = sum over the successors (i+1, j), (i, j+1), (i+1, j+1) of
+ *             e(p, q) * exp((r(p, q) - delta(p, q) - r(i, j)) / gamma).
+ * With the squared Euclidean delta, d delta_{ij} / d x_i = 2 (x_i - y_j), so
+ *   grad_i = sum_j e(i, j) * 2 (x_i - y_j)   (j ascending).
+ * Outputs: value, grad (M*d), rowmass (M, sum_j e(i,j); may be NULL),
+ * E (M*N; may be NULL).  Needs M*N doubles for R. */
+int wts_o_softdtw_grad(const double* X, int64_t M, const double* Y, int64_t N, int d,
+                       double gamma, double* value, double* grad, double* rowmass, double* E) {
+  double* R = (double*)malloc(sizeof(double) * (size_t)(M * N));
+  double* enext = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* ecur = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* rnext = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* dnext = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  if (!R || !enext || !ecur || !rnext || !dnext) {
+    free(R); free(enext); free(ecur); free(rnext); free(dnext);
+    return -1;
+  }
+  wts_o_softdtw(X, M, Y, N, d, gamma, value, R);
+  /* row M (outside): r = -inf except r(M, N) = r(M-1, N-1); e = 0 except e(M, N) = 1 */
+  for (int64_t j = 0; j <= N; ++j) { enext[j] = 0.0; rnext[j] = -INFINITY; dnext[j] = 0.0; }
+  enext[N] = 1.0;
+  rnext[N] = R[(M - 1) * N + (N - 1)];
+  for (int64_t i = M - 1; i >= 0; --i) {
+    /* column N (outside) of row i: r = -inf, e = 0, delta = 0 */
+    double e_right = 0.0, r_right = -INFINITY, d_right = 0.0;
+    for (int64_t j = N - 1; j >= 0; --j) {
+      double rij = R[i * N + j];
+      double e = 0.0;
+      e = e + enext[j] * exp((rnext[j] - dnext[j] - rij) / gamma);              /* (i+1, j)   */
+      e = e + e_right * exp((r_right - d_right - rij) / gamma);                 /* (i, j+1)   */
+      e = e + enext[j + 1] * exp((rnext[j + 1] - dnext[j + 1] - rij) / gamma);  /* (i+1, j+1) */
+      ecur[j] = e;
+      e_right = e;
+      r_right = rij;
+      d_right = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID);
+      if (E) E[i * N + j] = e;
+    }
+    /* gradient row i, then shift row i into the "next" buffers */
+    double mass = 0.0;
+    for (int c = 0; c < d; ++c) {
+      double g = 0.0;
+      for (int64_t j = 0; j < N; ++j) g = g + ecur[j] * (2.0 * (X[i * d + c] - Y[j * d + c]));
+      grad[i * d + c] = g;
+    }
+    for (int64_t j = 0; j < N; ++j) mass = mass + ecur[j];
+    if (rowmass) rowmass[i] = mass;
+    for (int64_t j = 0; j < N; ++j) {
+      enext[j] = ecur[j];
+      rnext[j] = R[i * N + j];
+      dnext[j] = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID);
+    }
+    enext[N] = 0.0; rnext[N] = -INFINITY; dnext[N] = 0.0;
+  }
+  free(R); free(enext); free(ecur); free(rnext); free(dnext);
+  return 0;
+}
+
+/* Batched Soft-DTW values and the weighted gradient of sum_i w_i SDTW(X, Y_i)
+ * (Eq. 7 with w_i = lambda_i / m_i supplied by the caller).  grad (M*d) and
+ * rowmass (M, may be NULL) receive sum_i w_i * (per-pair quantity), summed in
+ * ascending i.  values: n. */
+int wts_o_softdtw_batch(const double* X, int64_t M, const double* Yall, const int64_t* off, int n,
+                        int d, double gamma, const double* w, double* values, double* grad,
+                        double* rowmass) {
+  double* pg = grad ? (double*)malloc(sizeof(double) * (size_t)(n * M * d)) : NULL;
+  double* ph = rowmass ? (double*)malloc(sizeof(double) * (size_t)(n * M)) : NULL;
+  if ((grad && !pg) || (rowmass && !ph)) { free(pg); free(ph); return -1; }
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int p = 0; p < n; ++p) {
+    const double* Y = Yall + off[p] * d;
+    int64_t N = off[p + 1] - off[p];
+    if (grad || rowmass) {
+      double* g = pg ? pg + (int64_t)p * M * d : (double*)malloc(sizeof(double) * (size_t)(M * d));
+      err |= wts_o_softdtw_grad(X, M, Y, N, d, gamma, &values[p], g,
+                                ph ? ph + (int64_t)p * M : NULL, NULL);
+      if (!pg) free(g);
+    } else {
+      err |= wts_o_softdtw(X, M, Y, N, d, gamma, &values[p], NULL);
+    }
+  }
+  if (!err && grad) {
+    for (int64_t k = 0; k < M * d; ++k) {
+      double s = 0.0;
+      for (int p = 0; p < n; ++p) s = s + (w ? w[p] : 1.0) * pg[(int64_t)p * M * d + k];
+      grad[k] = s;
+    }
+  }
+  if (!err && rowmass) {
+    for (int64_t k = 0; k < M; ++k) {
+      double s = 0.0;
+      for (int p = 0; p < n; ++p) s = s + (w ? w[p] : 1.0) * ph[(int64_t)p * M + k];
+      rowmass[k] = s;
+    }
+  }
+  free(pg); free(ph);
+  return err ? -1 : 0;
+}
+
+/* Medoid initialisation: D[k][i] = DTW(Y_k, Y_i) for all k != i (D[k][k] = 0),
+ * total_k = sum_{i ascending} D[k][i], medoid = argmin_k total_k (lowest k on
+ * ties).  Dm: n*n (may be NULL). */
+int wts_o_medoid(const double* Yall, const int64_t* off, int n, int d, double* Dm, int* medoid) {
+  double* D = Dm ? Dm : (double*)malloc(sizeof(double) * (size_t)n * (size_t)n);
+  if (!D) return -1;
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int k = 0; k < n; ++k) {
+    for (int i = 0; i < n; ++i) {
+      if (i == k) { D[(int64_t)k * n + i] = 0.0; continue; }
+      int64_t len;
+      err |= wts_o_dtw(Yall + off[k] * d, off[k + 1] - off[k], Yall + off[i] * d,
+                       off[i + 1] - off[i], d, O_SQEUCLID, &D[(int64_t)k * n + i], &len, NULL,
+                       NULL);
+    }
+  }
+  int best = 0;
+  double bestv = INFINITY;
+  for (int k = 0; k < n; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s = s + D[(int64_t)k * n + i];
+    if (s < bestv) { bestv = s; best = k; }
+  }
+  *medoid = best;
+  if (!Dm) free(D);
+  return err ? -1 : 0;
+}
+
+/* Linear resampling of an N-sample series to L samples at the positions
+ * t_l = l (N-1) / (L-1): value = y[a] + f (y[a+1] - y[a]), a = floor(t_l),
+ * f = t_l - a (y[N-1] at the end; y[0] when L = 1). */
+void wts_o_resample(const double* Y, int64_t N, int d, int64_t L, double* out) {
+  for (int64_t l = 0; l < L; ++l) {
+    double pos = L == 1 ? 0.0 : ((double)l * (double)(N - 1)) / (double)(L - 1);
+    int64_t a = (int64_t)floor(pos);
+    for (int c = 0; c < d; ++c) {
+      double v;
+      if (a >= N - 1) {
+        v = Y[(N - 1) * d + c];
+      } else {
+        double f = pos - (double)a;
+        v = Y[a * d + c] + f * (Y[(a + 1) * d + c] - Y[a * d + c]);
+      }
+      out[l * d + c] = v;
+    }
+  }
+}
+
+/* Euclidean-mean initialisation (Table I "Euclidean barycenter"): pad every
+ * cycle with its last value to the longest length Nmax (as done for the
+ * paper's experiments), average per index in ascending cycle order, divide by
+ * n, then resample to L.  out: L*d. */
+int wts_o_euclid_mean(const double* Yall, const int64_t* off, int n, int d, int64_t L,
+                      double* out) {
+  int64_t Nmax = 0;
+  for (int p = 0; p < n; ++p)
+    if (off[p + 1] - off[p] > Nmax) Nmax = off[p + 1] - off[p];
+  double* m = (double*)malloc(sizeof(double) * (size_t)(Nmax * d));
+  if (!m) return -1;
+  for (int64_t t = 0; t < Nmax; ++t) {
+    for (int c = 0; c < d; ++c) {
+      double s = 0.0;
+      for (int p = 0; p < n; ++p) {
+        int64_t N = off[p + 1] - off[p];
+        int64_t tt = t < N ? t : N - 1;
+        s = s + Yall[(off[p] + tt) * d + c];
+      }
+      m[t * d + c] = s / (double)n;
+    }
+  }
+  wts_o_resample(m, Nmax, d, L, out);
+  free(m);
+  return 0;
+}
+
+/* Nearest-length initialisation: the cycle whose length is closest to L
+ * (lowest index on ties), resampled to L.  Returns the chosen index. */
+int wts_o_nearest_init(const double* Yall, const int64_t* off, int n, int d, int64_t L,
+                       double* out) {
+  int best = 0;
+  int64_t bestd = INT64_MAX;
+  for (int p = 0; p < n; ++p) {
+    int64_t N = off[p + 1] - off[p];
+    int64_t dd = N > L ? N - L : L - N;
+    if (dd < bestd) { bestd = dd; best = p; }
+  }
+  wts_o_resample(Yall + off[best] * d, off[best + 1] - off[best], d, L, out);
+  return best;
+}
+
+int wts_o_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

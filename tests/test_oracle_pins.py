@@ -1,0 +1,375 @@
+"""Pins for the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: brute force
+over all alignment paths (Def. 1, Eq. 1, Eq. 4), a hand-worked example,
+closed forms (Delannoy path counts, single-row series, constant series),
+invariants (DTW(x, x) = 0, symmetry, the Soft-DTW sandwich, E boundary
+values) and finite differences for the gradient of Eq. 6.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_2404_12134_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ----------------------------------------------------------------- cost (Def. 3)
+
+def test_cost_closed_form():
+    assert oracle.cost([1.0, 2.0, 3.0], [0.0, 0.0, 0.0]) == 14.0
+    assert oracle.cost([1.0, 2.0, 3.0], [0.0, 0.0, 0.0], oracle.EUCLID) == math.sqrt(14.0)
+    assert oracle.cost([0.5], [-0.25]) == 0.5625
+    assert oracle.cost([3.0, -1.0], [3.0, -1.0]) == 0.0
+
+
+def test_cost_single_rounding_order():
+    # e_0*e_0 then fma(e_1, e_1, s): the second square is not rounded on its own.
+    x, y = [0.1257302210933933, -0.1321048632913019], [0.0, 0.0]
+    e0, e1 = x[0], x[1]
+    expect = brute.fma(e1, e1, e0 * e0)
+    assert oracle.cost(x, y) == expect
+    assert expect != e0 * e0 + e1 * e1   # the rounding order is visible on this input
+
+
+# ----------------------------------------------------------- hand-worked example
+
+def test_hand_example_dtw_path_score_dba_soft():
+    g = json.load(open(os.path.join(GOLDEN, "dtw_hand_3x2.json")))
+    B, Y = np.array(g["B"]), np.array(g["Y"])
+    dist, plen, path, codes = oracle.dtw(B, Y, with_codes=True)
+    assert dist == g["dtw"]
+    assert plen == g["path_len"]
+    assert path.tolist() == g["path"]
+    score, _, _ = oracle.score_batch(B, [Y])
+    assert score[0] == g["d_score"]
+    Bn, K, _, _ = oracle.dba_iterate(B, [Y])
+    assert Bn.ravel().tolist() == g["dba_single_cycle"]["B_next"]
+    assert K.tolist() == g["dba_single_cycle"]["counts"]
+    costs = [c for _, c in g["all_paths_with_cost"]]
+    assert len(costs) == brute.delannoy(2, 1)
+    gam = g["soft_gamma"]
+    expect = -gam * math.log(sum(math.exp(-c / gam) for c in costs))
+    assert abs(oracle.softdtw(B, Y, gam) - expect) <= 1e-14 * abs(expect) + 1e-15
+    # E from the listed paths
+    w = np.array([math.exp(-c / gam) for c in costs])
+    w /= w.sum()
+    E = np.zeros((3, 2))
+    for (p, _), wk in zip(g["all_paths_with_cost"], w):
+        for i, j in p:
+            E[i, j] += wk
+    _, _, _, Eo = oracle.softdtw_grad(B, Y, gam, with_E=True)
+    np.testing.assert_allclose(Eo, E, rtol=1e-13, atol=1e-15)
+
+
+# ------------------------------------------------------- brute force: DTW (Eq. 1)
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_dtw_brute_random_reals(d):
+    r = rng(100 + d)
+    for M in range(1, 6):
+        for N in range(1, 6):
+            X, Y = r.standard_normal((M, d)), r.standard_normal((N, d))
+            dist, plen, path, _ = oracle.dtw(X, Y)
+            bd, bpath, _ = brute.dtw(X, Y)
+            assert dist == bd, (M, N)
+            assert path.tolist() == [list(c) for c in bpath], (M, N)
+            assert plen == len(bpath)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_dtw_brute_integer_ties(d):
+    # small integers: all sums exact, many tied optimal paths -> the tie-break decides
+    r = rng(200 + d)
+    n_tied = 0
+    for trial in range(60):
+        M, N = int(r.integers(1, 7)), int(r.integers(1, 7))
+        X, Y = synth.integer_pair(r, M, N, d, hi=2)
+        dist, plen, path, _ = oracle.dtw(X, Y)
+        bd, bpath, nopt = brute.dtw(X, Y)
+        n_tied += nopt > 1
+        assert dist == bd
+        assert path.tolist() == [list(c) for c in bpath], (trial, M, N)
+        assert plen == len(bpath)
+    assert n_tied > 20          # the test really exercises ties
+
+
+def test_dtw_l2_cost_brute():
+    r = rng(7)
+    X, Y = r.standard_normal((4, 3)), r.standard_normal((5, 3))
+    dist, _, path, _ = oracle.dtw(X, Y, kind=oracle.EUCLID)
+    bd, bpath, _ = brute.dtw(X, Y, kind="l2")
+    assert dist == bd and path.tolist() == [list(c) for c in bpath]
+
+
+# ------------------------------------------------------------- DTW invariants
+
+def test_dtw_self_is_zero_with_diagonal_path():
+    x = rng(1).standard_normal((37, 3))
+    dist, plen, path, _ = oracle.dtw(x, x)
+    assert dist == 0.0 and plen == 37
+    assert (path[:, 0] == path[:, 1]).all()
+
+
+def test_dtw_symmetry_bitwise():
+    r = rng(2)
+    for M, N, d in [(13, 29, 1), (40, 17, 3), (8, 8, 6)]:
+        X, Y = r.standard_normal((M, d)), r.standard_normal((N, d))
+        a, la, _, _ = oracle.dtw(X, Y, with_path=False)
+        b, lb, _, _ = oracle.dtw(Y, X, with_path=False)
+        assert a == b
+
+
+def test_dtw_single_row_closed_form():
+    r = rng(3)
+    b, Y = r.standard_normal((1, 2)), r.standard_normal((11, 2))
+    dist, plen, path, _ = oracle.dtw(b, Y)
+    s = 0.0
+    for j in range(11):               # one path: r(0, j) = delta + r(0, j-1)
+        s = brute.delta(b[0], Y[j]) + s
+    assert dist == s and plen == 11
+    assert path[:, 0].tolist() == [0] * 11
+
+
+def test_dtw_constant_series_closed_form():
+    # delta is the same on every cell, so the cheapest path is the shortest
+    # one: max(M, N) cells.
+    for M, N in [(5, 9), (9, 5), (7, 7)]:
+        dist, plen, _, _ = oracle.dtw(np.full(M, 1.5), np.full(N, 0.25))
+        assert plen == max(M, N)
+        assert dist == 1.5625 * max(M, N)
+
+
+def test_dtw_batch_matches_single():
+    r = rng(4)
+    B = r.standard_normal((30, 2))
+    cyc = [r.standard_normal((int(N), 2)) for N in r.integers(1, 50, 9)]
+    dist, plen = oracle.dtw_batch(B, cyc)
+    for k, Y in enumerate(cyc):
+        d1, l1, _, _ = oracle.dtw(B, Y, with_path=False)
+        assert dist[k] == d1 and plen[k] == l1
+
+
+# --------------------------------------------------------------------- score
+
+def test_score_is_dist_over_path_length():
+    r = rng(5)
+    B = r.standard_normal((20, 3))
+    cyc = [r.standard_normal((int(N), 3)) for N in (5, 20, 33)]
+    score, dist, plen = oracle.score_batch(B, cyc)
+    for k, Y in enumerate(cyc):
+        bd, plen1, _, _ = oracle.dtw(B, Y, with_path=False)
+        assert score[k] == bd / plen1
+    # a cycle that equals B scores 0
+    s0, _, _ = oracle.score_batch(B, [B])
+    assert s0[0] == 0.0
+
+
+# ----------------------------------------------------------------------- DBA
+
+def test_dba_matches_brute_force_paths():
+    r = rng(6)
+    for trial in range(25):
+        L, d, n = int(r.integers(1, 6)), int(r.integers(1, 3)), int(r.integers(1, 4))
+        B = r.standard_normal((L, d))
+        cyc = [r.standard_normal((int(r.integers(1, 6)), d)) for _ in range(n)]
+        w = r.uniform(0.5, 2.0, n) if trial % 2 else None
+        Bo, K, _, _ = oracle.dba_iterate(B, cyc, w)
+        Bb, Kb = brute.dba_iterate(B, cyc, w)
+        assert (K == Kb).all()
+        assert (Bo == Bb).all(), trial
+
+
+def test_dba_fixed_point_when_all_cycles_equal():
+    x = synth.dyadic(rng(8), (50, 3))
+    Bo, K, dist, plen = oracle.dba_iterate(x, [x, x, x, x])
+    assert (Bo == x).all()
+    assert (K == 4).all() and (dist == 0).all() and (plen == 50).all()
+
+
+def test_dba_counts_and_objective_monotone():
+    w = synth.make(1, n=6, len_range=(40, 60))
+    B = w.cycles[0].astype(np.float64)
+    prev = math.inf
+    for it in range(6):
+        Bn, K, dist, plen = oracle.dba_iterate(B, w.cycles)
+        obj = float(dist.sum())
+        assert obj <= prev * (1 + 1e-12)
+        assert K.sum() == plen.sum() and (K >= len(w.cycles)).all()
+        prev, B = obj, Bn
+
+
+def test_dba_row_mean_closed_form():
+    # one cycle equal to B with every sample repeated twice: each row l is
+    # aligned to its two copies, so the update returns B itself.
+    x = synth.dyadic(rng(9), (20, 2))
+    y = np.repeat(x, 2, axis=0)
+    Bo, K, _, _ = oracle.dba_iterate(x, [y])
+    assert (Bo == x).all() and (K == 2).all()
+
+
+# ---------------------------------------------------------- Soft-DTW (Eq. 3-5)
+
+@pytest.mark.parametrize("gamma", [0.1, 1.0, 10.0])
+def test_softdtw_brute(gamma):
+    r = rng(10)
+    for M in range(1, 6):
+        for N in range(1, 6):
+            X, Y = r.standard_normal((M, 2)), r.standard_normal((N, 2))
+            v = oracle.softdtw(X, Y, gamma)
+            b = brute.softdtw(X, Y, gamma)
+            assert abs(v - b) <= 1e-12 * max(1.0, abs(b)), (M, N)
+
+
+def test_softdtw_sandwich_and_limit():
+    r = rng(11)
+    X, Y = r.standard_normal((30, 3)), r.standard_normal((24, 3))
+    dtw, _, _, _ = oracle.dtw(X, Y, with_path=False)
+    npaths = brute.delannoy(29, 23)
+    for gamma in [1.0, 0.1, 1e-2, 1e-3]:
+        s = oracle.softdtw(X, Y, gamma)
+        assert dtw - gamma * math.log(npaths) - 1e-9 <= s <= dtw + 1e-9
+    assert abs(oracle.softdtw(X, Y, 1e-4) - dtw) < 1e-4 * math.log(npaths)
+
+
+def test_softdtw_single_row_exact():
+    # min^gamma(inf, inf, a) = a exactly: the single path's cost
+    r = rng(12)
+    b, Y = r.standard_normal((1, 2)), r.standard_normal((9, 2))
+    dist, _, _, _ = oracle.dtw(b, Y, with_path=False)
+    assert oracle.softdtw(b, Y, 0.3) == dist
+
+
+def test_softdtw_zero_cost_is_minus_gamma_log_delannoy():
+    for M, N in [(1, 1), (3, 7), (12, 9)]:
+        v = oracle.softdtw(np.zeros(M), np.zeros(N), 0.5)
+        expect = -0.5 * math.log(brute.delannoy(M - 1, N - 1))
+        assert abs(v - expect) <= 1e-13 * max(1, abs(expect))
+
+
+def test_softdtw_symmetry():
+    r = rng(13)
+    X, Y = r.standard_normal((17, 2)), r.standard_normal((23, 2))
+    a, b = oracle.softdtw(X, Y, 0.7), oracle.softdtw(Y, X, 0.7)
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+# -------------------------------------------------------------- E and Eq. 6
+
+@pytest.mark.parametrize("gamma", [0.2, 1.0])
+def test_E_brute_gibbs(gamma):
+    r = rng(14)
+    for M, N in [(1, 4), (3, 3), (4, 5), (5, 3)]:
+        X, Y = r.standard_normal((M, 2)), r.standard_normal((N, 2))
+        _, _, _, E = oracle.softdtw_grad(X, Y, gamma, with_E=True)
+        np.testing.assert_allclose(E, brute.gibbs_E(X, Y, gamma), rtol=1e-10, atol=1e-13)
+
+
+def test_E_zero_cost_delannoy_closed_form():
+    M, N = 9, 13
+    _, _, _, E = oracle.softdtw_grad(np.zeros(M), np.zeros(N), 0.8, with_E=True)
+    tot = brute.delannoy(M - 1, N - 1)
+    for i in range(M):
+        for j in range(N):
+            frac = brute.delannoy(i, j) * brute.delannoy(M - 1 - i, N - 1 - j) / tot
+            assert abs(E[i, j] - frac) <= 1e-12
+
+
+def test_E_invariants():
+    r = rng(15)
+    X, Y = r.standard_normal((25, 3)), r.standard_normal((31, 3))
+    _, _, h, E = oracle.softdtw_grad(X, Y, 0.5, with_E=True)
+    assert abs(E[0, 0] - 1) < 1e-12 and abs(E[-1, -1] - 1) < 1e-12
+    assert (E.sum(axis=1) >= 1 - 1e-12).all()
+    np.testing.assert_allclose(h, E.sum(axis=1), rtol=1e-13)
+    for k in range(25 + 31 - 1):
+        s = sum(E[i, k - i] for i in range(max(0, k - 30), min(25, k + 1)))
+        assert s <= 1 + 1e-12
+
+
+def test_E_tends_to_hard_alignment():
+    r = rng(16)
+    X, Y = r.standard_normal((12, 2)), r.standard_normal((15, 2))
+    _, _, path, _ = oracle.dtw(X, Y)
+    A = np.zeros((12, 15))
+    A[path[:, 0], path[:, 1]] = 1
+    _, _, _, E = oracle.softdtw_grad(X, Y, 1e-3, with_E=True)
+    assert np.abs(E - A).max() < 1e-6
+
+
+@pytest.mark.parametrize("gamma", [0.1, 1.0])
+def test_gradient_finite_differences(gamma):
+    r = rng(17)
+    X, Y = r.standard_normal((14, 3)), r.standard_normal((19, 3))
+    _, g, _, _ = oracle.softdtw_grad(X, Y, gamma)
+    h = 1e-6
+    fd = np.zeros_like(X)
+    for i in range(X.shape[0]):
+        for c in range(X.shape[1]):
+            Xp, Xm = X.copy(), X.copy()
+            Xp[i, c] += h
+            Xm[i, c] -= h
+            fd[i, c] = (oracle.softdtw(Xp, Y, gamma) - oracle.softdtw(Xm, Y, gamma)) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-6 * np.abs(g).max())
+
+
+def test_softdtw_batch_weighted_gradient():
+    r = rng(18)
+    X = r.standard_normal((10, 2))
+    cyc = [r.standard_normal((int(N), 2)) for N in (7, 12, 9)]
+    w = np.array([0.5, 2.0, 1.25])
+    vals, g, h = oracle.softdtw_batch(X, cyc, 0.4, w)
+    gs, hs = np.zeros_like(X), np.zeros(10)
+    for k, Y in enumerate(cyc):
+        v, gk, hk, _ = oracle.softdtw_grad(X, Y, 0.4)
+        assert vals[k] == v
+        gs += w[k] * gk
+        hs += w[k] * hk
+    np.testing.assert_allclose(g, gs, rtol=1e-13)
+    np.testing.assert_allclose(h, hs, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------- init
+
+def test_medoid_constant_series_closed_form():
+    # equal-length constant series: DTW(c_a, c_b) = (c_a - c_b)^2 * N, so the
+    # medoid is the level closest to the mean of the levels.
+    levels = [0.0, 3.0, 1.0, 0.75, 2.5]
+    k, D = oracle.medoid([np.full(8, c) for c in levels])
+    totals = [sum((a - b) ** 2 for b in levels) for a in levels]
+    assert k == int(np.argmin(totals)) == 2
+    for a in range(5):
+        for b in range(5):
+            assert D[a, b] == (levels[a] - levels[b]) ** 2 * 8
+
+
+def test_resample_closed_forms():
+    t = np.arange(10, dtype=np.float64)
+    y = np.stack([2 * t + 1, -t], axis=1)
+    np.testing.assert_array_equal(oracle.resample(y, 10), y)          # identity
+    out = oracle.resample(y, 19)                                       # midpoints of a line
+    np.testing.assert_allclose(out[:, 0], 2 * np.arange(19) * 0.5 + 1, rtol=0, atol=1e-13)
+    assert (oracle.resample(y, 1) == y[:1]).all()
+
+
+def test_euclid_mean_and_nearest_init():
+    r = rng(19)
+    cyc = [r.standard_normal((12, 2)) for _ in range(4)]
+    m = oracle.euclid_mean(cyc, 12)
+    np.testing.assert_allclose(m, np.mean(cyc, axis=0), rtol=1e-14, atol=1e-15)
+    # last-value padding
+    short = [np.array([[1.0], [2.0], [3.0]]), np.full((5, 1), 5.0)]   # [1,2,3] -> [1,2,3,3,3]
+    np.testing.assert_array_equal(oracle.euclid_mean(short, 5).ravel(), [3, 3.5, 4, 4, 4])
+    k, out = oracle.nearest_init([np.zeros((3, 1)), np.ones((9, 1)), np.ones((11, 1))], 10)
+    assert k == 1 and out.shape == (10, 1)
