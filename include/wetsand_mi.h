@@ -1,0 +1,186 @@
+/*
+ * wetsand_mi.h -- C ABI of the WETSAND hot path on AMD MI355X (gfx950).
+ *
+ * WETSAND (warped time-series anomaly detection) builds a prototype cycle
+ * (a barycenter B) from many unevenly long cycles and scores every cycle by
+ * its DTW distance to B.  This library runs the dynamic programs behind that
+ * on one GPU:
+ *
+ *   wts_dtw_align        DTW value, path length and optional warping path of
+ *                        every (B, C_k) pair                 (Sec. III-B, Eq. 1)
+ *   wts_dba_iterate      one DTW-barycenter-averaging update of B     (Sec. II,
+ *                        Sec. V-B: the DBA barycenter the paper compares with)
+ *   wts_softdtw_forward  Soft-DTW values of every (B, C_k) pair  (Eq. 3-5)
+ *   wts_softdtw_backward gradient of sum_k w_k Soft-DTW(B, C_k) w.r.t. B
+ *                        through the E matrix                  (Eq. 6, Eq. 7)
+ *   wts_anomaly_score    d_score = DTW(B, C_k) / |pi_k|        (Sec. III-D, Eq. 8)
+ *   wts_medoid           all-pairs DTW and the medoid cycle (barycenter init)
+ *   wts_init_barycenter  Euclidean-mean / nearest-length / copy initialisation
+ *
+ * Conventions
+ *  - Every pointer argument is DEVICE memory unless its name ends in _host.
+ *    The caller owns every buffer; compute calls never allocate and never
+ *    synchronise: they enqueue work on `stream` (a hipStream_t, NULL = the
+ *    null stream) and return.
+ *  - Series are time-major: sample t of a d-channel series occupies d
+ *    consecutive values.  The cycles of a batch are packed back to back in
+ *    one buffer; offsets_host[k] .. offsets_host[k+1] is cycle k.  Cycle
+ *    values are float32 (WTS_F32) or float64 (WTS_F64) as fixed at plan time
+ *    and are widened exactly to float64 on load.  Barycenters, distances,
+ *    scores and gradients are always float64.
+ *  - Cost: delta(b, y) = sum_c (b_c - y_c)^2 computed as e_0*e_0 followed by
+ *    fma(e_c, e_c, s) (squared Euclidean, Def. 3); WTS_COST_EUCLID takes its
+ *    correctly rounded square root (DTW values and scores only).
+ *  - Optimal path: the backtrack from (L, N) takes, at every cell, the first
+ *    predecessor in the order diagonal, up (i-1, j), left (i, j-1) whose
+ *    cumulative cost equals the minimum.  Distances, paths, path lengths and
+ *    alignment counts are bitwise identical to a float64 CPU evaluation of
+ *    the same definitions.
+ *  - Inputs must be finite (the paper drops NaN samples before any DTW,
+ *    Sec. III-A); non-finite inputs give unspecified results.
+ *  - Errors: a non-zero wts_status is returned before anything is enqueued;
+ *    wts_last_error() gives a message (thread-local).  WTS_E_HIP reports a
+ *    failed HIP call (for instance a launch failure).
+ */
+#ifndef WETSAND_MI_H
+#define WETSAND_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wts_plan wts_plan;
+
+typedef enum {
+  WTS_OK = 0,
+  WTS_E_ARG = -1,          /* null pointer where one is required, bad enum, gamma <= 0 ... */
+  WTS_E_SHAPE = -2,        /* n, d, L or a cycle length out of range */
+  WTS_E_DTYPE = -3,        /* dtype is not WTS_F32 / WTS_F64 */
+  WTS_E_WORKSPACE = -4,    /* ws_bytes (or ckpt_bytes) smaller than required */
+  WTS_E_HIP = -6,          /* a HIP runtime call failed */
+  WTS_E_UNSUPPORTED = -8   /* valid request this build does not implement */
+} wts_status;
+
+enum { WTS_F32 = 0, WTS_F64 = 1 };
+enum { WTS_COST_SQEUCLID = 0, WTS_COST_EUCLID = 1 };
+
+/* Operation selectors for wts_workspace_bytes. */
+enum {
+  WTS_OP_ALIGN = 0,        /* wts_dtw_align without paths           */
+  WTS_OP_ALIGN_PATHS = 1,  /* wts_dtw_align with paths              */
+  WTS_OP_DBA = 2,          /* wts_dba_iterate                       */
+  WTS_OP_SCORE = 3,        /* wts_anomaly_score                     */
+  WTS_OP_SOFT_FWD = 4,     /* checkpoint buffer of the Soft-DTW pair */
+  WTS_OP_SOFT_BWD = 5,     /* workspace of wts_softdtw_backward      */
+  WTS_OP_MEDOID = 6        /* wts_medoid                            */
+};
+
+enum { WTS_INIT_EUCLID_MEAN = 0, WTS_INIT_NEAREST = 1, WTS_INIT_COPY = 2 };
+
+typedef struct {
+  int32_t cost;       /* WTS_COST_* for wts_dtw_align / wts_anomaly_score; DBA, Soft-DTW and
+                         the medoid always use the squared cost                              */
+  int32_t rho;        /* barycenter rows per lane in the wavefront sweep (0 = tuned default;
+                         1, 2, 4 or 8)                                                        */
+  int32_t grid;       /* workgroups of the persistent sweep (0 = tuned default)              */
+  int32_t reserved;   /* must be 0                                                           */
+} wts_opts;
+
+/* Create a plan for a batch of n cycles of d channels (1 <= d <= 8) stored as
+ * `dtype`, with cycle k spanning offsets_host[k] .. offsets_host[k+1]
+ * (host array of n+1 non-decreasing int64, offsets_host[0] == 0, every
+ * cycle at least one sample long), against a barycenter of L rows.
+ * L = 0 makes a plan for wts_medoid only (all n(n-1)/2 cycle pairs); the
+ * barycenter operations need L > 0.
+ * The plan binds the lengths, L and the device; cycle and barycenter VALUES
+ * may change between calls.  It allocates a small device table (hipMalloc)
+ * here, never in the compute calls.  opts may be NULL (defaults). */
+wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int32_t dtype,
+                           const int64_t* offsets_host, int64_t L, const wts_opts* opts);
+void wts_plan_destroy(wts_plan* plan);
+
+/* Bytes of workspace (device memory, any content, 256-byte aligned) an
+ * operation needs; 0 for an operation the plan cannot run. */
+size_t wts_workspace_bytes(const wts_plan* plan, int op);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* wts_last_error(void);
+
+/* Eq. 1 (DTW) and the optimal path of every (B, C_k).
+ *   bary      [L][d] float64
+ *   cycles    packed cycle values, plan dtype
+ *   dist      [n] float64 out: DTW(B, C_k) = r_{L, N_k}
+ *   path_len  [n] int64 out: |pi_k|, number of index pairs on the path
+ *   paths     NULL, or int32 [n (L-1) + offsets_host[n]][2] out: the (i, j)
+ *             pairs of pi_k (0-based, forward order from (0, 0)) in rows
+ *             k (L-1) + offsets_host[k] .. + path_len[k] - 1 (each cycle owns
+ *             L + N_k - 1 rows, the longest possible path; rows past
+ *             path_len[k] are left untouched).  Squared cost only.
+ *   ws        workspace of wts_workspace_bytes(WTS_OP_ALIGN[_PATHS]) bytes */
+wts_status wts_dtw_align(const wts_plan* plan, const double* bary, const void* cycles,
+                         double* dist, int64_t* path_len, int32_t* paths, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* One DBA update.  With pi_k the optimal path of (B, C_k):
+ *   S_l = sum_{k ascending} w_k * sum_{j: (l, j) in pi_k, descending j} y_kj
+ *   C_l = sum_{k ascending} w_k * |{j: (l, j) in pi_k}|
+ *   bary_out_l = S_l / C_l,   counts_l = sum_k |{j: (l, j) in pi_k}|
+ * (sums start from +0.0, left to right).  weights [n] float64 or NULL (all 1).
+ * bary_out [L][d] float64, counts [L] int64, dist [n] float64 or NULL
+ * (DTW(B, C_k) of the input barycenter).  bary_out must not alias bary_in. */
+wts_status wts_dba_iterate(const wts_plan* plan, const double* bary_in, const void* cycles,
+                           const double* weights, double* bary_out, int64_t* counts,
+                           double* dist, void* ws, size_t ws_bytes, void* stream);
+
+/* Eq. 8: score_k = DTW(B, C_k) / |pi_k| (plan cost).  score [n] float64;
+ * dist [n] float64 and path_len [n] int64 may be NULL. */
+wts_status wts_anomaly_score(const wts_plan* plan, const double* bary, const void* cycles,
+                             double* score, double* dist, int64_t* path_len, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* Eq. 3-5 with gamma > 0: value_k = Soft-DTW^gamma(B, C_k) (squared cost).
+ * ckpt: checkpoint buffer of wts_workspace_bytes(WTS_OP_SOFT_FWD) bytes that
+ * wts_softdtw_backward consumes (the forward must precede the backward with
+ * the same bary, cycles and gamma). */
+wts_status wts_softdtw_forward(const wts_plan* plan, const double* bary, const void* cycles,
+                               double gamma, double* value, void* ckpt, size_t ckpt_bytes,
+                               void* stream);
+
+/* Eq. 6-7: grad_bary = sum_{k ascending} grad_value_k * d Soft-DTW^gamma(B, C_k) / d B,
+ * with E from the chain rule on Eq. 5 (E(L, N) = 1 and zero outside the grid).
+ * grad_value [n] float64 (the upstream gradient, e.g. lambda_k / m_k for Eq. 7);
+ * grad_bary [L][d] float64 out; row_mass [L] float64 out or NULL:
+ * row_mass_l = sum_k grad_value_k * sum_j E^k_{lj}. */
+wts_status wts_softdtw_backward(const wts_plan* plan, const double* bary, const void* cycles,
+                                double gamma, const void* ckpt, size_t ckpt_bytes,
+                                const double* grad_value, double* grad_bary, double* row_mass,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* Medoid initialisation: D[k][i] = DTW(C_k, C_i) (squared cost, D[k][k] = 0),
+ * total_k = sum_{i ascending} D[k][i], medoid = argmin_k total_k (lowest k on
+ * ties).  dist_matrix [n][n] float64 or NULL, totals [n] float64 or NULL,
+ * medoid [1] int32 out. */
+wts_status wts_medoid(const wts_plan* plan, const void* cycles, double* dist_matrix,
+                      double* totals, int32_t* medoid, void* ws, size_t ws_bytes, void* stream);
+
+/* Barycenter initialisation into bary_out [L][d] float64 (plan L > 0):
+ *   WTS_INIT_EUCLID_MEAN: pad every cycle with its last sample to the longest
+ *     length Nmax, average per index (ascending k, then / n), resample to L;
+ *   WTS_INIT_NEAREST: the cycle whose length is closest to L (lowest k on
+ *     ties), resampled to L;
+ *   WTS_INIT_COPY: cycle `index` resampled to L (a copy when its length is L).
+ * Resampling: t_l = l (N-1) / (L-1), value = y[a] + f (y[a+1] - y[a]) with
+ * a = floor(t_l), f = t_l - a.  chosen_host: HOST int32 out (the cycle used,
+ * -1 for the mean) or NULL. */
+wts_status wts_init_barycenter(const wts_plan* plan, const void* cycles, int32_t kind,
+                               int32_t index, double* bary_out, int32_t* chosen_host,
+                               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WETSAND_MI_H */

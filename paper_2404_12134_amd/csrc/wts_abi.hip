@@ -1,0 +1,518 @@
+// wts_abi.hip -- the C ABI of include/wetsand_mi.h: plans, argument checks,
+// workspace layout and the launch sequences of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/wetsand_mi.h"
+#include "wts_kernels.h"
+
+using wts::PairDesc;
+
+namespace {
+
+thread_local std::string g_err;
+
+wts_status fail(wts_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+wts_status fail(wts_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(WTS_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));              \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Pairs of one kind (barycenter vs cycles, or cycle vs cycle) with their
+// sweep items and the sizes of the buffers the sweep needs.
+struct PairSet {
+  std::vector<PairDesc> pairs;
+  std::vector<int2> items;
+  PairDesc* d_pairs = nullptr;
+  int2* d_items = nullptr;
+  int n_pairs = 0, n_items = 0, n_flags = 0;
+  int64_t code_words = 0, bnd_elems = 0, aux_strip_elems = 0;
+  int64_t max_rows = 0;
+};
+
+struct Job {
+  int64_t x_off, y_off;
+  int32_t M, N, out;
+};
+
+void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
+  const int H = wts::kWave * rho;
+  std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) {
+    return (int64_t)a.M * a.N > (int64_t)b.M * b.N;
+  });
+  ps.pairs.clear();
+  ps.items.clear();
+  int64_t code = 0, bnd = 0, aux = 0;
+  int flags = 0;
+  for (size_t p = 0; p < jobs.size(); ++p) {
+    const Job& jb = jobs[p];
+    PairDesc d{};
+    d.x_off = jb.x_off;
+    d.y_off = jb.y_off;
+    d.M = jb.M;
+    d.N = jb.N;
+    d.S = (jb.M + H - 1) / H;
+    d.out = jb.out;
+    d.WT = (jb.N + wts::kWave - 1 + 15) / 16;
+    d.code_base = code;
+    d.bnd_base = bnd;
+    d.aux_base = aux;
+    d.flag_base = flags;
+    d.item_base = (int)ps.items.size();
+    code += (int64_t)d.S * d.WT * rho * wts::kWave;
+    bnd += jb.N;
+    aux += (int64_t)d.S * jb.N;
+    flags += d.S;
+    for (int s = 0; s < d.S; ++s) ps.items.push_back(make_int2((int)p, s));
+    ps.pairs.push_back(d);
+    ps.max_rows = std::max<int64_t>(ps.max_rows, jb.M);
+  }
+  ps.n_pairs = (int)ps.pairs.size();
+  ps.n_items = (int)ps.items.size();
+  ps.n_flags = flags;
+  ps.code_words = code;
+  ps.bnd_elems = bnd;
+  ps.aux_strip_elems = aux;
+}
+
+// Workspace: every region 256-byte aligned, in this order.
+struct Layout {
+  size_t queue = 0, progress = 0, bnd_r = 0, bnd_aux = 0, codes = 0, out_dist = 0, out_aux = 0;
+  size_t seg = 0, seg_len = 0, seg_off = 0, psum = 0, pcnt = 0, dm = 0, totals = 0;
+  size_t total = 0;
+};
+
+}  // namespace
+
+struct wts_plan {
+  int device = 0, n = 0, d = 0, dtype = 0, cus = 256;
+  int64_t L = 0;
+  wts_opts opts{};
+  int rho = 4;
+  std::vector<int64_t> off;
+  int64_t* d_off = nullptr;
+  int64_t* d_path_base = nullptr;
+  int2* d_med_ab = nullptr;
+  PairSet bary, med;
+  int64_t nmax = 0;
+};
+
+namespace {
+
+Layout layout(const wts_plan* p, int op) {
+  Layout l;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
+  const PairSet& ps = op == WTS_OP_MEDOID ? p->med : p->bary;
+  const bool paths = op == WTS_OP_ALIGN_PATHS || op == WTS_OP_DBA;
+  l.queue = take(2 * sizeof(int));   // [0] item counter, [1] status word
+  l.progress = take(sizeof(int) * (size_t)ps.n_flags);
+  l.bnd_r = take(sizeof(double) * (size_t)ps.bnd_elems);
+  l.bnd_aux = take(sizeof(int) * (size_t)(paths ? ps.aux_strip_elems : ps.bnd_elems));
+  if (paths) l.codes = take(sizeof(uint32_t) * (size_t)ps.code_words);
+  l.out_dist = take(sizeof(double) * (size_t)ps.n_pairs);
+  l.out_aux = take(sizeof(int) * (size_t)ps.n_pairs);
+  if (paths) {
+    l.seg = take(sizeof(int2) * (size_t)ps.n_items);
+    l.seg_len = take(sizeof(int) * (size_t)ps.n_items);
+    l.seg_off = take(sizeof(int) * (size_t)ps.n_items);
+  }
+  if (op == WTS_OP_DBA) {
+    l.psum = take(sizeof(double) * (size_t)p->n * (size_t)p->L * (size_t)p->d);
+    l.pcnt = take(sizeof(int) * (size_t)p->n * (size_t)p->L);
+  }
+  if (op == WTS_OP_MEDOID) {
+    l.dm = take(sizeof(double) * (size_t)p->n * (size_t)p->n);
+    l.totals = take(sizeof(double) * (size_t)p->n);
+  }
+  l.total = o;
+  return l;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+int default_grid(const wts_plan* p, const PairSet& ps) {
+  const int g = p->opts.grid > 0 ? p->opts.grid : p->cus * 8;
+  return std::max(1, std::min(g, ps.n_items));
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+wts_status check_ws(const wts_plan* p, int op, void* ws, size_t ws_bytes) {
+  const size_t need = layout(p, op).total;
+  if (ws == nullptr) return fail(WTS_E_ARG, "workspace pointer is null");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
+    return fail(WTS_E_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(WTS_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  return WTS_OK;
+}
+
+wts_status check_bary_plan(const wts_plan* p) {
+  if (!p) return fail(WTS_E_ARG, "plan is null");
+  if (p->L <= 0) return fail(WTS_E_ARG, "plan was created with L = 0 (medoid/init only)");
+  return WTS_OK;
+}
+
+// Zero the queue and progress counters, then run the persistent sweep.
+wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, bool x_is_cycle,
+                     const void* x, const void* y, void* ws, const Layout& l, double* out_dist,
+                     hipStream_t st) {
+  HIP_TRY(wts::launch_zero(at<int>(ws, l.queue), 2, st));
+  HIP_TRY(wts::launch_zero(at<int>(ws, l.progress), ps.n_flags, st));
+  wts::FwdArgs a{};
+  a.pairs = ps.d_pairs;
+  a.items = ps.d_items;
+  a.n_items = ps.n_items;
+  a.queue = at<int>(ws, l.queue);
+  a.status = at<int>(ws, l.queue) + 1;
+  a.progress = at<int>(ws, l.progress);
+  a.x = x;
+  a.y = y;
+  a.bnd_r = at<double>(ws, l.bnd_r);
+  a.bnd_aux = at<int>(ws, l.bnd_aux);
+  a.codes = mode == wts::MODE_PATH ? at<uint32_t>(ws, l.codes) : nullptr;
+  a.out_dist = out_dist ? out_dist : at<double>(ws, l.out_dist);
+  a.out_aux = at<int>(ws, l.out_aux);
+  a.aux_per_strip = mode == wts::MODE_PATH ? 1 : 0;
+  a.cost_kind = euc ? 1 : 0;
+  HIP_TRY(wts::launch_fwd(p->d, p->rho, mode, euc, x_is_cycle, p->dtype, a,
+                          default_grid(p, ps), st));
+  return WTS_OK;
+}
+
+// PATH sweep, strip chain and the first walk (row runs, segment lengths,
+// DBA partial sums when psum != nullptr).
+wts_status run_paths(const wts_plan* p, const double* bary, const void* cycles, void* ws,
+                     const Layout& l, double* out_dist, double* psum, int* pcnt, hipStream_t st) {
+  const PairSet& ps = p->bary;
+  wts_status rc = run_sweep(p, ps, wts::MODE_PATH, false, false, bary, cycles, ws, l, out_dist, st);
+  if (rc != WTS_OK) return rc;
+  HIP_TRY(wts::launch_chain(ps.d_pairs, ps.n_pairs, at<int>(ws, l.bnd_aux),
+                            at<int>(ws, l.out_aux), at<int2>(ws, l.seg),
+                            at<int>(ws, l.queue) + 1, st));
+  wts::WalkArgs w{};
+  w.pairs = ps.d_pairs;
+  w.items = ps.d_items;
+  w.seg = at<int2>(ws, l.seg);
+  w.codes = at<uint32_t>(ws, l.codes);
+  w.y = cycles;
+  w.psum = psum;
+  w.pcnt = pcnt;
+  w.L = p->L;
+  w.seg_len = at<int>(ws, l.seg_len);
+  w.status = at<int>(ws, l.queue) + 1;
+  HIP_TRY(wts::launch_walk(p->d, p->rho, p->dtype, false, w, ps.n_items, st));
+  return WTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wts_last_error(void) { return g_err.c_str(); }
+
+wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int32_t dtype,
+                           const int64_t* offsets_host, int64_t L, const wts_opts* opts) {
+  if (!out) return fail(WTS_E_ARG, "out is null");
+  *out = nullptr;
+  if (!offsets_host) return fail(WTS_E_ARG, "offsets_host is null");
+  if (n < 1) return fail(WTS_E_SHAPE, "n = %d: need at least one cycle", n);
+  if (d < 1 || d > 8) return fail(d < 1 ? WTS_E_SHAPE : WTS_E_UNSUPPORTED, "d = %d: 1..8 supported", d);
+  if (dtype != WTS_F32 && dtype != WTS_F64) return fail(WTS_E_DTYPE, "dtype %d", dtype);
+  if (L < 0 || L > (1 << 24)) return fail(WTS_E_SHAPE, "L = %lld out of range", (long long)L);
+  if (offsets_host[0] != 0) return fail(WTS_E_SHAPE, "offsets_host[0] must be 0");
+  for (int k = 0; k < n; ++k) {
+    const int64_t len = offsets_host[k + 1] - offsets_host[k];
+    if (len < 1) return fail(WTS_E_SHAPE, "cycle %d has length %lld", k, (long long)len);
+    if (len > (1 << 24)) return fail(WTS_E_SHAPE, "cycle %d too long", k);
+  }
+  wts_opts o{};
+  if (opts) o = *opts;
+  if (o.cost != WTS_COST_SQEUCLID && o.cost != WTS_COST_EUCLID) return fail(WTS_E_ARG, "opts.cost");
+  if (o.rho != 0 && o.rho != 2 && o.rho != 4)
+    return fail(WTS_E_UNSUPPORTED, "opts.rho = %d: 2 or 4 supported", o.rho);
+  if (o.grid < 0 || o.reserved != 0) return fail(WTS_E_ARG, "opts.grid / opts.reserved");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(WTS_E_ARG, "device %d of %d", device, ndev);
+
+  wts_plan* p = new wts_plan();
+  p->device = device;
+  p->n = n;
+  p->d = d;
+  p->dtype = dtype;
+  p->L = L;
+  p->opts = o;
+  p->rho = o.rho ? o.rho : 4;
+  p->off.assign(offsets_host, offsets_host + n + 1);
+  for (int k = 0; k < n; ++k) p->nmax = std::max(p->nmax, p->off[k + 1] - p->off[k]);
+
+  DeviceGuard g(device);
+  auto cleanup_fail = [&](hipError_t e, const char* what) {
+    wts_plan_destroy(p);
+    return fail(WTS_E_HIP, "%s failed: %s", what, hipGetErrorString(e));
+  };
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    p->cus = cus;
+
+  std::vector<Job> jobs;
+  if (L > 0) {
+    for (int k = 0; k < n; ++k)
+      jobs.push_back(Job{0, p->off[k], (int32_t)L, (int32_t)(p->off[k + 1] - p->off[k]), k});
+    build_set(p->bary, jobs, p->rho);
+    std::vector<int64_t> base(n);
+    for (int k = 0; k < n; ++k) base[k] = (int64_t)k * (L - 1) + p->off[k];
+    hipError_t e;
+    if ((e = hipMalloc(&p->d_path_base, sizeof(int64_t) * n)) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+    if ((e = hipMemcpy(p->d_path_base, base.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup_fail(e, "hipMemcpy");
+  } else {
+    // all pairs a < b, the shorter cycle on the rows (DTW is symmetric)
+    std::vector<int2> ab;
+    for (int a = 0; a < n; ++a)
+      for (int b = a + 1; b < n; ++b) {
+        const int64_t la = p->off[a + 1] - p->off[a], lb = p->off[b + 1] - p->off[b];
+        const int slot = (int)ab.size();
+        ab.push_back(make_int2(a, b));
+        if (la <= lb) jobs.push_back(Job{p->off[a], p->off[b], (int32_t)la, (int32_t)lb, slot});
+        else jobs.push_back(Job{p->off[b], p->off[a], (int32_t)lb, (int32_t)la, slot});
+      }
+    build_set(p->med, jobs, p->rho);
+    if (!ab.empty()) {
+      hipError_t e;
+      if ((e = hipMalloc(&p->d_med_ab, sizeof(int2) * ab.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+      if ((e = hipMemcpy(p->d_med_ab, ab.data(), sizeof(int2) * ab.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return cleanup_fail(e, "hipMemcpy");
+    }
+  }
+  for (PairSet* ps : {&p->bary, &p->med}) {
+    if (ps->pairs.empty()) continue;
+    hipError_t e;
+    if ((e = hipMalloc(&ps->d_pairs, sizeof(PairDesc) * ps->pairs.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&ps->d_items, sizeof(int2) * ps->items.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+    if ((e = hipMemcpy(ps->d_pairs, ps->pairs.data(), sizeof(PairDesc) * ps->pairs.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup_fail(e, "hipMemcpy");
+    if ((e = hipMemcpy(ps->d_items, ps->items.data(), sizeof(int2) * ps->items.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup_fail(e, "hipMemcpy");
+  }
+  hipError_t e;
+  if ((e = hipMalloc(&p->d_off, sizeof(int64_t) * (n + 1))) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+  if ((e = hipMemcpy(p->d_off, p->off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup_fail(e, "hipMemcpy");
+  *out = p;
+  return WTS_OK;
+}
+
+void wts_plan_destroy(wts_plan* p) {
+  if (!p) return;
+  DeviceGuard g(p->device);
+  for (PairSet* ps : {&p->bary, &p->med}) {
+    if (ps->d_pairs) (void)hipFree(ps->d_pairs);
+    if (ps->d_items) (void)hipFree(ps->d_items);
+  }
+  if (p->d_off) (void)hipFree(p->d_off);
+  if (p->d_path_base) (void)hipFree(p->d_path_base);
+  if (p->d_med_ab) (void)hipFree(p->d_med_ab);
+  delete p;
+}
+
+size_t wts_workspace_bytes(const wts_plan* p, int op) {
+  if (!p) return 0;
+  switch (op) {
+    case WTS_OP_ALIGN:
+    case WTS_OP_ALIGN_PATHS:
+    case WTS_OP_DBA:
+    case WTS_OP_SCORE:
+      return p->L > 0 ? layout(p, op).total : 0;
+    case WTS_OP_MEDOID:
+      return p->L == 0 ? layout(p, op).total : 0;
+    default:
+      return 0;
+  }
+}
+
+wts_status wts_dtw_align(const wts_plan* p, const double* bary, const void* cycles, double* dist,
+                         int64_t* path_len, int32_t* paths, void* ws, size_t ws_bytes,
+                         void* stream) {
+  wts_status rc = check_bary_plan(p);
+  if (rc != WTS_OK) return rc;
+  if (!bary || !cycles || !dist || !path_len) return fail(WTS_E_ARG, "null bary/cycles/dist/path_len");
+  if (paths && p->opts.cost != WTS_COST_SQEUCLID)
+    return fail(WTS_E_UNSUPPORTED, "paths are recovered for the squared cost only");
+  const int op = paths ? WTS_OP_ALIGN_PATHS : WTS_OP_ALIGN;
+  if ((rc = check_ws(p, op, ws, ws_bytes)) != WTS_OK) return rc;
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout l = layout(p, op);
+  if (!paths) {
+    rc = run_sweep(p, p->bary, wts::MODE_DIST_LEN, p->opts.cost == WTS_COST_EUCLID, false, bary,
+                   cycles, ws, l, dist, st);
+    if (rc != WTS_OK) return rc;
+    HIP_TRY(wts::launch_score(dist, at<int>(ws, l.out_aux), p->n, nullptr, path_len, st));
+    return WTS_OK;
+  }
+  rc = run_paths(p, bary, cycles, ws, l, dist, nullptr, nullptr, st);
+  if (rc != WTS_OK) return rc;
+  const PairSet& ps = p->bary;
+  HIP_TRY(wts::launch_seg_prefix(ps.d_pairs, ps.n_pairs, at<int>(ws, l.seg_len),
+                                 at<int>(ws, l.seg_off), path_len, st));
+  wts::WalkArgs w{};
+  w.pairs = ps.d_pairs;
+  w.items = ps.d_items;
+  w.seg = at<int2>(ws, l.seg);
+  w.codes = at<uint32_t>(ws, l.codes);
+  w.y = cycles;
+  w.L = p->L;
+  w.seg_len = at<int>(ws, l.seg_len);
+  w.seg_off = at<int>(ws, l.seg_off);
+  w.path_base = p->d_path_base;
+  w.paths = paths;
+  w.status = at<int>(ws, l.queue) + 1;
+  HIP_TRY(wts::launch_walk(p->d, p->rho, p->dtype, true, w, ps.n_items, st));
+  return WTS_OK;
+}
+
+wts_status wts_dba_iterate(const wts_plan* p, const double* bary_in, const void* cycles,
+                           const double* weights, double* bary_out, int64_t* counts, double* dist,
+                           void* ws, size_t ws_bytes, void* stream) {
+  wts_status rc = check_bary_plan(p);
+  if (rc != WTS_OK) return rc;
+  if (!bary_in || !cycles || !bary_out || !counts) return fail(WTS_E_ARG, "null bary/cycles/out/counts");
+  if (bary_in == bary_out) return fail(WTS_E_ARG, "bary_out must not alias bary_in");
+  if ((rc = check_ws(p, WTS_OP_DBA, ws, ws_bytes)) != WTS_OK) return rc;
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout l = layout(p, WTS_OP_DBA);
+  rc = run_paths(p, bary_in, cycles, ws, l, dist, at<double>(ws, l.psum), at<int>(ws, l.pcnt), st);
+  if (rc != WTS_OK) return rc;
+  HIP_TRY(wts::launch_dba_reduce(at<double>(ws, l.psum), at<int>(ws, l.pcnt), weights, p->n,
+                                 p->L, p->d, bary_out, counts, st));
+  return WTS_OK;
+}
+
+wts_status wts_anomaly_score(const wts_plan* p, const double* bary, const void* cycles,
+                             double* score, double* dist, int64_t* path_len, void* ws,
+                             size_t ws_bytes, void* stream) {
+  wts_status rc = check_bary_plan(p);
+  if (rc != WTS_OK) return rc;
+  if (!bary || !cycles || !score) return fail(WTS_E_ARG, "null bary/cycles/score");
+  if ((rc = check_ws(p, WTS_OP_SCORE, ws, ws_bytes)) != WTS_OK) return rc;
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout l = layout(p, WTS_OP_SCORE);
+  double* dv = dist ? dist : at<double>(ws, l.out_dist);
+  rc = run_sweep(p, p->bary, wts::MODE_DIST_LEN, p->opts.cost == WTS_COST_EUCLID, false, bary,
+                 cycles, ws, l, dv, st);
+  if (rc != WTS_OK) return rc;
+  HIP_TRY(wts::launch_score(dv, at<int>(ws, l.out_aux), p->n, score, path_len, st));
+  return WTS_OK;
+}
+
+wts_status wts_softdtw_forward(const wts_plan* p, const double*, const void*, double gamma,
+                               double*, void*, size_t, void*) {
+  wts_status rc = check_bary_plan(p);
+  if (rc != WTS_OK) return rc;
+  if (!(gamma > 0)) return fail(WTS_E_ARG, "gamma must be > 0");
+  return fail(WTS_E_UNSUPPORTED, "Soft-DTW forward is not built yet");
+}
+
+wts_status wts_softdtw_backward(const wts_plan* p, const double*, const void*, double gamma,
+                                const void*, size_t, const double*, double*, double*, void*,
+                                size_t, void*) {
+  wts_status rc = check_bary_plan(p);
+  if (rc != WTS_OK) return rc;
+  if (!(gamma > 0)) return fail(WTS_E_ARG, "gamma must be > 0");
+  return fail(WTS_E_UNSUPPORTED, "Soft-DTW backward is not built yet");
+}
+
+wts_status wts_medoid(const wts_plan* p, const void* cycles, double* dist_matrix, double* totals,
+                      int32_t* medoid, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(WTS_E_ARG, "plan is null");
+  if (p->L != 0) return fail(WTS_E_ARG, "wts_medoid needs a plan created with L = 0");
+  if (!cycles || !medoid) return fail(WTS_E_ARG, "null cycles/medoid");
+  wts_status rc = check_ws(p, WTS_OP_MEDOID, ws, ws_bytes);
+  if (rc != WTS_OK) return rc;
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout l = layout(p, WTS_OP_MEDOID);
+  double* Dm = dist_matrix ? dist_matrix : at<double>(ws, l.dm);
+  double* tot = totals ? totals : at<double>(ws, l.totals);
+  double* pair_dist = at<double>(ws, l.out_dist);
+  if (p->med.n_pairs > 0) {
+    rc = run_sweep(p, p->med, wts::MODE_DIST, false, true, cycles, cycles, ws, l, pair_dist, st);
+    if (rc != WTS_OK) return rc;
+  }
+  HIP_TRY(wts::launch_medoid(pair_dist, p->d_med_ab, p->med.n_pairs, p->n, Dm, tot, medoid, st));
+  return WTS_OK;
+}
+
+wts_status wts_init_barycenter(const wts_plan* p, const void* cycles, int32_t kind, int32_t index,
+                               double* bary_out, int32_t* chosen_host, void* stream) {
+  if (!p) return fail(WTS_E_ARG, "plan is null");
+  if (p->L <= 0) return fail(WTS_E_ARG, "wts_init_barycenter needs a plan with L > 0");
+  if (!cycles || !bary_out) return fail(WTS_E_ARG, "null cycles/bary_out");
+  int src = 0;
+  int64_t Nsrc = 0;
+  int euclid = 0;
+  if (kind == WTS_INIT_EUCLID_MEAN) {
+    euclid = 1;
+    Nsrc = p->nmax;
+  } else if (kind == WTS_INIT_NEAREST) {
+    int64_t best = INT64_MAX;
+    for (int k = 0; k < p->n; ++k) {
+      const int64_t N = p->off[k + 1] - p->off[k];
+      const int64_t dd = N > p->L ? N - p->L : p->L - N;
+      if (dd < best) { best = dd; src = k; }
+    }
+    Nsrc = p->off[src + 1] - p->off[src];
+  } else if (kind == WTS_INIT_COPY) {
+    if (index < 0 || index >= p->n) return fail(WTS_E_ARG, "index %d out of range", index);
+    src = index;
+    Nsrc = p->off[src + 1] - p->off[src];
+  } else {
+    return fail(WTS_E_ARG, "init kind %d", kind);
+  }
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(wts::launch_init(p->dtype, cycles, p->d_off, p->n, p->d, src, Nsrc, p->L, euclid,
+                           bary_out, st));
+  if (chosen_host) *chosen_host = euclid ? -1 : src;
+  return WTS_OK;
+}
+
+}  // extern "C"

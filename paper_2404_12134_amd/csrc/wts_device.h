@@ -1,0 +1,108 @@
+// wts_device.h -- device-side definitions shared by the WETSAND HIP kernels.
+//
+// Layout of the dynamic program on gfx950 (one wavefront = 64 lanes):
+//  * a "strip" is 64*RHO consecutive rows of X (the barycenter, or the
+//    shorter cycle for the medoid); lane k owns rows i0 + k*RHO .. + RHO-1 and
+//    keeps them in registers as float64;
+//  * the wave sweeps the columns (samples of Y) in a skewed order: at step t
+//    lane k works on column j = t - k, so the cells a lane needs from the
+//    rows above (lane k-1) were produced one step earlier and arrive through
+//    a DPP wave_shr:1 move; lane 0 takes them from the previous strip's
+//    bottom row;
+//  * strips of one pair run on different workgroups and hand their bottom
+//    row over through device memory, with a per-strip progress counter
+//    (columns published so far).  Both the row values and the counters use
+//    device-scope relaxed atomics, ordered by s_waitcnt, so no L2 writeback
+//    is needed;
+//  * workgroups pop (pair, strip) items from a queue in which the strips of
+//    one pair are consecutive and pairs are sorted by decreasing size: a
+//    strip only ever waits for an item popped earlier by a running
+//    workgroup, so the sweep cannot deadlock.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wts {
+
+constexpr int kWave = 64;
+
+struct PairDesc {
+  int64_t x_off;      // first row of X in the x buffer (row units)
+  int64_t y_off;      // first row of Y in the cycle buffer (row units)
+  int64_t code_base;  // first code word (uint32 units) of this pair
+  int64_t bnd_base;   // first element of this pair's boundary rows
+  int32_t M, N;       // rows of X, columns (samples of Y)
+  int32_t S;          // strips
+  int32_t out;        // output slot (cycle index, or pair index for the medoid)
+  int32_t flag_base;  // progress counter of strip 0
+  int32_t WT;         // code words per (strip, row, lane): ceil((N + 63) / 16) rounded
+  int32_t item_base;  // index of this pair's strip 0 in the item list
+  int32_t pad;
+  int64_t aux_base;   // first element of this pair's per-strip boundary tags (S * N)
+};
+
+enum Mode { MODE_DIST = 0, MODE_DIST_LEN = 1, MODE_PATH = 2 };
+
+struct FwdArgs {
+  const PairDesc* pairs;
+  const int2* items;     // (pair, strip)
+  int n_items;
+  int* queue;            // item counter, zeroed before the launch
+  int* status;           // device status word (bit 0: a boundary wait gave up)
+  int* progress;         // per strip: columns of its bottom row published
+  const void* x;         // X rows (float64 barycenter, or cycles for the medoid)
+  const void* y;         // cycle values
+  double* bnd_r;         // boundary rows: cumulative cost
+  int* bnd_aux;          // boundary rows: path length (DIST_LEN) or entry code (PATH)
+  uint32_t* codes;       // 2-bit argmin codes (PATH)
+  double* out_dist;      // [pair slot] r(M-1, N-1)
+  int* out_aux;          // [pair slot] |pi| (DIST_LEN) or entry code of (M-1, N-1) (PATH)
+  int aux_per_strip;     // 1: bnd_aux keeps every strip's bottom row (PATH)
+  int cost_kind;         // 0 squared, 1 Euclidean (sqrt)
+};
+
+__device__ __forceinline__ double inf_d() { return __builtin_huge_val(); }
+
+// Status bits reported in the workspace status word.
+constexpr int kStatusSpinTimeout = 1;   // a strip gave up waiting for its predecessor
+constexpr int kStatusBadPath = 2;       // path recovery left the strip (inconsistent tags)
+// Polls of a progress counter before a strip gives up (about a second);
+// a legitimate wait is bounded by one chunk of the predecessor strip.
+constexpr int kSpinLimit = 1 << 20;
+
+// DPP wave_shr:1 -- lane k receives v from lane k-1; lane 0 receives `old`.
+__device__ __forceinline__ int shr1_i32(int v, int old) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double shr1_f64(double v, double old) {
+  const long long s = __double_as_longlong(v), o = __double_as_longlong(old);
+  const int lo = shr1_i32((int)s, (int)o);
+  const int hi = shr1_i32((int)(s >> 32), (int)(o >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Device-scope relaxed accesses for data exchanged between workgroups.
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __longlong_as_double((long long)__hip_atomic_load(
+      reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_dev(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_dev(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait for every outstanding memory operation of this wave (orders the
+// relaxed stores above before a following progress-counter store).
+__device__ __forceinline__ void mem_drain() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+}  // namespace wts

@@ -1,0 +1,640 @@
+// wts_dtw.hip -- DTW forward sweep, path recovery, DBA update, scores, medoid
+// and barycenter initialisation for gfx950.
+//
+// The recurrence (Eq. 5 with gamma = 0, i.e. Eq. 1 by dynamic programming):
+//   r(-1,-1) = 0, r(i,-1) = r(-1,j) = +inf,
+//   r(i,j) = delta(x_i, y_j) + min(r(i-1,j-1), r(i-1,j), r(i,j-1)),
+// all in float64, delta = e_0*e_0 then fma(e_c, e_c, s) (Def. 3, squared
+// Euclidean).  The argmin code of a cell is the first of diag (0), up (1),
+// left (2) that attains the minimum; following the codes back from
+// (M-1, N-1) gives the optimal path that Eq. 8 divides by.
+#include <type_traits>
+
+#include "wts_device.h"
+#include "wts_kernels.h"
+
+namespace wts {
+
+namespace {
+
+template <int D>
+__device__ __forceinline__ double sq_cost(const double (&x)[D], const double (&y)[D]) {
+  double e = x[0] - y[0];
+  double s = e * e;
+#pragma unroll
+  for (int c = 1; c < D; ++c) {
+    e = x[c] - y[c];
+    s = __builtin_fma(e, e, s);
+  }
+  return s;
+}
+
+constexpr int kChunk = 64;          // sweep steps between two boundary hand-overs
+constexpr int kRing = 2 * kChunk;   // Y columns kept in LDS
+
+// One wavefront sweeps one strip of one pair.  State per lane: RHO rows of X
+// (float64 registers), the cumulative cost of those rows at the previous
+// column (`left`) and, for the row above its first row, the value received
+// one step earlier (`upprev`, the diagonal predecessor).
+template <typename TX, typename TY, int D, int RHO, int MODE, bool EUC>
+__global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
+  constexpr int H = kWave * RHO;
+  __shared__ double ys[D][kRing];
+  __shared__ double binr[kChunk];
+  __shared__ int binx[kChunk];
+  __shared__ double bor[kRing];
+  __shared__ int box[kRing];
+  __shared__ int s_item;
+
+  const int lane = threadIdx.x;
+  const TX* __restrict__ X = static_cast<const TX*>(a.x);
+  const TY* __restrict__ Y = static_cast<const TY*>(a.y);
+  const double INF = inf_d();
+
+  for (;;) {
+    if (lane == 0) s_item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= a.n_items) break;
+    const int2 it = a.items[item];
+    const PairDesc pd = a.pairs[it.x];
+    const int s = it.y;
+    const int M = pd.M, N = pd.N;
+    const int i0 = s * H;
+    const int ib = i0 + lane * RHO;
+    const bool has_prev = s > 0;
+    const bool has_next = s + 1 < pd.S;
+    const int Tend = pd.WT * 16;
+
+    double* r_row = a.bnd_r + pd.bnd_base;                       // rolling boundary row
+    int* aux_in = a.bnd_aux + (a.aux_per_strip ? pd.aux_base + (int64_t)(s - 1) * N : pd.bnd_base);
+    int* aux_out = a.bnd_aux + (a.aux_per_strip ? pd.aux_base + (int64_t)s * N : pd.bnd_base);
+    int* prog_in = a.progress + pd.flag_base + s - 1;
+    int* prog_out = a.progress + pd.flag_base + s;
+
+    double xr[RHO][D];
+#pragma unroll
+    for (int r = 0; r < RHO; ++r) {
+      const int i = ib + r;
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        xr[r][c] = (i < M) ? static_cast<double>(X[(pd.x_off + i) * D + c]) : 0.0;
+    }
+    double left[RHO];
+    int lx[RHO];
+    uint32_t acc[RHO];
+#pragma unroll
+    for (int r = 0; r < RHO; ++r) { left[r] = INF; lx[r] = 0; acc[r] = 0u; }
+    double upprev = (s == 0 && lane == 0) ? 0.0 : INF;   // r(-1,-1) = 0 at the origin
+    int upprevx = 0;
+    double bot = INF;
+    int botx = 0;
+    bool gave_up = false;   // set once a wait times out: the strip never waits again
+
+    double yv[D];
+    {
+      const int j = lane;
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        yv[c] = j < N ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
+    }
+    __syncthreads();
+
+    for (int t0 = 0; t0 < Tend; t0 += kChunk) {
+      const int tcnt = min(kChunk, Tend - t0);
+      const bool more = t0 + kChunk < Tend;
+      if (more) {   // next chunk of Y into registers; stored to LDS after this sweep
+        const int j = t0 + kChunk + lane;
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          yv[c] = j < N ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0;
+      }
+      if (has_prev) {
+        const int need = min(N, t0 + kChunk);
+        if (lane == 0 && !gave_up) {
+          int polls = 0;
+          while (ld_dev(prog_in) < need) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > kSpinLimit) {   // never expected: report and carry on
+              atomicOr(a.status, kStatusSpinTimeout);
+              gave_up = true;
+              break;
+            }
+          }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int j = t0 + lane;
+        binr[lane] = j < N ? ld_dev(r_row + j) : INF;
+        if (MODE != MODE_DIST) binx[lane] = j < N ? ld_dev(aux_in + j) : 0;
+      }
+      __syncthreads();
+
+      // 16 sweep steps; FULL: every lane is inside the grid (no masking)
+      auto group16 = [&](auto full_tag, int tb) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        const int tg = t0 + tb;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int t = tg + u;
+          const int j = t - lane;
+          const double bval = has_prev ? binr[tb + u] : INF;
+          const double upin = shr1_f64(bot, bval);
+          int upinx = 0, dgx0 = 0;
+          if (MODE == MODE_DIST_LEN) {
+            upinx = shr1_i32(botx, has_prev ? binx[tb + u] : 0);
+            dgx0 = upprevx;
+          } else if (MODE == MODE_PATH) {
+            // top row of the strip (lane 0): entered from above at column j,
+            // coded 2j (up) or 2j+1 (diagonal)
+            upinx = shr1_i32(botx, 2 * t);
+            dgx0 = lane == 0 ? upinx + 1 : upprevx;
+          }
+          const double dg0 = upprev;
+          upprev = upin;
+          upprevx = upinx;
+          if (FULL || (j >= 0 && j < N)) {
+            double y[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
+            double dg = dg0, up = upin;
+            int dgx = dgx0, upx = upinx;
+#pragma unroll
+            for (int r = 0; r < RHO; ++r) {
+              const double lf = left[r];
+              const double m1 = __builtin_fmin(up, lf);
+              const double m = __builtin_fmin(dg, m1);
+              double delta = sq_cost<D>(xr[r], y);
+              if (EUC) delta = __builtin_sqrt(delta);
+              const double rv = delta + m;
+              int rxv = 0;
+              if (MODE != MODE_DIST) {
+                const bool isd = dg <= m1;
+                const bool isu = up <= lf;
+                // keep these as lane selects (v_cndmask), not branches
+                const int t1 = __builtin_unpredictable(isu) ? upx : lx[r];
+                const int sel = __builtin_unpredictable(isd) ? dgx : t1;
+                rxv = MODE == MODE_DIST_LEN ? sel + 1 : sel;
+                if (MODE == MODE_PATH) {
+                  const uint32_t c1 = __builtin_unpredictable(isu) ? 1u : 2u;
+                  const uint32_t code = __builtin_unpredictable(isd) ? 0u : c1;
+                  acc[r] = (u == 0) ? code : (acc[r] | (code << (2 * u)));
+                }
+              }
+              dg = lf;
+              dgx = lx[r];
+              up = rv;
+              upx = rxv;
+              left[r] = rv;
+              lx[r] = rxv;
+            }
+            bot = left[RHO - 1];
+            botx = lx[RHO - 1];
+          }
+          if (has_next && lane == kWave - 1 && (FULL || (j >= 0 && j < N))) {
+            bor[j & (kRing - 1)] = bot;
+            if (MODE != MODE_DIST) box[j & (kRing - 1)] = botx;
+          }
+        }
+        if (MODE == MODE_PATH) {
+          const int w = tg >> 4;
+#pragma unroll
+          for (int r = 0; r < RHO; ++r)
+            a.codes[pd.code_base + ((int64_t)(s * pd.WT + w) * RHO + r) * kWave + lane] = acc[r];
+        }
+      };
+      for (int tb = 0; tb < tcnt; tb += 16) {
+        const int tg = t0 + tb;
+        if (tg >= kWave - 1 && tg + 16 <= N) group16(std::true_type{}, tb);
+        else group16(std::false_type{}, tb);
+      }
+      __syncthreads();
+      if (has_next) {   // publish the bottom-row columns finished in this chunk
+        const int jend = t0 + tcnt - (kWave - 1);
+        const int j = t0 - (kWave - 1) + lane;
+        if (j >= 0 && j < N && j < jend) {
+          st_dev(r_row + j, bor[j & (kRing - 1)]);
+          if (MODE != MODE_DIST) st_dev(aux_out + j, box[j & (kRing - 1)]);
+        }
+        mem_drain();
+        if (lane == 0) st_dev(prog_out, min(N, max(0, jend)));
+      }
+      if (more) {
+        const int j = t0 + kChunk + lane;
+#pragma unroll
+        for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
+      }
+      __syncthreads();
+    }
+    // every lane ends with left[r] = r(ib + r, N - 1)
+    if (ib <= M - 1 && M - 1 < ib + RHO) {
+      const int rl = M - 1 - ib;
+      double v = left[0];
+      int vx = lx[0];
+#pragma unroll
+      for (int r = 1; r < RHO; ++r)
+        if (r == rl) { v = left[r]; vx = lx[r]; }
+      a.out_dist[pd.out] = v;
+      if (MODE != MODE_DIST) a.out_aux[pd.out] = vx;
+    }
+    __syncthreads();
+  }
+}
+
+// Strip-level path recovery.  The forward sweep tagged every cell with the
+// top-row cell through which its optimal path enters the strip (code 2j for
+// "from (i0-1, j)", 2j+1 for "from (i0-1, j-1)"), and kept that tag for the
+// bottom row of every strip.  Walking the tags from (M-1, N-1) gives, per
+// strip, where the path crosses its bottom row and its top row.
+__global__ void chain_kernel(const PairDesc* __restrict__ pairs, int n_pairs,
+                             const int* __restrict__ bnd_aux, const int* __restrict__ out_aux,
+                             int2* __restrict__ seg, int* __restrict__ status) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const PairDesc pd = pairs[p];
+  int e = out_aux[pd.out];
+  int jx = pd.N - 1;
+  for (int s = pd.S - 1; s >= 0; --s) {
+    const int jtop = e >> 1;
+    if (jtop < 0 || jtop > jx) {   // inconsistent tags: mark every strip left empty
+      atomicOr(status, kStatusBadPath);
+      for (int q = s; q >= 0; --q) seg[pd.item_base + q] = make_int2(-1, -1);
+      return;
+    }
+    seg[pd.item_base + s] = make_int2(jx, jtop);
+    if (s == 0) break;
+    const int jp = jtop - (e & 1);
+    if (jp < 0) {
+      atomicOr(status, kStatusBadPath);
+      for (int q = s - 1; q >= 0; --q) seg[pd.item_base + q] = make_int2(-1, -1);
+      return;
+    }
+    e = bnd_aux[pd.aux_base + (int64_t)(s - 1) * pd.N + jp];
+    jx = jp;
+  }
+}
+
+constexpr int kWalkWords = 16;   // code words (per row and lane) staged in LDS at a time
+
+// Walks the optimal path through one strip, from its bottom-row crossing to
+// its top-row cell, with the strip's argmin codes staged in LDS.  All 64
+// lanes walk in lockstep (identical state), so the staging loads are
+// cooperative and the LDS reads are broadcasts.
+//   EMIT = false: per-row runs -> DBA partial sums (psum != nullptr) and the
+//                 strip's segment length;
+//   EMIT = true:  writes the segment's (i, j) pairs into the path list.
+template <typename TY, int D, int RHO, bool EMIT>
+__global__ __launch_bounds__(kWave) void walk_kernel(WalkArgs a) {
+  constexpr int H = kWave * RHO;
+  __shared__ uint32_t blk[kWalkWords][RHO][kWave];
+  __shared__ int run_lo[H];
+  __shared__ int run_hi[H];
+  const int lane = threadIdx.x;
+  const int item = blockIdx.x;
+  const int2 it = a.items[item];
+  const PairDesc pd = a.pairs[it.x];
+  const int s = it.y;
+  const int i0 = s * H;
+  const int iend = min(pd.M, i0 + H) - 1;
+  const int2 sg = a.seg[item];
+  const uint32_t* codes = a.codes + pd.code_base + (int64_t)s * pd.WT * RHO * kWave;
+
+  int i = iend, j = sg.x, hi = sg.x;
+  const int jstop = sg.y;
+  if (sg.x < 0 || sg.x >= pd.N || sg.y < 0 || sg.y > sg.x) {   // chain reported a bad path
+    if (lane == 0 && !EMIT) {
+      a.seg_len[item] = 0;
+      atomicOr(a.status, kStatusBadPath);
+    }
+    return;
+  }
+  int wlo = 1 << 30, whi = -1;
+  int cnt = 0;
+  int32_t* out = nullptr;
+  int seg_len = 0;
+  if (EMIT) {
+    out = a.paths + 2 * (a.path_base[pd.out] + a.seg_off[item]);
+    seg_len = a.seg_len[item];
+  }
+  for (;;) {
+    if (i < i0 || j < 0 || (EMIT && cnt >= seg_len)) {   // left the strip: inconsistent tags
+      if (lane == 0) atomicOr(a.status, kStatusBadPath);
+      break;
+    }
+    if (EMIT && lane == 0) {
+      out[2 * (seg_len - 1 - cnt)] = i;
+      out[2 * (seg_len - 1 - cnt) + 1] = j;
+    }
+    ++cnt;
+    if (i == i0 && j == jstop) {
+      if (!EMIT && lane == 0) { run_lo[0] = j; run_hi[0] = hi; }
+      break;
+    }
+    const int q = i - i0;
+    const int k = q / RHO, r = q - k * RHO;
+    const int t = j + k;
+    const int w = t >> 4;
+    if (w < wlo || w > whi) {
+      __syncthreads();
+      wlo = max(0, w - kWalkWords + 1);
+      whi = w;
+      for (int ww = wlo; ww <= whi; ++ww)
+#pragma unroll
+        for (int rr = 0; rr < RHO; ++rr)
+          blk[ww - wlo][rr][lane] = codes[((int64_t)ww * RHO + rr) * kWave + lane];
+      __syncthreads();
+    }
+    const uint32_t code = (blk[w - wlo][r][k] >> (2 * (t & 15))) & 3u;
+    if (code == 2u) {
+      --j;
+    } else {
+      if (!EMIT && lane == 0) { run_lo[q] = j; run_hi[q] = hi; }
+      --i;
+      if (code == 0u) --j;
+      hi = j;
+    }
+  }
+  if (EMIT) return;
+  if (lane == 0) a.seg_len[item] = cnt;
+  if (a.psum == nullptr) return;
+  __syncthreads();
+  const TY* __restrict__ Y = static_cast<const TY*>(a.y);
+  const int nrows = iend - i0 + 1;
+  for (int q = lane; q < nrows; q += kWave) {
+    const int lo = run_lo[q], h = run_hi[q];
+    const int64_t o = ((int64_t)pd.out * a.L + i0 + q);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double acc = 0.0;
+      for (int jj = h; jj >= lo; --jj) acc = acc + static_cast<double>(Y[(pd.y_off + jj) * D + c]);
+      a.psum[o * D + c] = acc;
+    }
+    a.pcnt[o] = h - lo + 1;
+  }
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- small kernels
+
+__global__ void zero_i32_kernel(int* p, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = 0;
+}
+
+// Segment offsets in forward path order (strip 0 first) and |pi| per pair.
+__global__ void seg_prefix_kernel(const PairDesc* __restrict__ pairs, int n_pairs,
+                                  const int* __restrict__ seg_len, int* __restrict__ seg_off,
+                                  int64_t* __restrict__ path_len) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  const PairDesc pd = pairs[p];
+  int off = 0;
+  for (int s = 0; s < pd.S; ++s) {
+    seg_off[pd.item_base + s] = off;
+    off += seg_len[pd.item_base + s];
+  }
+  if (path_len) path_len[pd.out] = off;
+}
+
+// B'_l = S_l / C_l with S_l, C_l folded over cycles in ascending order.
+__global__ void dba_reduce_kernel(const double* __restrict__ psum, const int* __restrict__ pcnt,
+                                  const double* __restrict__ w, int n, int64_t L, int d,
+                                  double* __restrict__ bout, int64_t* __restrict__ counts) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= L * d) return;
+  const int64_t l = idx / d;
+  const int c = (int)(idx - l * d);
+  double S = 0.0, C = 0.0;
+  int64_t K = 0;
+  for (int p = 0; p < n; ++p) {
+    const double wp = w ? w[p] : 1.0;
+    S = S + wp * psum[((int64_t)p * L + l) * d + c];
+  }
+  for (int p = 0; p < n; ++p) {
+    const double wp = w ? w[p] : 1.0;
+    const int k = pcnt[(int64_t)p * L + l];
+    C = C + wp * (double)k;
+    K += k;
+  }
+  bout[idx] = S / C;
+  if (c == 0 && counts) counts[l] = K;
+}
+
+__global__ void score_kernel(const double* __restrict__ dist, const int* __restrict__ len, int n,
+                             double* __restrict__ score, int64_t* __restrict__ path_len) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double dv = dist[p];
+  const int lv = len[p];
+  if (score) score[p] = dv / (double)lv;
+  if (path_len) path_len[p] = lv;
+}
+
+// Medoid: D[a][b] = D[b][a] = DTW of pair (a, b); totals in ascending order.
+__global__ void medoid_fill_kernel(const double* __restrict__ pair_dist,
+                                   const int2* __restrict__ pair_ab, int n_pairs, int n,
+                                   double* __restrict__ Dm) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n_pairs) {
+    const int2 ab = pair_ab[k];
+    Dm[(int64_t)ab.x * n + ab.y] = pair_dist[k];
+    Dm[(int64_t)ab.y * n + ab.x] = pair_dist[k];
+  }
+  if (k < n) Dm[k * n + k] = 0.0;
+}
+
+__global__ void medoid_total_kernel(const double* __restrict__ Dm, int n,
+                                    double* __restrict__ totals) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s = s + Dm[(int64_t)k * n + i];
+  totals[k] = s;
+}
+
+__global__ void medoid_argmin_kernel(const double* __restrict__ totals, int n,
+                                     int32_t* __restrict__ medoid) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int best = 0;
+  double bv = inf_d();
+  for (int k = 0; k < n; ++k)
+    if (totals[k] < bv) { bv = totals[k]; best = k; }
+  *medoid = best;
+}
+
+// Resampling at t_l = l (N-1)/(L-1); source = one cycle, or (euclid = true)
+// the per-index mean of all cycles padded with their last sample.
+template <typename TY>
+__global__ void init_kernel(const TY* __restrict__ Y, const int64_t* __restrict__ off, int n,
+                            int d, int src, int64_t Nsrc, int64_t L, int euclid,
+                            double* __restrict__ out) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= L * d) return;
+  const int64_t l = idx / d;
+  const int c = (int)(idx - l * d);
+  auto sample = [&](int64_t tt) -> double {
+    if (!euclid) return static_cast<double>(Y[(off[src] + tt) * d + c]);
+    double s = 0.0;
+    for (int p = 0; p < n; ++p) {
+      const int64_t Np = off[p + 1] - off[p];
+      const int64_t q = tt < Np ? tt : Np - 1;
+      s = s + static_cast<double>(Y[(off[p] + q) * d + c]);
+    }
+    return s / (double)n;
+  };
+  const double pos = L == 1 ? 0.0 : ((double)l * (double)(Nsrc - 1)) / (double)(L - 1);
+  const int64_t a0 = (int64_t)__builtin_floor(pos);
+  double v;
+  if (a0 >= Nsrc - 1) {
+    v = sample(Nsrc - 1);
+  } else {
+    const double f = pos - (double)a0;
+    const double ya = sample(a0), yb = sample(a0 + 1);
+    v = ya + f * (yb - ya);
+  }
+  out[idx] = v;
+}
+
+// ------------------------------------------------------------------ dispatch
+
+template <typename TX, typename TY, int D, int RHO>
+static hipError_t launch_fwd_t(int mode, bool euc, const FwdArgs& a, int grid, hipStream_t st) {
+  if (mode == MODE_DIST) {
+    hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST, false>), dim3(grid),
+                       dim3(kWave), 0, st, a);
+  } else if (mode == MODE_DIST_LEN) {
+    if (euc)
+      hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST_LEN, true>), dim3(grid),
+                         dim3(kWave), 0, st, a);
+    else
+      hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST_LEN, false>), dim3(grid),
+                         dim3(kWave), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_PATH, false>), dim3(grid),
+                       dim3(kWave), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <int D, int RHO>
+static hipError_t launch_fwd_d(int mode, bool euc, bool x_is_cycle, int ydtype,
+                               const FwdArgs& a, int grid, hipStream_t st) {
+  if (ydtype == 0) {
+    if (x_is_cycle) {
+      if (mode != MODE_DIST) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((dtw_fwd_kernel<float, float, D, RHO, MODE_DIST, false>), dim3(grid),
+                         dim3(kWave), 0, st, a);
+      return hipGetLastError();
+    }
+    return launch_fwd_t<double, float, D, RHO>(mode, euc, a, grid, st);
+  }
+  if (x_is_cycle && mode != MODE_DIST) return hipErrorInvalidValue;
+  return launch_fwd_t<double, double, D, RHO>(mode, euc, a, grid, st);
+}
+
+#define WTS_D_SWITCH(d, RHO, CALL)   \
+  switch (d) {                       \
+    case 1: return CALL(1, RHO);     \
+    case 2: return CALL(2, RHO);     \
+    case 3: return CALL(3, RHO);     \
+    case 4: return CALL(4, RHO);     \
+    case 5: return CALL(5, RHO);     \
+    case 6: return CALL(6, RHO);     \
+    case 7: return CALL(7, RHO);     \
+    case 8: return CALL(8, RHO);     \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_fwd(int d, int rho, int mode, bool euc, bool x_is_cycle, int ydtype,
+                      const FwdArgs& a, int grid, hipStream_t st) {
+#define CALLF(D, R) launch_fwd_d<D, R>(mode, euc, x_is_cycle, ydtype, a, grid, st)
+  if (rho == 4) { WTS_D_SWITCH(d, 4, CALLF) }
+  if (rho == 2) { WTS_D_SWITCH(d, 2, CALLF) }
+#undef CALLF
+  return hipErrorInvalidValue;
+}
+
+template <typename TY, int D, int RHO>
+static hipError_t launch_walk_t(bool emit, const WalkArgs& a, int n_items, hipStream_t st) {
+  if (emit)
+    hipLaunchKernelGGL((walk_kernel<TY, D, RHO, true>), dim3(n_items), dim3(kWave), 0, st, a);
+  else
+    hipLaunchKernelGGL((walk_kernel<TY, D, RHO, false>), dim3(n_items), dim3(kWave), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk(int d, int rho, int ydtype, bool emit, const WalkArgs& a, int n_items,
+                       hipStream_t st) {
+#define CALLW(D, R) (ydtype == 0 ? launch_walk_t<float, D, R>(emit, a, n_items, st) \
+                                 : launch_walk_t<double, D, R>(emit, a, n_items, st))
+  if (rho == 4) { WTS_D_SWITCH(d, 4, CALLW) }
+  if (rho == 2) { WTS_D_SWITCH(d, 2, CALLW) }
+#undef CALLW
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_chain(const PairDesc* pairs, int n_pairs, const int* bnd_aux,
+                        const int* out_aux, int2* seg, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(chain_kernel, dim3((n_pairs + 63) / 64), dim3(64), 0, st, pairs, n_pairs,
+                     bnd_aux, out_aux, seg, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(int* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256),
+                     0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_prefix(const PairDesc* pairs, int n_pairs, const int* seg_len,
+                             int* seg_off, int64_t* path_len, hipStream_t st) {
+  hipLaunchKernelGGL(seg_prefix_kernel, dim3((n_pairs + 63) / 64), dim3(64), 0, st, pairs,
+                     n_pairs, seg_len, seg_off, path_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_dba_reduce(const double* psum, const int* pcnt, const double* w, int n,
+                             int64_t L, int d, double* bout, int64_t* counts, hipStream_t st) {
+  const int64_t tot = L * d;
+  hipLaunchKernelGGL(dba_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     psum, pcnt, w, n, L, d, bout, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_score(const double* dist, const int* len, int n, double* score,
+                        int64_t* path_len, hipStream_t st) {
+  hipLaunchKernelGGL(score_kernel, dim3((n + 255) / 256), dim3(256), 0, st, dist, len, n, score,
+                     path_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_medoid(const double* pair_dist, const int2* pair_ab, int n_pairs, int n,
+                         double* Dm, double* totals, int32_t* medoid, hipStream_t st) {
+  const int64_t m = n_pairs > n ? n_pairs : n;
+  hipLaunchKernelGGL(medoid_fill_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                     pair_dist, pair_ab, n_pairs, n, Dm);
+  hipLaunchKernelGGL(medoid_total_kernel, dim3((n + 255) / 256), dim3(256), 0, st, Dm, n, totals);
+  hipLaunchKernelGGL(medoid_argmin_kernel, dim3(1), dim3(64), 0, st, totals, n, medoid);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int ydtype, const void* Y, const int64_t* off, int n, int d, int src,
+                       int64_t Nsrc, int64_t L, int euclid, double* out, hipStream_t st) {
+  const int64_t tot = L * d;
+  const dim3 g((unsigned)((tot + 255) / 256));
+  if (ydtype == 0)
+    hipLaunchKernelGGL(init_kernel<float>, g, dim3(256), 0, st, static_cast<const float*>(Y), off,
+                       n, d, src, Nsrc, L, euclid, out);
+  else
+    hipLaunchKernelGGL(init_kernel<double>, g, dim3(256), 0, st, static_cast<const double*>(Y),
+                       off, n, d, src, Nsrc, L, euclid, out);
+  return hipGetLastError();
+}
+
+}  // namespace wts

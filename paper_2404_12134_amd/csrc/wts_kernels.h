@@ -1,0 +1,44 @@
+// wts_kernels.h -- host-side launchers of the WETSAND kernels (wts_dtw.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wts_device.h"
+
+namespace wts {
+
+struct WalkArgs {
+  const PairDesc* pairs;
+  const int2* items;
+  const int2* seg;          // per item: (bottom-row column, top-row column) of the path
+  const uint32_t* codes;
+  const void* y;
+  double* psum;             // [out][L][d] per-cycle row sums, or nullptr
+  int* pcnt;                // [out][L] per-cycle row counts
+  int64_t L;
+  int* seg_len;             // per item: cells of the path inside the strip
+  const int* seg_off;       // per item: offset of the strip's segment in the pair's path
+  const int64_t* path_base; // per pair slot: first path row
+  int32_t* paths;           // [rows][2]
+  int* status;              // device status word
+};
+
+hipError_t launch_fwd(int d, int rho, int mode, bool euc, bool x_is_cycle, int ydtype,
+                      const FwdArgs& a, int grid, hipStream_t st);
+hipError_t launch_walk(int d, int rho, int ydtype, bool emit, const WalkArgs& a, int n_items,
+                       hipStream_t st);
+hipError_t launch_chain(const PairDesc* pairs, int n_pairs, const int* bnd_aux,
+                        const int* out_aux, int2* seg, int* status, hipStream_t st);
+hipError_t launch_zero(int* p, int64_t n, hipStream_t st);
+hipError_t launch_seg_prefix(const PairDesc* pairs, int n_pairs, const int* seg_len,
+                             int* seg_off, int64_t* path_len, hipStream_t st);
+hipError_t launch_dba_reduce(const double* psum, const int* pcnt, const double* w, int n,
+                             int64_t L, int d, double* bout, int64_t* counts, hipStream_t st);
+hipError_t launch_score(const double* dist, const int* len, int n, double* score,
+                        int64_t* path_len, hipStream_t st);
+hipError_t launch_medoid(const double* pair_dist, const int2* pair_ab, int n_pairs, int n,
+                         double* Dm, double* totals, int32_t* medoid, hipStream_t st);
+hipError_t launch_init(int ydtype, const void* Y, const int64_t* off, int n, int d, int src,
+                       int64_t Nsrc, int64_t L, int euclid, double* out, hipStream_t st);
+
+}  // namespace wts

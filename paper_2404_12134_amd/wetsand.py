@@ -1,0 +1,246 @@
+"""Thin Python binding of libwetsand_mi.so (the C ABI in include/wetsand_mi.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels behind the C ABI.  PyTorch provides device memory (tensors) and the
+stream (torch's current stream) -- nothing is computed with it here.
+The library is required: if it is not built, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwetsand_mi.so")
+
+F32, F64 = 0, 1
+COST_SQ, COST_EUCLID = 0, 1
+OP_ALIGN, OP_ALIGN_PATHS, OP_DBA, OP_SCORE, OP_SOFT_FWD, OP_SOFT_BWD, OP_MEDOID = range(7)
+INIT_EUCLID_MEAN, INIT_NEAREST, INIT_COPY = 0, 1, 2
+
+_lib = None
+
+
+class WtsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("wetsand_mi status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("cost", ctypes.c_int32), ("rho", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+def load():
+    """Open the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libwetsand_mi.so is not built (python -m paper_2404_12134_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t,
+                          ctypes.c_double)
+    sig = {
+        "wts_plan_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, I32, I32, I32, P, I64,
+                            ctypes.POINTER(_Opts)],
+        "wts_workspace_bytes": [P, ctypes.c_int],
+        "wts_dtw_align": [P, P, P, P, P, P, P, SZ, P],
+        "wts_dba_iterate": [P, P, P, P, P, P, P, P, SZ, P],
+        "wts_anomaly_score": [P, P, P, P, P, P, P, SZ, P],
+        "wts_softdtw_forward": [P, P, P, D, P, P, SZ, P],
+        "wts_softdtw_backward": [P, P, P, D, P, SZ, P, P, P, P, SZ, P],
+        "wts_medoid": [P, P, P, P, P, P, SZ, P],
+        "wts_init_barycenter": [P, P, I32, I32, P, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.wts_workspace_bytes.restype = SZ
+    L.wts_plan_destroy.argtypes = [P]
+    L.wts_plan_destroy.restype = None
+    L.wts_last_error.argtypes = []
+    L.wts_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    """Names the binding expects the library to export."""
+    return ["wts_plan_create", "wts_plan_destroy", "wts_workspace_bytes", "wts_last_error",
+            "wts_dtw_align", "wts_dba_iterate", "wts_anomaly_score", "wts_softdtw_forward",
+            "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter"]
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise WtsError(rc, load().wts_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A plan binds the cycle lengths, the channel count, the storage dtype and
+    the barycenter length L (L = 0: a plan for the medoid only)."""
+
+    def __init__(self, offsets, d: int, dtype: str, L: int, device: int = 0, cost: str = "sq",
+                 rho: int = 0, grid: int = 0):
+        lib = load()
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.offsets = off
+        self.n = int(off.size - 1)
+        self.d = int(d)
+        self.dtype = dtype
+        self.L = int(L)
+        self.device = int(device)
+        opts = _Opts(COST_EUCLID if cost == "euclid" else COST_SQ, int(rho), int(grid), 0)
+        h = ctypes.c_void_p()
+        _check(lib.wts_plan_create(ctypes.byref(h), self.device, self.n, self.d,
+                                   F32 if dtype == "f32" else F64,
+                                   off.ctypes.data_as(ctypes.c_void_p), self.L,
+                                   ctypes.byref(opts)))
+        self._h = h
+        self._ws = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self, op: int) -> int:
+        return int(load().wts_workspace_bytes(self._h, op))
+
+    def workspace(self, op: int) -> torch.Tensor:
+        """A cached, 256-byte aligned device buffer for operation `op`."""
+        nbytes = self.workspace_bytes(op)
+        ws = self._ws.get(op)
+        if ws is None or ws[1] < nbytes:
+            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda:%d" % self.device)
+            shift = (-raw.data_ptr()) % 256
+            ws = (raw, nbytes, raw[shift:shift + nbytes])
+            self._ws[op] = ws
+        return ws[2]
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.wts_plan_destroy(self._h)
+            self._h = None
+        self._ws = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_status(plan: Plan, op: int) -> int:
+    """Status word the kernels of the last `op` call left in its workspace
+    (0 = clean; 1 = a strip gave up waiting; 2 = path recovery inconsistency)."""
+    ws = plan._ws.get(op)
+    if ws is None:
+        return 0
+    return int(ws[2][4:8].view(torch.int32).item())
+
+
+def pack_cycles(cycles: Sequence[np.ndarray], device: int = 0, dtype: Optional[str] = None):
+    """Host ragged cycles -> (device tensor [sum N][d], int64 offsets)."""
+    lens = np.array([c.shape[0] for c in cycles], dtype=np.int64)
+    off = np.zeros(len(cycles) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    vals = np.concatenate([np.asarray(c).reshape(c.shape[0], -1) for c in cycles], axis=0)
+    if dtype is None:
+        dtype = "f32" if vals.dtype == np.float32 else "f64"
+    vals = vals.astype(np.float32 if dtype == "f32" else np.float64, copy=False)
+    t = torch.from_numpy(np.ascontiguousarray(vals)).to("cuda:%d" % device)
+    return t, off, dtype
+
+
+def _dev(plan: Plan):
+    return "cuda:%d" % plan.device
+
+
+def dtw_align(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, paths: bool = False):
+    """Eq. 1 per cycle: (dist [n] f64, path_len [n] i64, paths or None).
+
+    With paths=True the path rows of cycle k start at k*(L-1) + offsets[k]."""
+    n = plan.n
+    dist = torch.empty(n, dtype=torch.float64, device=_dev(plan))
+    plen = torch.empty(n, dtype=torch.int64, device=_dev(plan))
+    pth = None
+    op = OP_ALIGN
+    if paths:
+        rows = n * (plan.L - 1) + int(plan.offsets[-1])
+        pth = torch.empty((rows, 2), dtype=torch.int32, device=_dev(plan))
+        op = OP_ALIGN_PATHS
+    ws = plan.workspace(op)
+    _check(load().wts_dtw_align(plan.handle, _ptr(bary), _ptr(cycles), _ptr(dist), _ptr(plen),
+                                _ptr(pth), _ptr(ws), ws.numel(), _stream()))
+    return dist, plen, pth
+
+
+def path_of(plan: Plan, paths: torch.Tensor, path_len: torch.Tensor, k: int) -> np.ndarray:
+    base = k * (plan.L - 1) + int(plan.offsets[k])
+    return paths[base:base + int(path_len[k])].cpu().numpy()
+
+
+def dba_iterate(plan: Plan, bary_in: torch.Tensor, cycles: torch.Tensor,
+                weights: Optional[torch.Tensor] = None, bary_out: Optional[torch.Tensor] = None,
+                counts: Optional[torch.Tensor] = None, dist: Optional[torch.Tensor] = None):
+    """One DBA update: returns (bary_out [L][d] f64, counts [L] i64, dist [n] f64)."""
+    if bary_out is None:
+        bary_out = torch.empty((plan.L, plan.d), dtype=torch.float64, device=_dev(plan))
+    if counts is None:
+        counts = torch.empty(plan.L, dtype=torch.int64, device=_dev(plan))
+    if dist is None:
+        dist = torch.empty(plan.n, dtype=torch.float64, device=_dev(plan))
+    ws = plan.workspace(OP_DBA)
+    _check(load().wts_dba_iterate(plan.handle, _ptr(bary_in), _ptr(cycles), _ptr(weights),
+                                  _ptr(bary_out), _ptr(counts), _ptr(dist), _ptr(ws), ws.numel(),
+                                  _stream()))
+    return bary_out, counts, dist
+
+
+def anomaly_score(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor):
+    """Eq. 8: (score [n], dist [n], path_len [n])."""
+    n = plan.n
+    score = torch.empty(n, dtype=torch.float64, device=_dev(plan))
+    dist = torch.empty(n, dtype=torch.float64, device=_dev(plan))
+    plen = torch.empty(n, dtype=torch.int64, device=_dev(plan))
+    ws = plan.workspace(OP_SCORE)
+    _check(load().wts_anomaly_score(plan.handle, _ptr(bary), _ptr(cycles), _ptr(score),
+                                    _ptr(dist), _ptr(plen), _ptr(ws), ws.numel(), _stream()))
+    return score, dist, plen
+
+
+def medoid(plan: Plan, cycles: torch.Tensor, with_matrix: bool = True):
+    """All-pairs DTW: (medoid index tensor [1] i32, D [n][n] or None, totals [n])."""
+    n = plan.n
+    Dm = torch.empty((n, n), dtype=torch.float64, device=_dev(plan)) if with_matrix else None
+    tot = torch.empty(n, dtype=torch.float64, device=_dev(plan))
+    k = torch.empty(1, dtype=torch.int32, device=_dev(plan))
+    ws = plan.workspace(OP_MEDOID)
+    _check(load().wts_medoid(plan.handle, _ptr(cycles), _ptr(Dm), _ptr(tot), _ptr(k), _ptr(ws),
+                             ws.numel(), _stream()))
+    return k, Dm, tot
+
+
+def init_barycenter(plan: Plan, cycles: torch.Tensor, kind: int, index: int = 0):
+    """(bary [L][d] f64, index of the cycle used or -1 for the mean)."""
+    out = torch.empty((plan.L, plan.d), dtype=torch.float64, device=_dev(plan))
+    chosen = ctypes.c_int32(-2)
+    _check(load().wts_init_barycenter(plan.handle, _ptr(cycles), int(kind), int(index), _ptr(out),
+                                      ctypes.byref(chosen), _stream()))
+    return out, int(chosen.value)
