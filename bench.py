@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the WETSAND hot path on one MI355X.
+
+Workload (default): 64 cycles x 3 channels, float32, lengths U{4000..6000},
+random-Fourier template with random time warps, N(0, 0.05) noise and three
+cycles carrying a gradual drift.  One step is the whole DTW path over that
+batch: medoid initialisation (all-pairs DTW), 10 DBA iterations from the
+medoid, then the anomaly score of every cycle.  Inputs are resident in HBM
+before timing starts.
+
+Metric: DTW cell updates per second (GCUPS), cells = M * N per dynamic
+program (all pairs of the medoid, L * N_k per DBA iteration and for the
+scores).  Also reported: seconds per DBA iteration, per-phase GCUPS, the
+roofline fraction of the dominant kernel, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# gfx950 (MI355X): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz; FP64 add/mul/fma/min
+# issue at one per lane per clock (78.6 TFLOP/s FP64 vector counts an FMA as 2).
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9          # 39.32e12 lane-ops/s
+HBM_PEAK_GBS = 8000.0
+
+
+def c_min_dist(d: int) -> int:
+    """Algorithmic VALU ops per cell of the DTW value sweep (squared cost):
+    d subtractions, 1 multiply, d-1 FMAs, 2 minima, 1 add."""
+    return 2 * d + 3
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("wts_dtw.hip", "wts_device.h"):
+        with open(os.path.join(ROOT, "paper_2404_12134_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch measured with rocprofv3 PMC counters, if the
+    committed measurement was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p)).get(kernel)
+    except Exception:
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, n_sample: int = 16):
+    """The FP64 oracle on the first n_sample cycles: all-pairs medoid, one DBA
+    iteration from it and the scores.  Returns the record for the JSON line."""
+    import numpy as np
+    import oracle
+    cyc = [np.asarray(c, dtype=np.float64) for c in w.cycles[:n_sample]]
+    lens = np.array([c.shape[0] for c in cyc], dtype=np.int64)
+    t0 = time.perf_counter()
+    k, _ = oracle.medoid(cyc)
+    B = cyc[k]
+    Bn, _, _, _ = oracle.dba_iterate(B, cyc)
+    oracle.score_batch(Bn, cyc)
+    dt = time.perf_counter() - t0
+    n = len(cyc)
+    cells = int(sum(int(lens[a]) * int(lens[b]) for a in range(n) for b in range(n) if a != b))
+    cells += 2 * int(B.shape[0]) * int(lens.sum())
+    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": "first %d of %d cycles: all-pairs medoid (both orders, as the oracle "
+                      "computes them), 1 DBA iteration, scores; %d cells" % (n, w.n, cells)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-speedup", action="store_true",
+                    help="skip the batched vs one-cycle-per-launch comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2404_12134_amd import synth
+    from paper_2404_12134_amd import wetsand as wts
+
+    wts.load()
+    dev = torch.device("cuda:0")
+    w = synth.make(2)
+    lens = w.lengths
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    mplan = wts.Plan(off, w.d, dt, 0)
+    k0 = int(wts.medoid(mplan, Y, with_matrix=False)[0].item())
+    L = int(lens[k0])
+    plan = wts.Plan(off, w.d, dt, L)
+    n = w.n
+    Ba = torch.empty((L, w.d), dtype=torch.float64, device=dev)
+    Bb = torch.empty_like(Ba)
+    counts = torch.empty(L, dtype=torch.int64, device=dev)
+    dist = torch.empty(n, dtype=torch.float64, device=dev)
+
+    cells_medoid = int(sum(int(lens[a]) * int(lens[b]) for a in range(n) for b in range(a + 1, n)))
+    cells_bary = L * int(lens.sum())
+    iters = w.dba_iters
+    cells_step = cells_medoid + iters * cells_bary + cells_bary
+
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in ("medoid", "dba", "score")}
+    times = {k: [] for k in ev}
+
+    def step(record: bool):
+        e = ev["medoid"]
+        e[0].record()
+        kk, _, _ = wts.medoid(mplan, Y, with_matrix=False)
+        e[1].record()
+        if int(kk.item()) != k0:
+            raise RuntimeError("medoid changed between steps")
+        Bi, _ = wts.init_barycenter(plan, Y, wts.INIT_COPY, k0)
+        Ba.copy_(Bi)
+        src, dst = Ba, Bb
+        ev["dba"][0].record()
+        for _ in range(iters):
+            wts.dba_iterate(plan, src, Y, bary_out=dst, counts=counts, dist=dist)
+            src, dst = dst, src
+        ev["dba"][1].record()
+        ev["score"][0].record()
+        out = wts.anomaly_score(plan, src, Y)
+        ev["score"][1].record()
+        if record:
+            torch.cuda.synchronize()
+            for k, (a, b) in ev.items():
+                times[k].append(a.elapsed_time(b) / 1e3)
+        return out
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for op in (wts.OP_MEDOID, wts.OP_DBA, wts.OP_SCORE):
+        st = wts.device_status(mplan if op == wts.OP_MEDOID else plan, op)
+        if st != 0:
+            raise RuntimeError("device status %d after op %d" % (st, op))
+
+    sec = (t1 - t0) / args.steps
+    value = cells_step / sec / 1e9
+    t_med = float(np.mean(times["medoid"]))
+    t_dba = float(np.mean(times["dba"])) / iters
+    t_score = float(np.mean(times["score"]))
+
+    # roofline of the dominant kernel: the all-pairs DTW value sweep of the medoid
+    ops = cells_medoid * c_min_dist(w.d)
+    achieved = ops / t_med / 1e12
+    peak = VALU_LANE_OPS_PEAK / 1e12
+    traffic = traffic_from_profiles("dtw_fwd_kernel<float,float,3,4,DIST>")
+    roofline = {"bound": "alu", "kernel": "dtw_fwd_kernel (medoid, value sweep)",
+                "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "ops_per_cell": c_min_dist(w.d), "cells_per_launch": cells_medoid,
+                "launch_ms": round(t_med * 1e3, 3)}
+
+    speed = None
+    if not args.no_speedup:
+        # same kernels, one launch per cycle vs one batched launch
+        single = [wts.Plan(off[k:k + 2] - off[k], w.d, dt, L) for k in range(n)]
+        Ys = [Y[int(off[k]):int(off[k + 1])] for k in range(n)]
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for k in range(n):
+            wts.dba_iterate(single[k], Ba, Ys[k])
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        wts.dba_iterate(plan, Ba, Y, bary_out=Bb, counts=counts, dist=dist)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        speed = {"op": "dba_iterate", "one_cycle_per_launch_s": round(tb - ta, 5),
+                 "batched_s": round(tc - tb, 5), "speedup": round((tb - ta) / (tc - tb), 2)}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+
+    line = {
+        "metric": "DTW cell updates/s (GCUPS): medoid init + 10 DBA iterations + anomaly scores",
+        "value": round(value, 3), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name + ": medoid init + %d DBA iterations + anomaly scores" % iters,
+                   "n": n, "d": w.d, "L": L, "cells_per_step": cells_step},
+        "s_per_dba_iteration": round(t_dba, 6),
+        "phase_gcups": {"medoid": round(cells_medoid / t_med / 1e9, 2),
+                        "dba_iteration": round(cells_bary / t_dba / 1e9, 2),
+                        "score": round(cells_bary / t_score / 1e9, 2)},
+        "roofline": roofline,
+        "batched_vs_per_cycle": speed,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()
