@@ -155,7 +155,9 @@ template <typename T>
 T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
 
 int default_grid(const wts_plan* p, const PairSet& ps) {
-  const int g = p->opts.grid > 0 ? p->opts.grid : p->cus * 8;
+  // 24 one-wave workgroups per CU: enough resident waves for the value sweep
+  // (6 per SIMD); the path sweep's register budget caps it lower by itself.
+  const int g = p->opts.grid > 0 ? p->opts.grid : p->cus * 24;
   return std::max(1, std::min(g, ps.n_items));
 }
 

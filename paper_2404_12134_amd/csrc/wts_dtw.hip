@@ -29,8 +29,12 @@ __device__ __forceinline__ double sq_cost(const double (&x)[D], const double (&y
   return s;
 }
 
-constexpr int kChunk = 64;          // sweep steps between two boundary hand-overs
-constexpr int kRing = 2 * kChunk;   // Y columns kept in LDS
+#ifndef WTS_CHUNK
+#define WTS_CHUNK 64
+#endif
+constexpr int kChunk = WTS_CHUNK;   // sweep steps between two boundary hand-overs
+static_assert(kChunk == 32 || kChunk == 64, "chunk must be 32 or 64 steps");
+constexpr int kRing = 128;          // Y columns kept in LDS (>= kChunk + 63, power of 2)
 
 // One wavefront sweeps one strip of one pair.  State per lane: RHO rows of X
 // (float64 registers), the cumulative cost of those rows at the previous
@@ -93,7 +97,7 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
     bool gave_up = false;   // set once a wait times out: the strip never waits again
 
     double yv[D];
-    {
+    if (lane < kChunk) {
       const int j = lane;
 #pragma unroll
       for (int c = 0; c < D; ++c)
@@ -106,7 +110,7 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
     for (int t0 = 0; t0 < Tend; t0 += kChunk) {
       const int tcnt = min(kChunk, Tend - t0);
       const bool more = t0 + kChunk < Tend;
-      if (more) {   // next chunk of Y into registers; stored to LDS after this sweep
+      if (more && lane < kChunk) {   // next chunk of Y into registers; to LDS after this sweep
         const int j = t0 + kChunk + lane;
 #pragma unroll
         for (int c = 0; c < D; ++c)
@@ -127,24 +131,49 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         const int j = t0 + lane;
-        binr[lane] = j < N ? ld_dev(r_row + j) : INF;
-        if (MODE != MODE_DIST) binx[lane] = j < N ? ld_dev(aux_in + j) : 0;
+        if (lane < kChunk) {
+          binr[lane] = j < N ? ld_dev(r_row + j) : INF;
+          if (MODE != MODE_DIST) binx[lane] = j < N ? ld_dev(aux_in + j) : 0;
+        }
       }
       __syncthreads();
 
       // 16 sweep steps; FULL: every lane is inside the grid (no masking)
       auto group16 = [&](auto full_tag, int tb) {
         constexpr bool FULL = decltype(full_tag)::value;
+        // PATH / DIST_LEN sweeps run at low occupancy: keep the bottom row of
+        // 16 steps in registers instead of a lane-masked LDS store per step.
+        constexpr bool kHist = MODE != MODE_DIST;
+        double bhist[kHist ? 16 : 1];
+        int bxhist[kHist ? 16 : 1];
         const int tg = t0 + tb;
+        // LDS operands of step u+1 are read during step u (software pipelining)
+        double yn[D];
+        double bn;
+        int bxn = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) yn[c] = ys[c][(tg - lane) & (kRing - 1)];
+        bn = has_prev ? binr[tb] : INF;
+        if (MODE == MODE_DIST_LEN) bxn = has_prev ? binx[tb] : 0;
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int t = tg + u;
           const int j = t - lane;
-          const double bval = has_prev ? binr[tb + u] : INF;
+          double y[D];
+#pragma unroll
+          for (int c = 0; c < D; ++c) y[c] = yn[c];
+          const double bval = bn;
+          const int bxv = bxn;
+          if (u + 1 < 16) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) yn[c] = ys[c][(j + 1) & (kRing - 1)];
+            bn = has_prev ? binr[tb + u + 1] : INF;
+            if (MODE == MODE_DIST_LEN) bxn = has_prev ? binx[tb + u + 1] : 0;
+          }
           const double upin = shr1_f64(bot, bval);
           int upinx = 0, dgx0 = 0;
           if (MODE == MODE_DIST_LEN) {
-            upinx = shr1_i32(botx, has_prev ? binx[tb + u] : 0);
+            upinx = shr1_i32(botx, bxv);
             dgx0 = upprevx;
           } else if (MODE == MODE_PATH) {
             // top row of the strip (lane 0): entered from above at column j,
@@ -156,9 +185,6 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
           upprev = upin;
           upprevx = upinx;
           if (FULL || (j >= 0 && j < N)) {
-            double y[D];
-#pragma unroll
-            for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
             double dg = dg0, up = upin;
             int dgx = dgx0, upx = upinx;
 #pragma unroll
@@ -193,9 +219,19 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
             bot = left[RHO - 1];
             botx = lx[RHO - 1];
           }
-          if (has_next && lane == kWave - 1 && (FULL || (j >= 0 && j < N))) {
+          if (kHist && FULL) {
+            bhist[u] = bot;
+            if (MODE != MODE_DIST) bxhist[u] = botx;
+          } else if (has_next && lane == kWave - 1 && (FULL || (j >= 0 && j < N))) {
             bor[j & (kRing - 1)] = bot;
             if (MODE != MODE_DIST) box[j & (kRing - 1)] = botx;
+          }
+        }
+        if (kHist && FULL && has_next && lane == kWave - 1) {   // 16 bottom-row cells at once
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            bor[(tg + u - (kWave - 1)) & (kRing - 1)] = bhist[u];
+            if (MODE != MODE_DIST) box[(tg + u - (kWave - 1)) & (kRing - 1)] = bxhist[u];
           }
         }
         if (MODE == MODE_PATH) {
@@ -221,7 +257,7 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
         mem_drain();
         if (lane == 0) st_dev(prog_out, min(N, max(0, jend)));
       }
-      if (more) {
+      if (more && lane < kChunk) {
         const int j = t0 + kChunk + lane;
 #pragma unroll
         for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
