@@ -20,7 +20,10 @@ OBJDIR = os.path.join(HERE, "_build")
 # Per-source extra flags.  The DTW kernels never form a NaN from finite
 # inputs (only +inf boundaries, sums and minima of non-negative values), so
 # -fno-honor-nans lets min() map to a bare v_min_f64.
-SOURCES = {"wts_dtw.hip": ["-fno-honor-nans"], "wts_abi.hip": []}
+# The Soft-DTW kernels never subtract two infinities: every computed cell has
+# at least one finite predecessor, so the same holds there.
+SOURCES = {"wts_dtw.hip": ["-fno-honor-nans"], "wts_soft.hip": ["-fno-honor-nans"],
+           "wts_abi.hip": []}
 ARCH = os.environ.get("WTS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

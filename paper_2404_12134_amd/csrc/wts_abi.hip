@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -44,11 +45,12 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // sweep items and the sizes of the buffers the sweep needs.
 struct PairSet {
   std::vector<PairDesc> pairs;
-  std::vector<int2> items;
+  std::vector<int2> items, items_rev;   // strips ascending / descending within each pair
   PairDesc* d_pairs = nullptr;
   int2* d_items = nullptr;
+  int2* d_items_rev = nullptr;
   int n_pairs = 0, n_items = 0, n_flags = 0;
-  int64_t code_words = 0, bnd_elems = 0, aux_strip_elems = 0;
+  int64_t code_words = 0, bnd_elems = 0, aux_strip_elems = 0, state_elems = 0;
   int64_t max_rows = 0;
 };
 
@@ -64,7 +66,7 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
   });
   ps.pairs.clear();
   ps.items.clear();
-  int64_t code = 0, bnd = 0, aux = 0;
+  int64_t code = 0, bnd = 0, aux = 0, state = 0;
   int flags = 0;
   for (size_t p = 0; p < jobs.size(); ++p) {
     const Job& jb = jobs[p];
@@ -79,13 +81,16 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
     d.code_base = code;
     d.bnd_base = bnd;
     d.aux_base = aux;
+    d.state_base = state;
     d.flag_base = flags;
     d.item_base = (int)ps.items.size();
     code += (int64_t)d.S * d.WT * rho * wts::kWave;
     bnd += jb.N;
     aux += (int64_t)d.S * jb.N;
+    state += (int64_t)d.S * d.WT * (rho + 1) * wts::kWave;
     flags += d.S;
     for (int s = 0; s < d.S; ++s) ps.items.push_back(make_int2((int)p, s));
+    for (int s = d.S - 1; s >= 0; --s) ps.items_rev.push_back(make_int2((int)p, s));
     ps.pairs.push_back(d);
     ps.max_rows = std::max<int64_t>(ps.max_rows, jb.M);
   }
@@ -95,12 +100,14 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
   ps.code_words = code;
   ps.bnd_elems = bnd;
   ps.aux_strip_elems = aux;
+  ps.state_elems = state;
 }
 
 // Workspace: every region 256-byte aligned, in this order.
 struct Layout {
   size_t queue = 0, progress = 0, bnd_r = 0, bnd_aux = 0, codes = 0, out_dist = 0, out_aux = 0;
   size_t seg = 0, seg_len = 0, seg_off = 0, psum = 0, pcnt = 0, dm = 0, totals = 0;
+  size_t rows = 0, states = 0, push_up = 0, push_dg = 0, gsum = 0, hsum = 0;
   size_t total = 0;
 };
 
@@ -115,7 +122,7 @@ struct wts_plan {
   int64_t* d_off = nullptr;
   int64_t* d_path_base = nullptr;
   int2* d_med_ab = nullptr;
-  PairSet bary, med;
+  PairSet bary, med, soft;
   int64_t nmax = 0;
 };
 
@@ -125,7 +132,23 @@ Layout layout(const wts_plan* p, int op) {
   Layout l;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
-  const PairSet& ps = op == WTS_OP_MEDOID ? p->med : p->bary;
+  const PairSet& ps = op == WTS_OP_MEDOID ? p->med
+                      : (op == WTS_OP_SOFT_FWD || op == WTS_OP_SOFT_BWD) ? p->soft : p->bary;
+  if (op == WTS_OP_SOFT_FWD || op == WTS_OP_SOFT_BWD) {
+    l.queue = take(2 * sizeof(int));
+    l.progress = take(sizeof(int) * (size_t)ps.n_flags);
+    if (op == WTS_OP_SOFT_FWD) {
+      l.rows = take(sizeof(double) * (size_t)ps.aux_strip_elems);
+      l.states = take(sizeof(double) * (size_t)ps.state_elems);
+    } else {
+      l.push_up = take(sizeof(double) * (size_t)ps.bnd_elems);
+      l.push_dg = take(sizeof(double) * (size_t)ps.bnd_elems);
+      l.gsum = take(sizeof(double) * (size_t)p->n * (size_t)p->L * (size_t)p->d);
+      l.hsum = take(sizeof(double) * (size_t)p->n * (size_t)p->L);
+    }
+    l.total = o;
+    return l;
+  }
   const bool paths = op == WTS_OP_ALIGN_PATHS || op == WTS_OP_DBA;
   l.queue = take(2 * sizeof(int));   // [0] item counter, [1] status word
   l.progress = take(sizeof(int) * (size_t)ps.n_flags);
@@ -297,6 +320,7 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
     for (int k = 0; k < n; ++k)
       jobs.push_back(Job{0, p->off[k], (int32_t)L, (int32_t)(p->off[k + 1] - p->off[k]), k});
     build_set(p->bary, jobs, p->rho);
+    build_set(p->soft, jobs, wts::kSoftRho);
     std::vector<int64_t> base(n);
     for (int k = 0; k < n; ++k) base[k] = (int64_t)k * (L - 1) + p->off[k];
     hipError_t e;
@@ -322,11 +346,14 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
         return cleanup_fail(e, "hipMemcpy");
     }
   }
-  for (PairSet* ps : {&p->bary, &p->med}) {
+  for (PairSet* ps : {&p->bary, &p->med, &p->soft}) {
     if (ps->pairs.empty()) continue;
     hipError_t e;
     if ((e = hipMalloc(&ps->d_pairs, sizeof(PairDesc) * ps->pairs.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
     if ((e = hipMalloc(&ps->d_items, sizeof(int2) * ps->items.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&ps->d_items_rev, sizeof(int2) * ps->items_rev.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+    if ((e = hipMemcpy(ps->d_items_rev, ps->items_rev.data(), sizeof(int2) * ps->items_rev.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup_fail(e, "hipMemcpy");
     if ((e = hipMemcpy(ps->d_pairs, ps->pairs.data(), sizeof(PairDesc) * ps->pairs.size(), hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup_fail(e, "hipMemcpy");
     if ((e = hipMemcpy(ps->d_items, ps->items.data(), sizeof(int2) * ps->items.size(), hipMemcpyHostToDevice)) != hipSuccess)
@@ -343,9 +370,10 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
 void wts_plan_destroy(wts_plan* p) {
   if (!p) return;
   DeviceGuard g(p->device);
-  for (PairSet* ps : {&p->bary, &p->med}) {
+  for (PairSet* ps : {&p->bary, &p->med, &p->soft}) {
     if (ps->d_pairs) (void)hipFree(ps->d_pairs);
     if (ps->d_items) (void)hipFree(ps->d_items);
+    if (ps->d_items_rev) (void)hipFree(ps->d_items_rev);
   }
   if (p->d_off) (void)hipFree(p->d_off);
   if (p->d_path_base) (void)hipFree(p->d_path_base);
@@ -360,6 +388,8 @@ size_t wts_workspace_bytes(const wts_plan* p, int op) {
     case WTS_OP_ALIGN_PATHS:
     case WTS_OP_DBA:
     case WTS_OP_SCORE:
+    case WTS_OP_SOFT_FWD:
+    case WTS_OP_SOFT_BWD:
       return p->L > 0 ? layout(p, op).total : 0;
     case WTS_OP_MEDOID:
       return p->L == 0 ? layout(p, op).total : 0;
@@ -445,21 +475,77 @@ wts_status wts_anomaly_score(const wts_plan* p, const double* bary, const void* 
   return WTS_OK;
 }
 
-wts_status wts_softdtw_forward(const wts_plan* p, const double*, const void*, double gamma,
-                               double*, void*, size_t, void*) {
+wts_status wts_softdtw_forward(const wts_plan* p, const double* bary, const void* cycles,
+                               double gamma, double* value, void* ckpt, size_t ckpt_bytes,
+                               void* stream) {
   wts_status rc = check_bary_plan(p);
   if (rc != WTS_OK) return rc;
-  if (!(gamma > 0)) return fail(WTS_E_ARG, "gamma must be > 0");
-  return fail(WTS_E_UNSUPPORTED, "Soft-DTW forward is not built yet");
+  if (!bary || !cycles || !value) return fail(WTS_E_ARG, "null bary/cycles/value");
+  if (!(gamma > 0) || !(gamma < INFINITY)) return fail(WTS_E_ARG, "gamma must be finite and > 0");
+  if ((rc = check_ws(p, WTS_OP_SOFT_FWD, ckpt, ckpt_bytes)) != WTS_OK) return rc;
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout l = layout(p, WTS_OP_SOFT_FWD);
+  const PairSet& ps = p->soft;
+  HIP_TRY(wts::launch_zero(at<int>(ckpt, l.queue), 2, st));
+  HIP_TRY(wts::launch_zero(at<int>(ckpt, l.progress), ps.n_flags, st));
+  wts::SoftArgs a{};
+  a.pairs = ps.d_pairs;
+  a.items = ps.d_items;
+  a.n_items = ps.n_items;
+  a.queue = at<int>(ckpt, l.queue);
+  a.status = at<int>(ckpt, l.queue) + 1;
+  a.progress = at<int>(ckpt, l.progress);
+  a.x = bary;
+  a.y = cycles;
+  a.rows = at<double>(ckpt, l.rows);
+  a.states = at<double>(ckpt, l.states);
+  a.kscale = 1.0 / (gamma * 0.69314718055994530942);
+  a.value = value;
+  a.L = p->L;
+  HIP_TRY(wts::launch_soft(p->d, p->dtype, false, a, default_grid(p, ps), st));
+  return WTS_OK;
 }
 
-wts_status wts_softdtw_backward(const wts_plan* p, const double*, const void*, double gamma,
-                                const void*, size_t, const double*, double*, double*, void*,
-                                size_t, void*) {
+wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const void* cycles,
+                                double gamma, const void* ckpt, size_t ckpt_bytes,
+                                const double* grad_value, double* grad_bary, double* row_mass,
+                                void* ws, size_t ws_bytes, void* stream) {
   wts_status rc = check_bary_plan(p);
   if (rc != WTS_OK) return rc;
-  if (!(gamma > 0)) return fail(WTS_E_ARG, "gamma must be > 0");
-  return fail(WTS_E_UNSUPPORTED, "Soft-DTW backward is not built yet");
+  if (!bary || !cycles || !grad_bary) return fail(WTS_E_ARG, "null bary/cycles/grad_bary");
+  if (!(gamma > 0) || !(gamma < INFINITY)) return fail(WTS_E_ARG, "gamma must be finite and > 0");
+  if ((rc = check_ws(p, WTS_OP_SOFT_FWD, const_cast<void*>(ckpt), ckpt_bytes)) != WTS_OK) return rc;
+  if ((rc = check_ws(p, WTS_OP_SOFT_BWD, ws, ws_bytes)) != WTS_OK) return rc;
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout lc = layout(p, WTS_OP_SOFT_FWD);
+  const Layout l = layout(p, WTS_OP_SOFT_BWD);
+  const PairSet& ps = p->soft;
+  void* ck = const_cast<void*>(ckpt);
+  HIP_TRY(wts::launch_zero(at<int>(ws, l.queue), 2, st));
+  HIP_TRY(wts::launch_zero(at<int>(ws, l.progress), ps.n_flags, st));
+  wts::SoftArgs a{};
+  a.pairs = ps.d_pairs;
+  a.items = ps.d_items_rev;
+  a.n_items = ps.n_items;
+  a.queue = at<int>(ws, l.queue);
+  a.status = at<int>(ws, l.queue) + 1;
+  a.progress = at<int>(ws, l.progress);
+  a.x = bary;
+  a.y = cycles;
+  a.rows = at<double>(ck, lc.rows);
+  a.states = at<double>(ck, lc.states);
+  a.kscale = 1.0 / (gamma * 0.69314718055994530942);
+  a.push_up = at<double>(ws, l.push_up);
+  a.push_dg = at<double>(ws, l.push_dg);
+  a.gsum = at<double>(ws, l.gsum);
+  a.hsum = at<double>(ws, l.hsum);
+  a.L = p->L;
+  HIP_TRY(wts::launch_soft(p->d, p->dtype, true, a, default_grid(p, ps), st));
+  HIP_TRY(wts::launch_soft_reduce(a.gsum, a.hsum, grad_value, p->n, p->L, p->d, grad_bary,
+                                  row_mass, st));
+  return WTS_OK;
 }
 
 wts_status wts_medoid(const wts_plan* p, const void* cycles, double* dist_matrix, double* totals,

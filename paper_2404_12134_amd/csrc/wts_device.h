@@ -38,8 +38,13 @@ struct PairDesc {
   int32_t WT;         // code words per (strip, row, lane): ceil((N + 63) / 16) rounded
   int32_t item_base;  // index of this pair's strip 0 in the item list
   int32_t pad;
-  int64_t aux_base;   // first element of this pair's per-strip boundary tags (S * N)
+  int64_t aux_base;   // first element of this pair's per-strip rows (S * N)
+  int64_t state_base; // first double of this pair's Soft-DTW sweep states
 };
+
+// Rows per lane of the Soft-DTW sweeps (the backward keeps 3 weights per cell
+// for 16 steps in registers).
+constexpr int kSoftRho = 2;
 
 enum Mode { MODE_DIST = 0, MODE_DIST_LEN = 1, MODE_PATH = 2 };
 
@@ -59,6 +64,26 @@ struct FwdArgs {
   int* out_aux;          // [pair slot] |pi| (DIST_LEN) or entry code of (M-1, N-1) (PATH)
   int aux_per_strip;     // 1: bnd_aux keeps every strip's bottom row (PATH)
   int cost_kind;         // 0 squared, 1 Euclidean (sqrt)
+};
+
+struct SoftArgs {
+  const PairDesc* pairs;
+  const int2* items;     // (pair, strip); strips descending within a pair for the backward
+  int n_items;
+  int* queue;
+  int* status;
+  int* progress;
+  const double* x;       // barycenter [L][d]
+  const void* y;         // cycle values
+  double* rows;          // bottom row of every strip, scaled units (S * N per pair)
+  double* states;        // sweep state every 16 steps (RHO + 1 values per lane)
+  double kscale;         // log2(e) / gamma
+  double* value;         // [n] Soft-DTW values (forward)
+  double* push_up;       // rolling top-row pushes between strips (backward)
+  double* push_dg;
+  double* gsum;          // [n][L][d] per-cycle gradient rows
+  double* hsum;          // [n][L] per-cycle row mass
+  int64_t L;
 };
 
 __device__ __forceinline__ double inf_d() { return __builtin_huge_val(); }

@@ -38,6 +38,9 @@ hipError_t launch_score(const double* dist, const int* len, int n, double* score
                         int64_t* path_len, hipStream_t st);
 hipError_t launch_medoid(const double* pair_dist, const int2* pair_ab, int n_pairs, int n,
                          double* Dm, double* totals, int32_t* medoid, hipStream_t st);
+hipError_t launch_soft(int d, int ydtype, bool bwd, const SoftArgs& a, int grid, hipStream_t st);
+hipError_t launch_soft_reduce(const double* gsum, const double* hsum, const double* w, int n,
+                              int64_t L, int d, double* grad, double* mass, hipStream_t st);
 hipError_t launch_init(int ydtype, const void* Y, const int64_t* off, int n, int d, int src,
                        int64_t Nsrc, int64_t L, int euclid, double* out, hipStream_t st);
 

@@ -1,0 +1,524 @@
+// wts_soft.hip -- Soft-DTW forward (Eq. 3-5) and its gradient (Eq. 6) for gfx950.
+//
+// Units.  The cumulative costs are kept scaled, R' = R * k with
+// k = log2(e) / gamma, so the soft-min of Eq. 3 becomes
+//   min'(a, b, c) = m - log2(2^(m-a) + 2^(m-b) + 2^(m-c)),  m = min(a, b, c),
+// evaluated with float64 differences and the hardware base-2 exponential and
+// logarithm (v_exp_f32 / v_log_f32); every cost delta enters as delta * k.
+// The Soft-DTW value is r'(M-1, N-1) / k.
+//
+// Forward.  Same skewed wavefront sweep as the DTW kernels (one wave per strip
+// of 64*RHO rows, strips of a pair chained through device memory).  It keeps
+// every strip's bottom row and, every 16 sweep steps, the sweep state of each
+// lane (its RHO cumulative costs at the previous column and the diagonal
+// input from the row above): enough to replay any 16-step tile.
+//
+// Backward.  E of Eq. 6 follows from Eq. 5 by the chain rule:
+//   e(i, j) = sum over the successors s of (i, j) of e(s) * w_s(i, j),
+// where w_s(i, j) = 2^(m_s - r'(i, j)) / sum_s is the normalised weight of
+// (i, j) in the soft-min of its successor s, and e(M-1, N-1) = 1 (the cell
+// that closes the path).  The kernel walks each strip's tiles from the last
+// column to the first: it replays the tile forward, keeping the three weights
+// of every cell in registers (float32), then sweeps the tile backwards in
+// "push" form -- each finished cell splits its e into its three predecessors
+// with its own weights -- so no cell ever needs a neighbour's weights.  The
+// pushes of a strip's top row feed the strip above, so strips are pipelined
+// from the bottom up.  Per row l of the barycenter the kernel accumulates
+// sum_j e(l, j) and sum_j e(l, j) y_j, and the gradient is
+//   d Soft-DTW / d b_l = 2 (b_l * sum_j e(l, j) - sum_j e(l, j) y_j).
+#include <type_traits>
+
+#include "wts_device.h"
+#include "wts_kernels.h"
+
+namespace wts {
+
+namespace {
+
+template <int D>
+__device__ __forceinline__ double sq_cost(const double (&x)[D], const double (&y)[D]) {
+  double e = x[0] - y[0];
+  double s = e * e;
+#pragma unroll
+  for (int c = 1; c < D; ++c) {
+    e = x[c] - y[c];
+    s = __builtin_fma(e, e, s);
+  }
+  return s;
+}
+
+__device__ __forceinline__ double shl1_f64(double v, double old) {
+  // DPP wave_shl:1 -- lane k receives v from lane k+1; lane 63 receives `old`.
+  const long long s = __double_as_longlong(v), o = __double_as_longlong(old);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x130, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+constexpr int kRing = 128;   // Y columns in LDS (>= 16 + 63 for a tile, power of 2)
+constexpr int kTile = 16;    // sweep steps per checkpoint / replay tile
+
+// Soft-min of the three predecessors in scaled units.  Returns the soft-min
+// value and the three (unnormalised) base-2 exponentials.
+struct SoftMin {
+  double v;
+  float ed, eu, el, s;
+};
+__device__ __forceinline__ SoftMin softmin3(double dg, double up, double lf) {
+  const double m = __builtin_fmin(__builtin_fmin(dg, up), lf);
+  SoftMin o;
+  o.ed = __builtin_amdgcn_exp2f((float)(m - dg));
+  o.eu = __builtin_amdgcn_exp2f((float)(m - up));
+  o.el = __builtin_amdgcn_exp2f((float)(m - lf));
+  o.s = (o.ed + o.eu) + o.el;
+  o.v = m - (double)__builtin_amdgcn_logf(o.s);
+  return o;
+}
+
+// --------------------------------------------------------------- forward
+
+template <typename TY, int D, int RHO>
+__global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
+  constexpr int H = kWave * RHO;
+  constexpr int kChunk = 64;
+  __shared__ double ys[D][kRing];
+  __shared__ double binr[kChunk];
+  __shared__ double bor[kRing];
+  __shared__ int s_item;
+  const int lane = threadIdx.x;
+  const TY* __restrict__ Y = static_cast<const TY*>(a.y);
+  const double INF = inf_d();
+  const double k = a.kscale;
+
+  for (;;) {
+    if (lane == 0) s_item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= a.n_items) break;
+    const int2 it = a.items[item];
+    const PairDesc pd = a.pairs[it.x];
+    const int s = it.y;
+    const int M = pd.M, N = pd.N;
+    const int i0 = s * H;
+    const int ib = i0 + lane * RHO;
+    const bool has_prev = s > 0;
+    const bool has_next = s + 1 < pd.S;
+    const int Tend = pd.WT * 16;
+    const double* row_in = a.rows + pd.aux_base + (int64_t)(s - 1) * N;
+    double* row_out = a.rows + pd.aux_base + (int64_t)s * N;
+    double* st = a.states + pd.state_base + (int64_t)s * pd.WT * (RHO + 1) * kWave;
+    int* prog_in = a.progress + pd.flag_base + s - 1;
+    int* prog_out = a.progress + pd.flag_base + s;
+
+    double xr[RHO][D];
+#pragma unroll
+    for (int r = 0; r < RHO; ++r)
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        xr[r][c] = (ib + r < M) ? a.x[(int64_t)(ib + r) * D + c] : 0.0;
+    double left[RHO];
+#pragma unroll
+    for (int r = 0; r < RHO; ++r) left[r] = INF;
+    double upprev = (s == 0 && lane == 0) ? 0.0 : INF;
+    double bot = INF;
+    bool gave_up = false;
+
+    double yv[D];
+    {
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        yv[c] = lane < N ? static_cast<double>(Y[(pd.y_off + lane) * D + c]) : 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) ys[c][lane] = yv[c];
+    }
+    __syncthreads();
+
+    for (int t0 = 0; t0 < Tend; t0 += kChunk) {
+      const int tcnt = min(kChunk, Tend - t0);
+      const bool more = t0 + kChunk < Tend;
+      if (more) {
+        const int j = t0 + kChunk + lane;
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          yv[c] = j < N ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0;
+      }
+      if (has_prev) {
+        const int need = min(N, t0 + kChunk);
+        if (lane == 0 && !gave_up) {
+          int polls = 0;
+          while (ld_dev(prog_in) < need) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > kSpinLimit) {
+              atomicOr(a.status, kStatusSpinTimeout);
+              gave_up = true;
+              break;
+            }
+          }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int j = t0 + lane;
+        binr[lane] = j < N ? ld_dev(row_in + j) : INF;
+      }
+      __syncthreads();
+
+      auto group16 = [&](auto full_tag, int tb) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        const int tg = t0 + tb;
+        {   // checkpoint: the sweep state at the start of these 16 steps
+          double* p = st + (int64_t)(tg >> 4) * (RHO + 1) * kWave + lane;
+#pragma unroll
+          for (int r = 0; r < RHO; ++r) p[r * kWave] = left[r];
+          p[RHO * kWave] = upprev;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int t = tg + u;
+          const int j = t - lane;
+          const double bval = has_prev ? binr[tb + u] : INF;
+          const double upin = shr1_f64(bot, bval);
+          const double dg0 = upprev;
+          upprev = upin;
+          if (FULL || (j >= 0 && j < N)) {
+            double y[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
+            double dg = dg0, up = upin;
+#pragma unroll
+            for (int r = 0; r < RHO; ++r) {
+              const double lf = left[r];
+              const SoftMin sm = softmin3(dg, up, lf);
+              const double rv = sq_cost<D>(xr[r], y) * k + sm.v;
+              dg = lf;
+              up = rv;
+              left[r] = rv;
+            }
+            bot = left[RHO - 1];
+            if (has_next && lane == kWave - 1) bor[j & (kRing - 1)] = bot;
+          }
+        }
+      };
+      for (int tb = 0; tb < tcnt; tb += 16) {
+        const int tg = t0 + tb;
+        if (tg >= kWave - 1 && tg + 16 <= N) group16(std::true_type{}, tb);
+        else group16(std::false_type{}, tb);
+      }
+      __syncthreads();
+      if (has_next) {
+        const int jend = t0 + tcnt - (kWave - 1);
+        const int j = t0 - (kWave - 1) + lane;
+        if (j >= 0 && j < N && j < jend) st_dev(row_out + j, bor[j & (kRing - 1)]);
+        mem_drain();
+        if (lane == 0) st_dev(prog_out, min(N, max(0, jend)));
+      }
+      if (more) {
+        const int j = t0 + kChunk + lane;
+#pragma unroll
+        for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
+      }
+      __syncthreads();
+    }
+    if (ib <= M - 1 && M - 1 < ib + RHO) {
+      const int rl = M - 1 - ib;
+      double v = left[0];
+#pragma unroll
+      for (int r = 1; r < RHO; ++r)
+        if (r == rl) v = left[r];
+      a.value[pd.out] = v / k;
+    }
+    __syncthreads();
+  }
+}
+
+// -------------------------------------------------------------- backward
+
+template <typename TY, int D, int RHO>
+__global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
+  constexpr int H = kWave * RHO;
+  __shared__ double ys[D][kRing];
+  __shared__ double bin_fwd[kTile];        // lane 0's upper input for the replay
+  __shared__ double bin_up[kTile];         // lane 63's pushes from the strip below
+  __shared__ double bin_dg[kTile];
+  __shared__ double bout_up[kTile];        // lane 0's pushes for the strip above
+  __shared__ double bout_dg[kTile];
+  __shared__ int s_item;
+  const int lane = threadIdx.x;
+  const TY* __restrict__ Y = static_cast<const TY*>(a.y);
+  const double INF = inf_d();
+  const double k = a.kscale;
+
+  for (;;) {
+    if (lane == 0) s_item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= a.n_items) break;
+    const int2 it = a.items[item];
+    const PairDesc pd = a.pairs[it.x];
+    const int s = it.y;
+    const int M = pd.M, N = pd.N;
+    const int i0 = s * H;
+    const int ib = i0 + lane * RHO;
+    const bool has_above = s > 0;            // a strip above consumes our top-row pushes
+    const bool has_below = s + 1 < pd.S;     // the strip below feeds our bottom row
+    const int G = pd.WT;                     // 16-step tiles
+    const double* row_fwd = a.rows + pd.aux_base + (int64_t)(s - 1) * N;
+    const double* st = a.states + pd.state_base + (int64_t)s * G * (RHO + 1) * kWave;
+    // rolling push rows: the strip below wrote them for us, we overwrite them
+    // for the strip above after reading
+    double* pu_row = a.push_up + pd.bnd_base;
+    double* pd_row = a.push_dg + pd.bnd_base;
+    int* prog_below = a.progress + pd.flag_base + s + 1;
+    int* prog_self = a.progress + pd.flag_base + s;
+    // the cell that closes the path, (M-1, N-1), receives e = 1
+    const bool last = s + 1 == pd.S;
+    const int k_last = (M - 1 - i0) / RHO;
+    const int r_last = (M - 1 - i0) - k_last * RHO;
+    const int t_inj = last ? N - 1 + k_last : -1;
+
+    double xr[RHO][D];
+#pragma unroll
+    for (int r = 0; r < RHO; ++r)
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        xr[r][c] = (ib + r < M) ? a.x[(int64_t)(ib + r) * D + c] : 0.0;
+
+    double acc_e[RHO], acc_ey[RHO][D];
+    double pl[RHO], pdg[RHO];                 // pending left / diagonal pushes into each row
+#pragma unroll
+    for (int r = 0; r < RHO; ++r) {
+      acc_e[r] = 0.0;
+      pl[r] = 0.0;
+      pdg[r] = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc_ey[r][c] = 0.0;
+    }
+    double up0 = 0.0, dg0 = 0.0;              // this lane's row-0 pushes, sent up next step
+    double recv_dg = 0.0;                     // diagonal push received last step
+    bool gave_up = false;
+
+    // Y columns of the last tile
+    {
+      const int jlo = 16 * (G - 1) - (kWave - 1);
+      for (int q = lane; q < 16 + kWave - 1; q += kWave) {
+        const int j = jlo + q;
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          ys[c][j & (kRing - 1)] = (j >= 0 && j < N) ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0;
+      }
+    }
+
+    for (int g = G - 1; g >= 0; --g) {
+      const int tg = 16 * g;
+      // next tile's 16 new Y columns, stored after this tile
+      double yv[D];
+      const int jn = tg - 16 - (kWave - 1) + lane;
+      if (g > 0 && lane < 16) {
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          yv[c] = (jn >= 0 && jn < N) ? static_cast<double>(Y[(pd.y_off + jn) * D + c]) : 0.0;
+      }
+      // lane 0's upper input for the replay (bottom row of the strip above)
+      if (lane < kTile) {
+        const int j = tg + lane;
+        bin_fwd[lane] = (has_above && j < N) ? row_fwd[j] : INF;
+      }
+      // lane 63's inputs: pushes of the strip below's top row at columns tg-63 ..
+      if (has_below) {
+        const int jlo = max(0, tg - (kWave - 1));
+        const int need = N - jlo;            // columns >= jlo published
+        if (lane == 0 && !gave_up && need > 0) {
+          int polls = 0;
+          while (ld_dev(prog_below) < need) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++polls > kSpinLimit) {
+              atomicOr(a.status, kStatusSpinTimeout);
+              gave_up = true;
+              break;
+            }
+          }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (lane < kTile) {
+          const int j = tg - (kWave - 1) + lane;
+          const bool in = j >= 0 && j < N;
+          bin_up[lane] = in ? ld_dev(pu_row + j) : 0.0;
+          bin_dg[lane] = in ? ld_dev(pd_row + j) : 0.0;
+        }
+      } else if (lane < kTile) {
+        bin_up[lane] = 0.0;
+        bin_dg[lane] = 0.0;
+      }
+      __syncthreads();
+
+      // ---- replay the tile forward, keeping the soft-min weights
+      double left[RHO];
+#pragma unroll
+      for (int r = 0; r < RHO; ++r) left[r] = st[((int64_t)g * (RHO + 1) + r) * kWave + lane];
+      double upprev = st[((int64_t)g * (RHO + 1) + RHO) * kWave + lane];
+      double bot = left[RHO - 1];
+      float wd[16][RHO], wu[16][RHO], wl[16][RHO];
+      const bool full = tg >= kWave - 1 && tg + 16 <= N;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int t = tg + u;
+        const int j = t - lane;
+        const double upin = shr1_f64(bot, bin_fwd[u]);
+        const double dgi = upprev;
+        upprev = upin;
+        if (full || (j >= 0 && j < N)) {
+          double y[D];
+#pragma unroll
+          for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
+          double dg = dgi, up = upin;
+#pragma unroll
+          for (int r = 0; r < RHO; ++r) {
+            const double lf = left[r];
+            const SoftMin sm = softmin3(dg, up, lf);
+            const double rv = sq_cost<D>(xr[r], y) * k + sm.v;
+            const float inv = __builtin_amdgcn_rcpf(sm.s);
+            wd[u][r] = sm.ed * inv;
+            wu[u][r] = sm.eu * inv;
+            wl[u][r] = sm.el * inv;
+            dg = lf;
+            up = rv;
+            left[r] = rv;
+          }
+          bot = left[RHO - 1];
+        }
+      }
+
+      // ---- backward over the tile
+#pragma unroll
+      for (int u = 15; u >= 0; --u) {
+        const int t = tg + u;
+        const int j = t - lane;
+        // pushes of the lane below (rows i+1): its up push for column j now,
+        // its diagonal push for column j-1 next step
+        const double recv_up = shl1_f64(up0, bin_up[u]);
+        const double recv_dg_next = shl1_f64(dg0, bin_dg[u]);
+        if (full || (j >= 0 && j < N)) {
+          double y[D];
+#pragma unroll
+          for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
+          double below_up = recv_up;         // push up from (i+1, j)
+          double new_pdg[RHO];
+#pragma unroll
+          for (int r = RHO - 1; r >= 0; --r) {
+            const double din = (r == RHO - 1) ? recv_dg : pdg[r];
+            double e = (below_up + pl[r]) + din;
+            if (t == t_inj && lane == k_last && r == r_last) e += 1.0;
+            below_up = e * (double)wu[u][r];
+            pl[r] = e * (double)wl[u][r];
+            const double dpush = e * (double)wd[u][r];
+            if (r > 0) new_pdg[r - 1] = dpush;
+            else dg0 = dpush;
+            acc_e[r] += e;
+#pragma unroll
+            for (int c = 0; c < D; ++c) acc_ey[r][c] = __builtin_fma(e, y[c], acc_ey[r][c]);
+          }
+          up0 = below_up;
+#pragma unroll
+          for (int r = 0; r + 1 < RHO; ++r) pdg[r] = new_pdg[r];
+          if (lane == 0 && has_above) {
+            bout_up[u] = up0;
+            bout_dg[u] = dg0;
+          }
+        } else if (lane == 0 && has_above) {
+          bout_up[u] = 0.0;
+          bout_dg[u] = 0.0;
+        }
+        recv_dg = recv_dg_next;
+      }
+      __syncthreads();
+      if (has_above) {   // publish the top row's pushes for columns tg .. tg+15
+        if (lane < kTile) {
+          const int j = tg + lane;
+          if (j < N) {
+            st_dev(pu_row + j, bout_up[lane]);
+            st_dev(pd_row + j, bout_dg[lane]);
+          }
+        }
+        mem_drain();
+        if (lane == 0) st_dev(prog_self, N - min(N, tg));
+      }
+      if (g > 0 && lane < 16) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) ys[c][jn & (kRing - 1)] = yv[c];
+      }
+      __syncthreads();
+    }
+    // per-row sums of this cycle: gradient 2 (b sum_j e - sum_j e y_j) and mass
+#pragma unroll
+    for (int r = 0; r < RHO; ++r) {
+      const int i = ib + r;
+      if (i < M) {
+        const int64_t o = (int64_t)pd.out * a.L + i;
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+          a.gsum[o * D + c] = 2.0 * (xr[r][c] * acc_e[r] - acc_ey[r][c]);
+        a.hsum[o] = acc_e[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// G_l = sum_k w_k * grad_k(l), h_l = sum_k w_k * mass_k(l), ascending k.
+__global__ void soft_reduce_kernel(const double* __restrict__ gsum, const double* __restrict__ hsum,
+                                   const double* __restrict__ w, int n, int64_t L, int d,
+                                   double* __restrict__ grad, double* __restrict__ mass) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= L * d) return;
+  const int64_t l = idx / d;
+  const int c = (int)(idx - l * d);
+  double g = 0.0;
+  for (int p = 0; p < n; ++p) g = g + (w ? w[p] : 1.0) * gsum[((int64_t)p * L + l) * d + c];
+  grad[idx] = g;
+  if (c == 0 && mass) {
+    double h = 0.0;
+    for (int p = 0; p < n; ++p) h = h + (w ? w[p] : 1.0) * hsum[(int64_t)p * L + l];
+    mass[l] = h;
+  }
+}
+
+}  // namespace
+
+#define WTS_SOFT_D_SWITCH(d, CALL) \
+  switch (d) {                     \
+    case 1: return CALL(1);        \
+    case 2: return CALL(2);        \
+    case 3: return CALL(3);        \
+    case 4: return CALL(4);        \
+    case 5: return CALL(5);        \
+    case 6: return CALL(6);        \
+    case 7: return CALL(7);        \
+    case 8: return CALL(8);        \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <typename TY, int D>
+static hipError_t launch_soft_t(bool bwd, const SoftArgs& a, int grid, hipStream_t st) {
+  if (bwd)
+    hipLaunchKernelGGL((soft_bwd_kernel<TY, D, kSoftRho>), dim3(grid), dim3(kWave), 0, st, a);
+  else
+    hipLaunchKernelGGL((soft_fwd_kernel<TY, D, kSoftRho>), dim3(grid), dim3(kWave), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_soft(int d, int ydtype, bool bwd, const SoftArgs& a, int grid, hipStream_t st) {
+#define CALLS(D) (ydtype == 0 ? launch_soft_t<float, D>(bwd, a, grid, st) \
+                              : launch_soft_t<double, D>(bwd, a, grid, st))
+  WTS_SOFT_D_SWITCH(d, CALLS)
+#undef CALLS
+}
+
+hipError_t launch_soft_reduce(const double* gsum, const double* hsum, const double* w, int n,
+                              int64_t L, int d, double* grad, double* mass, hipStream_t st) {
+  const int64_t tot = L * d;
+  hipLaunchKernelGGL(soft_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     gsum, hsum, w, n, L, d, grad, mass);
+  return hipGetLastError();
+}
+
+}  // namespace wts

@@ -244,3 +244,53 @@ def init_barycenter(plan: Plan, cycles: torch.Tensor, kind: int, index: int = 0)
     _check(load().wts_init_barycenter(plan.handle, _ptr(cycles), int(kind), int(index), _ptr(out),
                                       ctypes.byref(chosen), _stream()))
     return out, int(chosen.value)
+
+
+def softdtw_forward(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, gamma: float):
+    """Eq. 3-5: (values [n] f64, checkpoint buffer for softdtw_backward)."""
+    value = torch.empty(plan.n, dtype=torch.float64, device=_dev(plan))
+    nbytes = plan.workspace_bytes(OP_SOFT_FWD)
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=_dev(plan))
+    shift = (-raw.data_ptr()) % 256
+    ckpt = raw[shift:shift + nbytes]
+    ckpt._wts_base = raw   # keep the allocation alive with the view
+    _check(load().wts_softdtw_forward(plan.handle, _ptr(bary), _ptr(cycles), float(gamma),
+                                      _ptr(value), _ptr(ckpt), ckpt.numel(), _stream()))
+    return value, ckpt
+
+
+def softdtw_backward(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, gamma: float,
+                     ckpt: torch.Tensor, grad_value: Optional[torch.Tensor] = None,
+                     with_mass: bool = False):
+    """Eq. 6-7: grad_bary [L][d] = sum_k grad_value_k dSoft-DTW_k/dB (and row mass)."""
+    grad = torch.empty((plan.L, plan.d), dtype=torch.float64, device=_dev(plan))
+    mass = torch.empty(plan.L, dtype=torch.float64, device=_dev(plan)) if with_mass else None
+    ws = plan.workspace(OP_SOFT_BWD)
+    gv = None if grad_value is None else grad_value.to(torch.float64).contiguous()
+    _check(load().wts_softdtw_backward(plan.handle, _ptr(bary), _ptr(cycles), float(gamma),
+                                       _ptr(ckpt), ckpt.numel(), _ptr(gv), _ptr(grad),
+                                       _ptr(mass), _ptr(ws), ws.numel(), _stream()))
+    return (grad, mass) if with_mass else grad
+
+
+class SoftDTW(torch.autograd.Function):
+    """values[k] = Soft-DTW^gamma(B, C_k) with the hand-written E-matrix backward.
+
+    Usage: SoftDTW.apply(bary, plan, cycles, gamma) with bary a float64 [L][d]
+    tensor; the checkpoints of the forward are kept for the backward."""
+
+    @staticmethod
+    def forward(ctx, bary, plan, cycles, gamma):
+        bary_c = bary.detach().contiguous()
+        value, ckpt = softdtw_forward(plan, bary_c, cycles, gamma)
+        ctx.plan, ctx.cycles, ctx.gamma, ctx.ckpt = plan, cycles, gamma, ckpt
+        ctx.save_for_backward(bary_c)
+        return value
+
+    @staticmethod
+    def backward(ctx, grad_value):
+        (bary_c,) = ctx.saved_tensors
+        grad = softdtw_backward(ctx.plan, bary_c, ctx.cycles, ctx.gamma, ctx.ckpt,
+                                grad_value.contiguous())
+        ctx.ckpt = None
+        return grad, None, None, None

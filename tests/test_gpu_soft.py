@@ -1,0 +1,140 @@
+"""GPU parity of Soft-DTW forward and backward (Eq. 3-7) against the FP64 oracle.
+
+Soft-DTW uses float32 base-2 exponentials/logarithms on float64 differences,
+so it is not bit-exact: scalars must satisfy |a - b| <= 1e-4 |b| and vectors
+both |a_k - b_k| <= 1e-4 max(|b_k|, 1e-2 ||b||_inf) per element and
+||a - b||_2 <= 1e-4 ||b||_2 (the benchmark spec's 1e-4 relative bar).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_12134_amd import synth
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def check_vec(a, b, rtol=RTOL):
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    scale = np.maximum(np.abs(b), 1e-2 * np.abs(b).max())
+    assert (np.abs(a - b) <= rtol * scale).all(), np.max(np.abs(a - b) / scale)
+    assert np.linalg.norm(a - b) <= rtol * np.linalg.norm(b)
+
+
+def setup(wts, B, cycles, dtype=None):
+    import torch
+    Y, off, dt = wts.pack_cycles(cycles, dtype=dtype)
+    plan = wts.Plan(off, B.shape[1], dt, B.shape[0])
+    return plan, torch.from_numpy(np.ascontiguousarray(B, dtype=np.float64)).cuda(), Y
+
+
+SHAPES = [(1, [1, 7]), (5, [1, 64, 130]), (127, [128, 129]), (129, [300, 1]),
+          (300, [257, 64, 500])]
+
+
+@pytest.mark.parametrize("gamma", [0.1, 1.0])
+@pytest.mark.parametrize("d", [1, 3, 6])
+@pytest.mark.parametrize("L,lens", SHAPES)
+def test_soft_forward_and_gradient(wts, gamma, d, L, lens):
+    import torch
+    r = rng(L * 7 + d)
+    B = r.standard_normal((L, d))
+    cyc = [r.standard_normal((N, d)).astype(np.float32) for N in lens]
+    w = r.uniform(0.5, 2.0, len(cyc))
+    plan, Bt, Y = setup(wts, B, cyc)
+    say("case soft d=%d L=%d lens=%s gamma=%g" % (d, L, lens, gamma))
+    val, ckpt = wts.softdtw_forward(plan, Bt, Y, gamma)
+    grad, mass = wts.softdtw_backward(plan, Bt, Y, gamma, ckpt,
+                                      torch.from_numpy(w).cuda(), with_mass=True)
+    torch.cuda.synchronize()
+    assert wts.device_status(plan, wts.OP_SOFT_BWD) == 0
+    ov, og, oh = oracle.softdtw_batch(B, [c.astype(np.float64) for c in cyc], gamma, w)
+    check_vec(val.cpu().numpy(), ov)
+    check_vec(grad.cpu().numpy(), og)
+    check_vec(mass.cpu().numpy(), oh)
+
+
+def test_soft_config4_shaped(wts):
+    # the C4 recipe at reduced size: 6 channels, Euclidean-mean barycenter
+    import torch
+    w = synth.make(4, n=4, len_range=(900, 1100), L=1000)
+    cyc64 = [c.astype(np.float64) for c in w.cycles]
+    B = oracle.euclid_mean(cyc64, 1000)
+    plan, Bt, Y = setup(wts, B, w.cycles)
+    for gamma in w.gammas:
+        say("case soft c4-shaped gamma=%g" % gamma)
+        val, ckpt = wts.softdtw_forward(plan, Bt, Y, gamma)
+        wv = np.array([1.0 / c.shape[0] for c in w.cycles])   # Eq. 7: lambda_k / m_k
+        grad, mass = wts.softdtw_backward(plan, Bt, Y, gamma, ckpt, torch.from_numpy(wv).cuda(),
+                                          with_mass=True)
+        ov, og, oh = oracle.softdtw_batch(B, cyc64, gamma, wv)
+        check_vec(val.cpu().numpy(), ov)
+        check_vec(grad.cpu().numpy(), og)
+        check_vec(mass.cpu().numpy(), oh)
+
+
+def test_soft_limits_match_dtw(wts):
+    # single-row series: Soft-DTW equals the sum of costs; tiny gamma -> DTW
+    import torch
+    r = rng(3)
+    b, Y1 = r.standard_normal((1, 2)), r.standard_normal((40, 2))
+    plan, Bt, Y = setup(wts, b, [Y1], dtype="f64")
+    val, _ = wts.softdtw_forward(plan, Bt, Y, 0.5)
+    d0, _, _, _ = oracle.dtw(b, Y1, with_path=False)
+    assert abs(val.item() - d0) <= 1e-12 * d0
+    B2, Y2 = r.standard_normal((200, 3)), r.standard_normal((180, 3))
+    plan, Bt, Y = setup(wts, B2, [Y2], dtype="f64")
+    val, _ = wts.softdtw_forward(plan, Bt, Y, 1e-3)
+    d2, _, _, _ = oracle.dtw(B2, Y2, with_path=False)
+    assert abs(val.item() - d2) <= 1e-3 * 20 + 1e-4 * d2
+
+
+def test_autograd_function_and_finite_differences(wts):
+    import torch
+    r = rng(4)
+    B = r.standard_normal((150, 2))
+    cyc = [r.standard_normal((N, 2)) for N in (140, 170)]
+    plan, Bt, Y = setup(wts, B, cyc, dtype="f64")
+    Bp = Bt.clone().requires_grad_(True)
+    wv = torch.tensor([0.7, 1.3], dtype=torch.float64, device="cuda")
+    vals = wts.SoftDTW.apply(Bp, plan, Y, 1.0)
+    (vals * wv).sum().backward()
+    _, og, _ = oracle.softdtw_batch(B, cyc, 1.0, wv.cpu().numpy())
+    check_vec(Bp.grad.cpu().numpy(), og)
+    # directional finite difference of the GPU forward (loose: float32 exponentials)
+    V = torch.from_numpy(r.standard_normal(B.shape)).cuda()
+    h = 1e-3
+    fp = (wts.softdtw_forward(plan, Bt + h * V, Y, 1.0)[0] * wv).sum().item()
+    fm = (wts.softdtw_forward(plan, Bt - h * V, Y, 1.0)[0] * wv).sum().item()
+    dd = (fp - fm) / (2 * h)
+    an = float((Bp.grad * V).sum().item())
+    assert abs(dd - an) <= 1e-3 * abs(an) + 1e-6
+
+
+def test_soft_repeat_deterministic(wts):
+    import torch
+    r = rng(5)
+    B = r.standard_normal((400, 3))
+    cyc = [r.standard_normal((N, 3)).astype(np.float32) for N in (350, 420, 60)]
+    plan, Bt, Y = setup(wts, B, cyc)
+    outs = []
+    for _ in range(2):
+        v, ck = wts.softdtw_forward(plan, Bt, Y, 0.3)
+        g = wts.softdtw_backward(plan, Bt, Y, 0.3, ck)
+        torch.cuda.synchronize()
+        outs.append((v.cpu().numpy(), g.cpu().numpy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
