@@ -41,6 +41,20 @@ def c_min_dist(d: int) -> int:
     return 2 * d + 3
 
 
+def c_min_soft(d: int, tau: int = 2) -> int:
+    """Algorithmic VALU ops per cell of one Soft-DTW forward + backward pass pair,
+    counted per DP pass (two passes per gradient step).  Forward: cost (2d),
+    scale (1), min of three (2), three differences, conversions and base-2
+    exponentials (3 + 3 + 3 tau), sum (2), logarithm (tau), conversion, two
+    adds.  Backward: the replayed forward plus the three weights (reciprocal
+    tau + 3 mul), the E recursion (3 conversions, 3 multiplies, 2 adds) and the
+    gradient sums (d FMAs + 1 add).  tau = 2: a transcendental costs two FP64
+    issue slots (measured)."""
+    fwd = 2 * d + 1 + 2 + 3 + 3 + 3 * tau + 2 + tau + 1 + 2
+    bwd = fwd + tau + 3 + 3 + 3 + 2 + d + 1
+    return (fwd + bwd + 1) // 2
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("wts_dtw.hip", "wts_device.h"):
@@ -86,6 +100,59 @@ def cpu_baseline(w, n_sample: int = 16):
                       "computes them), 1 DBA iteration, scores; %d cells" % (n, w.n, cells)}
 
 
+def soft_section(wts, dev, steps: int = 2, gamma: float = 0.1):
+    """Soft-DTW barycenter gradient steps on the full 128-cycle workload:
+    forward (with checkpoints) + E-matrix backward + preconditioned step."""
+    import numpy as np
+    import torch
+    from paper_2404_12134_amd import synth
+    w = synth.make(4)
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    L = w.L
+    plan = wts.Plan(off, w.d, dt, L)
+    B, _ = wts.init_barycenter(plan, Y, wts.INIT_EUCLID_MEAN)
+    gv = torch.from_numpy(1.0 / w.lengths.astype(np.float64)).to(dev)   # Eq. 7: lambda / m
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    tf, tb = [], []
+
+    def step(record):
+        ev[0].record()
+        val, ck = wts.softdtw_forward(plan, B, Y, gamma)
+        ev[1].record()
+        g, h = wts.softdtw_backward(plan, B, Y, gamma, ck, gv, with_mass=True)
+        ev[2].record()
+        wts.precond_step(B, g, h, 0.5)
+        ev[3].record()
+        if record:
+            torch.cuda.synchronize()
+            tf.append(ev[0].elapsed_time(ev[1]) / 1e3)
+            tb.append(ev[1].elapsed_time(ev[2]) / 1e3)
+        return val
+
+    step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    for op in (wts.OP_SOFT_BWD,):
+        st = wts.device_status(plan, op)
+        if st != 0:
+            raise RuntimeError("device status %d after the Soft-DTW backward" % st)
+    cells = L * int(w.lengths.sum())
+    counted = 2 * cells
+    gcups = counted / sec / 1e9
+    cm = c_min_soft(w.d)
+    frac = gcups * 1e9 * cm / VALU_LANE_OPS_PEAK
+    return {"workload": w.name + ": Soft-DTW gamma=%g, forward + backward + preconditioned "
+                                 "step (eta 0.5), weights 1/m_k" % gamma,
+            "gcups_fwd_bwd": round(gcups, 2), "s_per_gradient_step": round(sec, 4),
+            "forward_ms": round(1e3 * float(np.mean(tf)), 2),
+            "backward_ms": round(1e3 * float(np.mean(tb)), 2),
+            "cells_per_pass": cells, "ops_per_cell": cm, "alu_frac": round(frac, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-speedup", action="store_true",
                     help="skip the batched vs one-cycle-per-launch comparison")
+    ap.add_argument("--no-soft", action="store_true", help="skip the Soft-DTW section")
+    ap.add_argument("--soft-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -200,6 +269,7 @@ def main():
         speed = {"op": "dba_iterate", "one_cycle_per_launch_s": round(tb - ta, 5),
                  "batched_s": round(tc - tb, 5), "speedup": round((tb - ta) / (tc - tb), 2)}
 
+    soft = None if args.no_soft else soft_section(wts, dev, args.soft_steps)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
 
     line = {
@@ -215,6 +285,7 @@ def main():
                         "score": round(cells_bary / t_score / 1e9, 2)},
         "roofline": roofline,
         "batched_vs_per_cycle": speed,
+        "soft_dtw": soft,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

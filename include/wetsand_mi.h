@@ -14,6 +14,7 @@
  *   wts_softdtw_backward gradient of sum_k w_k Soft-DTW(B, C_k) w.r.t. B
  *                        through the E matrix                  (Eq. 6, Eq. 7)
  *   wts_anomaly_score    d_score = DTW(B, C_k) / |pi_k|        (Sec. III-D, Eq. 8)
+ *   wts_precond_step     one preconditioned gradient step on B (Eq. 7 driver)
  *   wts_medoid           all-pairs DTW and the medoid cycle (barycenter init)
  *   wts_init_barycenter  Euclidean-mean / nearest-length / copy initialisation
  *
@@ -158,6 +159,15 @@ wts_status wts_softdtw_backward(const wts_plan* plan, const double* bary, const 
                                 double gamma, const void* ckpt, size_t ckpt_bytes,
                                 const double* grad_value, double* grad_bary, double* row_mass,
                                 void* ws, size_t ws_bytes, void* stream);
+
+/* One step of the gradient descent that approximates the Soft-DTW barycenter
+ * of Eq. 7 (Sec. III-C computes it by gradient descent):
+ *   bary_l <- bary_l - eta * grad_l / (2 row_mass_l)
+ * using the gradient and row mass of wts_softdtw_backward (eta = 1 gives the
+ * soft-DBA average sum_j E_lj y_j / sum_j E_lj).  bary [L][d] float64 updated
+ * in place; grad [L][d], row_mass [L] float64.  No plan needed. */
+wts_status wts_precond_step(double* bary, const double* grad, const double* row_mass, int64_t L,
+                            int32_t d, double eta, void* stream);
 
 /* Medoid initialisation: D[k][i] = DTW(C_k, C_i) (squared cost, D[k][k] = 0),
  * total_k = sum_{i ascending} D[k][i], medoid = argmin_k total_k (lowest k on

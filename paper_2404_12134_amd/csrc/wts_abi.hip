@@ -548,6 +548,16 @@ wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const voi
   return WTS_OK;
 }
 
+wts_status wts_precond_step(double* bary, const double* grad, const double* row_mass, int64_t L,
+                            int32_t d, double eta, void* stream) {
+  if (!bary || !grad || !row_mass) return fail(WTS_E_ARG, "null bary/grad/row_mass");
+  if (L < 1 || d < 1) return fail(WTS_E_SHAPE, "L = %lld, d = %d", (long long)L, d);
+  if (!(eta == eta)) return fail(WTS_E_ARG, "eta is NaN");
+  HIP_TRY(wts::launch_precond_step(bary, grad, row_mass, L, d, eta,
+                                   static_cast<hipStream_t>(stream)));
+  return WTS_OK;
+}
+
 wts_status wts_medoid(const wts_plan* p, const void* cycles, double* dist_matrix, double* totals,
                       int32_t* medoid, void* ws, size_t ws_bytes, void* stream) {
   if (!p) return fail(WTS_E_ARG, "plan is null");

@@ -41,6 +41,8 @@ hipError_t launch_medoid(const double* pair_dist, const int2* pair_ab, int n_pai
 hipError_t launch_soft(int d, int ydtype, bool bwd, const SoftArgs& a, int grid, hipStream_t st);
 hipError_t launch_soft_reduce(const double* gsum, const double* hsum, const double* w, int n,
                               int64_t L, int d, double* grad, double* mass, hipStream_t st);
+hipError_t launch_precond_step(double* bary, const double* grad, const double* mass, int64_t L,
+                               int d, double eta, hipStream_t st);
 hipError_t launch_init(int ydtype, const void* Y, const int64_t* off, int n, int d, int src,
                        int64_t Nsrc, int64_t L, int euclid, double* out, hipStream_t st);
 

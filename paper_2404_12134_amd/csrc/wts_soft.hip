@@ -18,8 +18,9 @@
 // where w_s(i, j) = 2^(m_s - r'(i, j)) / sum_s is the normalised weight of
 // (i, j) in the soft-min of its successor s, and e(M-1, N-1) = 1 (the cell
 // that closes the path).  The kernel walks each strip's tiles from the last
-// column to the first: it replays the tile forward, keeping the three weights
-// of every cell in registers (float32), then sweeps the tile backwards in
+// column to the first: it replays the tile forward, keeping the three base-2
+// exponentials of every cell in registers (float32, normalised in float64
+// when used), then sweeps the tile backwards in
 // "push" form -- each finished cell splits its e into its three predecessors
 // with its own weights -- so no cell ever needs a neighbour's weights.  The
 // pushes of a strip's top row feed the strip above, so strips are pipelined
@@ -376,10 +377,9 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
             const double lf = left[r];
             const SoftMin sm = softmin3(dg, up, lf);
             const double rv = sq_cost<D>(xr[r], y) * k + sm.v;
-            const float inv = __builtin_amdgcn_rcpf(sm.s);
-            wd[u][r] = sm.ed * inv;
-            wu[u][r] = sm.eu * inv;
-            wl[u][r] = sm.el * inv;
+            wd[u][r] = sm.ed;   // unnormalised; normalised in float64 below
+            wu[u][r] = sm.eu;
+            wl[u][r] = sm.el;
             dg = lf;
             up = rv;
             left[r] = rv;
@@ -408,9 +408,17 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
             const double din = (r == RHO - 1) ? recv_dg : pdg[r];
             double e = (below_up + pl[r]) + din;
             if (t == t_inj && lane == k_last && r == r_last) e += 1.0;
-            below_up = e * (double)wu[u][r];
-            pl[r] = e * (double)wl[u][r];
-            const double dpush = e * (double)wd[u][r];
+            // normalise the three weights in float64 so that every cell passes
+            // on exactly the mass it received (a float32 reciprocal would leak
+            // ~1e-8 per cell, which adds up over tens of thousands of cells)
+            const double xd = (double)wd[u][r], xu = (double)wu[u][r], xl = (double)wl[u][r];
+            const double sw = (xd + xu) + xl;
+            double inv = __builtin_amdgcn_rcp(sw);
+            inv = __builtin_fma(inv, __builtin_fma(-sw, inv, 1.0), inv);
+            const double en = e * inv;
+            below_up = en * xu;
+            pl[r] = en * xl;
+            const double dpush = en * xd;
             if (r > 0) new_pdg[r - 1] = dpush;
             else dg0 = dpush;
             acc_e[r] += e;
@@ -482,7 +490,27 @@ __global__ void soft_reduce_kernel(const double* __restrict__ gsum, const double
   }
 }
 
+// One preconditioned gradient step on the barycenter:
+//   b_l <- b_l - eta * G_l / (2 h_l)
+// With eta = 1 this is the soft-DBA update b_l = sum_j e y_j / sum_j e.
+__global__ void precond_step_kernel(double* __restrict__ bary, const double* __restrict__ grad,
+                                    const double* __restrict__ mass, int64_t L, int d,
+                                    double eta) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= L * d) return;
+  const int64_t l = idx / d;
+  bary[idx] = bary[idx] - eta * grad[idx] / (2.0 * mass[l]);
+}
+
 }  // namespace
+
+hipError_t launch_precond_step(double* bary, const double* grad, const double* mass, int64_t L,
+                               int d, double eta, hipStream_t st) {
+  const int64_t tot = L * d;
+  hipLaunchKernelGGL(precond_step_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     bary, grad, mass, L, d, eta);
+  return hipGetLastError();
+}
 
 #define WTS_SOFT_D_SWITCH(d, CALL) \
   switch (d) {                     \

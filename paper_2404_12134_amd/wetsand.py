@@ -58,6 +58,7 @@ def load():
         "wts_softdtw_backward": [P, P, P, D, P, SZ, P, P, P, P, SZ, P],
         "wts_medoid": [P, P, P, P, P, P, SZ, P],
         "wts_init_barycenter": [P, P, I32, I32, P, P, P],
+        "wts_precond_step": [P, P, P, I64, I32, D, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -76,7 +77,7 @@ def exported_symbols():
     """Names the binding expects the library to export."""
     return ["wts_plan_create", "wts_plan_destroy", "wts_workspace_bytes", "wts_last_error",
             "wts_dtw_align", "wts_dba_iterate", "wts_anomaly_score", "wts_softdtw_forward",
-            "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter"]
+            "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step"]
 
 
 def _check(rc: int):
@@ -294,3 +295,11 @@ class SoftDTW(torch.autograd.Function):
                                 grad_value.contiguous())
         ctx.ckpt = None
         return grad, None, None, None
+
+
+def precond_step(bary: torch.Tensor, grad: torch.Tensor, row_mass: torch.Tensor, eta: float):
+    """In place: bary <- bary - eta * grad / (2 row_mass) (Soft-DTW barycenter descent)."""
+    L, d = bary.shape
+    _check(load().wts_precond_step(_ptr(bary), _ptr(grad), _ptr(row_mass), int(L), int(d),
+                                   float(eta), _stream()))
+    return bary

@@ -1,0 +1,162 @@
+"""Parity at the full workload sizes, on outputs the oracle can afford.
+
+The GPU runs the whole batch in the bench's launch configuration; the oracle
+checks sampled cycles one by one.  Whole-batch reductions are sampled through
+the weights: with w_k = 0 for every cycle but a few, the fixed-order fold of
+DBA (and of the Soft-DTW gradient) equals the fold over those few cycles
+alone, so the comparison stays bit-exact (DBA) or within 1e-4 (Soft-DTW).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_12134_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def f64(cycles):
+    return [np.asarray(c, dtype=np.float64) for c in cycles]
+
+
+def check_vec(a, b, rtol=1e-4):
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    scale = np.maximum(np.abs(b), 1e-2 * np.abs(b).max())
+    assert (np.abs(a - b) <= rtol * scale).all(), np.max(np.abs(a - b) / scale)
+    assert np.linalg.norm(a - b) <= rtol * np.linalg.norm(b)
+
+
+@pytest.mark.timeout(600)
+def test_config2_full_step(wts):
+    """64 x 3 ch, 4000..6000: medoid (sampled entries), one DBA iteration and
+    the scores of all 64 cycles, bit-exact."""
+    import torch
+    w = synth.make(2)
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    say("c2: medoid on the GPU")
+    mplan = wts.Plan(off, 3, dt, 0)
+    k, Dm, tot = wts.medoid(mplan, Y)
+    Dm = Dm.cpu().numpy()
+    cyc = f64(w.cycles)
+    r = np.random.Generator(np.random.PCG64(0))
+    for a, b in r.integers(0, w.n, (8, 2)):
+        if a == b:
+            continue
+        od, _, _, _ = oracle.dtw(cyc[a], cyc[b], with_path=False)
+        assert Dm[a, b] == od and Dm[b, a] == od
+    assert (np.diag(Dm) == 0).all()
+    k = int(k.item())
+    tot_o = np.array([sum(Dm[q, i] for i in range(w.n)) for q in range(w.n)])
+    np.testing.assert_array_equal(tot.cpu().numpy(), tot_o)
+    assert k == int(np.argmin(tot_o))
+    L = w.lengths[k]
+    plan = wts.Plan(off, 3, dt, int(L))
+    B0, _ = wts.init_barycenter(plan, Y, wts.INIT_COPY, k)
+    say("c2: DBA iteration + scores, oracle on all 64 cycles")
+    B1, counts, dist = wts.dba_iterate(plan, B0, Y)
+    score, sdist, plen = wts.anomaly_score(plan, B1, Y)
+    torch.cuda.synchronize()
+    assert wts.device_status(plan, wts.OP_DBA) == 0
+    Bn, K, od, _ = oracle.dba_iterate(cyc[k], cyc)
+    np.testing.assert_array_equal(B1.cpu().numpy(), Bn)
+    np.testing.assert_array_equal(counts.cpu().numpy(), K)
+    np.testing.assert_array_equal(dist.cpu().numpy(), od)
+    os_, osd, ol = oracle.score_batch(Bn, cyc)
+    np.testing.assert_array_equal(score.cpu().numpy(), os_)
+    np.testing.assert_array_equal(plen.cpu().numpy(), ol)
+    # the drifted cycles carry the largest scores (sanity, not a parity gate)
+    top3 = set(np.argsort(-os_)[:3].tolist())
+    say("c2: drift cycles", w.meta["drift"], "top-3 scores", sorted(top3))
+
+
+@pytest.mark.timeout(600)
+def test_config3_full_sampled(wts):
+    """512 x 6 ch, log-uniform 1000..20000, L = 10000: paths of sampled cycles
+    and a DBA update weighted onto them, bit-exact."""
+    import torch
+    w = synth.make(3)
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    plan = wts.Plan(off, 6, dt, w.L)
+    cyc = f64(w.cycles)
+    lens = w.lengths
+    pick = sorted({int(np.argmin(lens)), int(np.argmax(lens)), 7, 301})
+    say("c3: nearest-length init, full alignment with paths")
+    B0, kn = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
+    ko, Bo = oracle.nearest_init(cyc, w.L)
+    assert kn == ko
+    np.testing.assert_array_equal(B0.cpu().numpy(), Bo)
+    dist, plen, paths = wts.dtw_align(plan, B0, Y, paths=True)
+    torch.cuda.synchronize()
+    assert wts.device_status(plan, wts.OP_ALIGN_PATHS) == 0
+    for q in pick:
+        say("c3: oracle on cycle", q, "N =", lens[q])
+        od, ol, op, _ = oracle.dtw(Bo, cyc[q])
+        assert dist[q].item() == od and plen[q].item() == ol
+        np.testing.assert_array_equal(wts.path_of(plan, paths, plen, q), op)
+    wv = np.zeros(w.n)
+    wv[pick] = [1.0, 2.0, 0.5, 1.5][:len(pick)]
+    say("c3: weighted DBA update")
+    B1, counts, d2 = wts.dba_iterate(plan, B0, Y, torch.from_numpy(wv).cuda())
+    Bn, _, _, _ = oracle.dba_iterate(Bo, [cyc[q] for q in pick], wv[pick])
+    np.testing.assert_array_equal(B1.cpu().numpy(), Bn)
+    assert int(counts.sum().item()) == int(plen.sum().item())
+
+
+@pytest.mark.timeout(900)
+def test_config4_full_soft_sampled(wts):
+    """128 x 6 ch, 18000..22000, L = 20000, gamma = 0.1: values of sampled
+    cycles and the gradient weighted onto them, within 1e-4."""
+    import torch
+    w = synth.make(4)
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    plan = wts.Plan(off, 6, dt, w.L)
+    cyc = f64(w.cycles)
+    pick = [5, 77]
+    say("c4: Euclidean-mean init")
+    B, _ = wts.init_barycenter(plan, Y, wts.INIT_EUCLID_MEAN)
+    Bo = oracle.euclid_mean(cyc, w.L)
+    np.testing.assert_array_equal(B.cpu().numpy(), Bo)
+    wv = np.zeros(w.n)
+    wv[pick] = [1.0 / lens for lens in w.lengths[pick]]
+    say("c4: Soft-DTW forward + backward on all 128 cycles")
+    val, ck = wts.softdtw_forward(plan, B, Y, 0.1)
+    g, h = wts.softdtw_backward(plan, B, Y, 0.1, ck, torch.from_numpy(wv).cuda(), with_mass=True)
+    torch.cuda.synchronize()
+    assert wts.device_status(plan, wts.OP_SOFT_BWD) == 0
+    del ck
+    say("c4: oracle on cycles", pick)
+    ov, og, oh = oracle.softdtw_batch(Bo, [cyc[q] for q in pick], 0.1, wv[pick])
+    check_vec(val.cpu().numpy()[pick], ov)
+    check_vec(g.cpu().numpy(), og)
+    check_vec(h.cpu().numpy(), oh)
+
+
+@pytest.mark.timeout(900)
+def test_config5_full_scores_sampled(wts):
+    """256 x 6 ch, 40000..50000 with 1 % gaps, L = max N: scores of all cycles
+    on the GPU, two of them checked against the oracle bit for bit."""
+    import torch
+    w = synth.make(5)
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    plan = wts.Plan(off, 6, dt, w.L)
+    cyc = f64(w.cycles)
+    pick = [3, int(np.argmin(w.lengths))]
+    say("c5: nearest-length init + scores of 256 cycles")
+    B, kn = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
+    score, dist, plen = wts.anomaly_score(plan, B, Y)
+    torch.cuda.synchronize()
+    assert wts.device_status(plan, wts.OP_SCORE) == 0
+    ko, Bo = oracle.nearest_init(cyc, w.L)
+    assert kn == ko
+    say("c5: oracle on cycles", pick)
+    os_, od, ol = oracle.score_batch(Bo, [cyc[q] for q in pick])
+    np.testing.assert_array_equal(score.cpu().numpy()[pick], os_)
+    np.testing.assert_array_equal(plen.cpu().numpy()[pick], ol)

@@ -138,3 +138,20 @@ def test_soft_repeat_deterministic(wts):
         outs.append((v.cpu().numpy(), g.cpu().numpy()))
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_precond_step_is_the_soft_dba_update(wts):
+    # b <- b - eta G / (2h); with eta = 1 this is sum_j e y_j / sum_j e per row
+    import torch
+    r = rng(6)
+    B = r.standard_normal((260, 3))
+    cyc = [r.standard_normal((N, 3)) for N in (250, 270)]
+    plan, Bt, Y = setup(wts, B, cyc, dtype="f64")
+    for eta in (1.0, 0.5):
+        Bg = Bt.clone()
+        val, ck = wts.softdtw_forward(plan, Bg, Y, 0.5)
+        g, h = wts.softdtw_backward(plan, Bg, Y, 0.5, ck, with_mass=True)
+        wts.precond_step(Bg, g, h, eta)
+        _, og, oh = oracle.softdtw_batch(B, cyc, 0.5)
+        expect = B - eta * og / (2.0 * oh[:, None])
+        check_vec(Bg.cpu().numpy(), expect)
