@@ -41,6 +41,13 @@ def c_min_dist(d: int) -> int:
     return 2 * d + 3
 
 
+def c_min_path(d: int) -> int:
+    """Algorithmic VALU ops per cell of a DTW sweep that also decides the argmin
+    (path code or carried path length): the value recursion (2d + 3), two
+    compares, two selects and one pack/add."""
+    return 2 * d + 8
+
+
 def c_min_soft(d: int, tau: int = 2) -> int:
     """Algorithmic VALU ops per cell of one Soft-DTW forward + backward pass pair,
     counted per DP pass (two passes per gradient step).  Forward: cost (2d),
@@ -57,7 +64,7 @@ def c_min_soft(d: int, tau: int = 2) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("wts_dtw.hip", "wts_device.h"):
+    for f in ("wts_dtw.hip", "wts_soft.hip", "wts_device.h"):
         with open(os.path.join(ROOT, "paper_2404_12134_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -76,6 +83,51 @@ def traffic_from_profiles(kernel: str):
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+KERNELS = {   # rocprofv3 kernel-name prefix -> key used in profiles/traffic.json
+    "medoid": "void wts::(anonymous namespace)::dtw_fwd_kernel<float, float, 3, 4, 0, false>",
+    "dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, 4, 2, false>",
+    "score": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, 4, 1, false>",
+}
+
+
+def ingest_traffic(root: str):
+    """Reads rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes (CSV) found under
+    `root` and writes profiles/traffic.json: HBM bytes per launch of every sweep
+    kernel, scaled by what the same counters read for the 1 GiB copy of
+    `bench.py --only copy` (bytes_read / FETCH_SIZE_KiB, and the same for
+    writes), tagged with the current kernel source hash."""
+    import csv
+    import glob
+    per_dispatch = {}      # counters come in several rows per dispatch: sum them
+    for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            key = (r["Kernel_Name"], r["Counter_Name"], f, r["Dispatch_Id"])
+            per_dispatch[key] = per_dispatch.get(key, 0.0) + float(r["Counter_Value"])
+    vals = {}
+    for (kname, cname, _, _), v in per_dispatch.items():
+        vals.setdefault((kname, cname), []).append(v)
+    avg = {k: sum(v) / len(v) for k, v in vals.items()}
+    gib = float(1 << 30)
+    # the 1 GiB copies are the largest copyBuffer dispatches of all passes
+    f_cal = max(v for k, vs in vals.items() if "copyBuffer" in k[0] and k[1] == "FETCH_SIZE"
+                for v in vs)
+    w_cal = max(v for k, vs in vals.items() if "copyBuffer" in k[0] and k[1] == "WRITE_SIZE"
+                for v in vs)
+    f_scale, w_scale = gib / f_cal, gib / w_cal        # bytes per counted KiB
+    out = {"_calibration": {"copy_bytes": int(gib), "fetch_kib": f_cal, "write_kib": w_cal,
+                            "fetch_scale": f_scale, "write_scale": w_scale}}
+    for key, prefix in KERNELS.items():
+        fk = [avg[k] for k in avg if k[0].startswith(prefix) and k[1] == "FETCH_SIZE"]
+        wk = [avg[k] for k in avg if k[0].startswith(prefix) and k[1] == "WRITE_SIZE"]
+        if fk and wk:
+            out[key] = {"kernel": prefix, "source_hash": kernel_source_hash(),
+                        "fetch_bytes": fk[0] * f_scale, "write_bytes": wk[0] * w_scale,
+                        "bytes_per_launch": fk[0] * f_scale + wk[0] * w_scale}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def cpu_baseline(w, n_sample: int = 16):
@@ -153,6 +205,46 @@ def soft_section(wts, dev, steps: int = 2, gamma: float = 0.1):
             "cells_per_pass": cells, "ops_per_cell": cm, "alu_frac": round(frac, 4)}
 
 
+def only_phase(args, wts, dev):
+    """One phase of the step, --steps times, for rocprofv3 counter passes.  The
+    'copy' phase is a plain 1 GiB device-to-device copy: the reference for
+    scaling FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    from paper_2404_12134_amd import synth
+    if args.only == "copy":
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"phase": "copy", "bytes_read": a.numel() * 8, "bytes_written": b.numel() * 8}))
+        return
+    if args.only == "soft":
+        soft_section(wts, dev, args.steps)
+        torch.cuda.synchronize()
+        print(json.dumps({"phase": "soft"}))
+        return
+    w = synth.make(2)
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    mplan = wts.Plan(off, w.d, dt, 0)
+    k0 = int(wts.medoid(mplan, Y, with_matrix=False)[0].item())
+    L = int(w.lengths[k0])
+    plan = wts.Plan(off, w.d, dt, L)
+    B, _ = wts.init_barycenter(plan, Y, wts.INIT_COPY, k0)
+    Bo = torch.empty_like(B)
+    counts = torch.empty(L, dtype=torch.int64, device=dev)
+    dist = torch.empty(w.n, dtype=torch.float64, device=dev)
+    for _ in range(args.steps):
+        if args.only == "medoid":
+            wts.medoid(mplan, Y, with_matrix=False)
+        elif args.only == "dba":
+            wts.dba_iterate(plan, B, Y, bary_out=Bo, counts=counts, dist=dist)
+        else:
+            wts.anomaly_score(plan, B, Y)
+    torch.cuda.synchronize()
+    print(json.dumps({"phase": args.only, "L": L}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,7 +255,14 @@ def main():
                     help="skip the batched vs one-cycle-per-launch comparison")
     ap.add_argument("--no-soft", action="store_true", help="skip the Soft-DTW section")
     ap.add_argument("--soft-steps", type=int, default=2)
+    ap.add_argument("--only", choices=["medoid", "dba", "score", "soft", "copy"],
+                    help="run only one phase --steps times (for hardware-counter passes)")
+    ap.add_argument("--traffic-from", metavar="DIR",
+                    help="write profiles/traffic.json from rocprofv3 FETCH/WRITE_SIZE passes")
     args = ap.parse_args()
+    if args.traffic_from:
+        ingest_traffic(args.traffic_from)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -176,6 +275,9 @@ def main():
 
     wts.load()
     dev = torch.device("cuda:0")
+    if args.only:
+        only_phase(args, wts, dev)
+        return
     w = synth.make(2)
     lens = w.lengths
     Y, off, dt = wts.pack_cycles(w.cycles)
@@ -225,6 +327,8 @@ def main():
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
+    mplan.enable_timing(4 * args.steps)
+    plan.enable_timing(16 * args.steps)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(True)
@@ -241,16 +345,31 @@ def main():
     t_dba = float(np.mean(times["dba"])) / iters
     t_score = float(np.mean(times["score"]))
 
-    # roofline of the dominant kernel: the all-pairs DTW value sweep of the medoid
-    ops = cells_medoid * c_min_dist(w.d)
-    achieved = ops / t_med / 1e12
+    # roofline of the dominant sweep kernel (largest total time over the timed
+    # steps), timed with HIP events around each launch on its stream
+    sweeps = {
+        "medoid": (mplan, wts.OP_MEDOID, cells_medoid, c_min_dist(w.d)),
+        "dba": (plan, wts.OP_DBA, cells_bary, c_min_path(w.d)),
+        "score": (plan, wts.OP_SCORE, cells_bary, c_min_path(w.d)),
+    }
+    kt = {}
+    for key, (pl, op, cells, cm) in sweeps.items():
+        tot, cnt = pl.sweep_ms(op)
+        kt[key] = (tot, cnt)
+    dom = max(kt, key=lambda k: kt[k][0])
+    pl, op, cells, cm = sweeps[dom]
+    launch_s = kt[dom][0] / max(1, kt[dom][1]) / 1e3
+    achieved = cells * cm / launch_s / 1e12
     peak = VALU_LANE_OPS_PEAK / 1e12
-    traffic = traffic_from_profiles("dtw_fwd_kernel<float,float,3,4,DIST>")
-    roofline = {"bound": "alu", "kernel": "dtw_fwd_kernel (medoid, value sweep)",
+    roofline = {"bound": "alu", "kernel": KERNELS[dom].replace("void ", ""),
                 "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "ops_per_cell": c_min_dist(w.d), "cells_per_launch": cells_medoid,
-                "launch_ms": round(t_med * 1e3, 3)}
+                "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(dom),
+                "ops_per_cell": cm, "cells_per_launch": cells,
+                "launch_ms": round(launch_s * 1e3, 3),
+                "per_kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in kt.items()},
+                "per_kernel_alu_frac": {k: round(sweeps[k][2] * sweeps[k][3] /
+                                                 (kt[k][0] / max(1, kt[k][1]) / 1e3) /
+                                                 VALU_LANE_OPS_PEAK, 4) for k in kt}}
 
     speed = None
     if not args.no_speedup:

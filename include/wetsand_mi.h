@@ -107,6 +107,19 @@ void wts_plan_destroy(wts_plan* plan);
  * operation needs; 0 for an operation the plan cannot run. */
 size_t wts_workspace_bytes(const wts_plan* plan, int op);
 
+/* Sweep timing, for profiling.  wts_plan_timing(plan, k) creates k pairs of
+ * HIP events (k = 0 switches timing off); afterwards every sweep kernel the
+ * plan launches (the dynamic-programming kernel of an operation, not its
+ * small helper kernels) is bracketed by an event pair recorded on the call's
+ * stream, reusing the pairs round-robin.  Not for use under graph capture.
+ * wts_plan_sweep_ms(plan, op, &total_ms, &launches) waits for the recorded
+ * launches of `op` (WTS_OP_DBA for the path sweep of wts_dba_iterate and of
+ * wts_dtw_align with paths, WTS_OP_SCORE for the value+length sweep,
+ * WTS_OP_MEDOID, WTS_OP_SOFT_FWD, WTS_OP_SOFT_BWD), sums their durations and
+ * forgets them. */
+wts_status wts_plan_timing(wts_plan* plan, int32_t max_launches);
+wts_status wts_plan_sweep_ms(wts_plan* plan, int op, double* total_ms, int32_t* launches);
+
 /* Message describing the last non-OK status returned on this thread. */
 const char* wts_last_error(void);
 

@@ -50,7 +50,7 @@ struct PairSet {
   int2* d_items = nullptr;
   int2* d_items_rev = nullptr;
   int n_pairs = 0, n_items = 0, n_flags = 0;
-  int64_t code_words = 0, bnd_elems = 0, aux_strip_elems = 0, state_elems = 0;
+  int64_t code_words = 0, bnd_elems = 0, aux_strip_elems = 0, state_elems = 0, row_elems = 0;
   int64_t max_rows = 0;
 };
 
@@ -66,7 +66,7 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
   });
   ps.pairs.clear();
   ps.items.clear();
-  int64_t code = 0, bnd = 0, aux = 0, state = 0;
+  int64_t code = 0, bnd = 0, aux = 0, state = 0, rows = 0;
   int flags = 0;
   for (size_t p = 0; p < jobs.size(); ++p) {
     const Job& jb = jobs[p];
@@ -82,6 +82,7 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
     d.bnd_base = bnd;
     d.aux_base = aux;
     d.state_base = state;
+    d.row_base = rows;
     d.flag_base = flags;
     d.item_base = (int)ps.items.size();
     code += (int64_t)d.S * d.WT * rho * wts::kWave;
@@ -89,6 +90,7 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
     aux += (int64_t)d.S * jb.N;
     state += (int64_t)d.S * d.WT * (rho + 1) * wts::kWave;
     flags += d.S;
+    rows += (int64_t)d.S * ((jb.N + wts::kWave - 1 + 3) & ~3);   // strip row stride RS
     for (int s = 0; s < d.S; ++s) ps.items.push_back(make_int2((int)p, s));
     for (int s = d.S - 1; s >= 0; --s) ps.items_rev.push_back(make_int2((int)p, s));
     ps.pairs.push_back(d);
@@ -101,6 +103,7 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
   ps.bnd_elems = bnd;
   ps.aux_strip_elems = aux;
   ps.state_elems = state;
+  ps.row_elems = rows;
 }
 
 // Workspace: every region 256-byte aligned, in this order.
@@ -124,6 +127,10 @@ struct wts_plan {
   int2* d_med_ab = nullptr;
   PairSet bary, med, soft;
   int64_t nmax = 0;
+  // optional sweep timing: pool of (start, stop) event pairs, one per sweep launch
+  std::vector<hipEvent_t> ev;
+  size_t ev_next = 0;
+  std::vector<int> ev_op;     // op tag of each used pair (-1 = unused)
 };
 
 namespace {
@@ -151,9 +158,8 @@ Layout layout(const wts_plan* p, int op) {
   }
   const bool paths = op == WTS_OP_ALIGN_PATHS || op == WTS_OP_DBA;
   l.queue = take(2 * sizeof(int));   // [0] item counter, [1] status word
-  l.progress = take(sizeof(int) * (size_t)ps.n_flags);
-  l.bnd_r = take(sizeof(double) * (size_t)ps.bnd_elems);
-  l.bnd_aux = take(sizeof(int) * (size_t)(paths ? ps.aux_strip_elems : ps.bnd_elems));
+  l.bnd_r = take(sizeof(double) * (size_t)ps.row_elems);
+  l.bnd_aux = take(sizeof(int) * (size_t)(op == WTS_OP_MEDOID ? 0 : ps.row_elems));
   if (paths) l.codes = take(sizeof(uint32_t) * (size_t)ps.code_words);
   l.out_dist = take(sizeof(double) * (size_t)ps.n_pairs);
   l.out_aux = take(sizeof(int) * (size_t)ps.n_pairs);
@@ -212,19 +218,36 @@ wts_status check_bary_plan(const wts_plan* p) {
   return WTS_OK;
 }
 
-// Zero the queue and progress counters, then run the persistent sweep.
+// Sweep timing (off unless wts_plan_timing enabled it): records a pair of
+// events around the sweep kernel of operation `op` on its stream.
+int timing_begin(const wts_plan* p, int op, hipStream_t st) {
+  wts_plan* q = const_cast<wts_plan*>(p);
+  if (q->ev.empty()) return -1;
+  const size_t pairs = q->ev.size() / 2;
+  const size_t k = q->ev_next % pairs;
+  q->ev_next++;
+  q->ev_op[k] = op;
+  (void)hipEventRecord(q->ev[2 * k], st);
+  return (int)k;
+}
+void timing_end(const wts_plan* p, int k, hipStream_t st) {
+  if (k >= 0) (void)hipEventRecord(p->ev[2 * k + 1], st);
+}
+
+// Zero the queue, fill the strip rows with sentinels, then run the
+// persistent sweep.
 wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, bool x_is_cycle,
                      const void* x, const void* y, void* ws, const Layout& l, double* out_dist,
                      hipStream_t st) {
   HIP_TRY(wts::launch_zero(at<int>(ws, l.queue), 2, st));
-  HIP_TRY(wts::launch_zero(at<int>(ws, l.progress), ps.n_flags, st));
+  HIP_TRY(wts::launch_fill_sentinels(at<double>(ws, l.bnd_r), ps.row_elems, at<int>(ws, l.bnd_aux),
+                                     mode == wts::MODE_DIST ? 0 : ps.row_elems, st));
   wts::FwdArgs a{};
   a.pairs = ps.d_pairs;
   a.items = ps.d_items;
   a.n_items = ps.n_items;
   a.queue = at<int>(ws, l.queue);
   a.status = at<int>(ws, l.queue) + 1;
-  a.progress = at<int>(ws, l.progress);
   a.x = x;
   a.y = y;
   a.bnd_r = at<double>(ws, l.bnd_r);
@@ -232,10 +255,11 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
   a.codes = mode == wts::MODE_PATH ? at<uint32_t>(ws, l.codes) : nullptr;
   a.out_dist = out_dist ? out_dist : at<double>(ws, l.out_dist);
   a.out_aux = at<int>(ws, l.out_aux);
-  a.aux_per_strip = mode == wts::MODE_PATH ? 1 : 0;
   a.cost_kind = euc ? 1 : 0;
+  const int tk = timing_begin(p, x_is_cycle ? WTS_OP_MEDOID : (mode == wts::MODE_PATH ? WTS_OP_DBA : WTS_OP_SCORE), st);
   HIP_TRY(wts::launch_fwd(p->d, p->rho, mode, euc, x_is_cycle, p->dtype, a,
                           default_grid(p, ps), st));
+  timing_end(p, tk, st);
   return WTS_OK;
 }
 
@@ -367,9 +391,46 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   return WTS_OK;
 }
 
+wts_status wts_plan_timing(wts_plan* p, int32_t max_launches) {
+  if (!p) return fail(WTS_E_ARG, "plan is null");
+  if (max_launches < 0 || max_launches > 4096) return fail(WTS_E_ARG, "max_launches %d", max_launches);
+  DeviceGuard g(p->device);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+  p->ev_op.clear();
+  p->ev_next = 0;
+  for (int k = 0; k < 2 * max_launches; ++k) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    p->ev.push_back(e);
+  }
+  p->ev_op.assign(max_launches, -1);
+  return WTS_OK;
+}
+
+wts_status wts_plan_sweep_ms(wts_plan* p, int op, double* total_ms, int32_t* launches) {
+  if (!p || !total_ms || !launches) return fail(WTS_E_ARG, "null argument");
+  DeviceGuard g(p->device);
+  double tot = 0.0;
+  int cnt = 0;
+  for (size_t k = 0; k < p->ev_op.size(); ++k) {
+    if (p->ev_op[k] != op) continue;
+    float ms = 0.f;
+    HIP_TRY(hipEventSynchronize(p->ev[2 * k + 1]));
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev[2 * k], p->ev[2 * k + 1]));
+    tot += ms;
+    ++cnt;
+    p->ev_op[k] = -1;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  return WTS_OK;
+}
+
 void wts_plan_destroy(wts_plan* p) {
   if (!p) return;
   DeviceGuard g(p->device);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   for (PairSet* ps : {&p->bary, &p->med, &p->soft}) {
     if (ps->d_pairs) (void)hipFree(ps->d_pairs);
     if (ps->d_items) (void)hipFree(ps->d_items);
@@ -503,7 +564,9 @@ wts_status wts_softdtw_forward(const wts_plan* p, const double* bary, const void
   a.kscale = 1.0 / (gamma * 0.69314718055994530942);
   a.value = value;
   a.L = p->L;
+  const int tk = timing_begin(p, WTS_OP_SOFT_FWD, st);
   HIP_TRY(wts::launch_soft(p->d, p->dtype, false, a, default_grid(p, ps), st));
+  timing_end(p, tk, st);
   return WTS_OK;
 }
 
@@ -542,7 +605,9 @@ wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const voi
   a.gsum = at<double>(ws, l.gsum);
   a.hsum = at<double>(ws, l.hsum);
   a.L = p->L;
+  const int tk = timing_begin(p, WTS_OP_SOFT_BWD, st);
   HIP_TRY(wts::launch_soft(p->d, p->dtype, true, a, default_grid(p, ps), st));
+  timing_end(p, tk, st);
   HIP_TRY(wts::launch_soft_reduce(a.gsum, a.hsum, grad_value, p->n, p->L, p->d, grad_bary,
                                   row_mass, st));
   return WTS_OK;

@@ -10,10 +10,13 @@
 //    a DPP wave_shr:1 move; lane 0 takes them from the previous strip's
 //    bottom row;
 //  * strips of one pair run on different workgroups and hand their bottom
-//    row over through device memory, with a per-strip progress counter
-//    (columns published so far).  Both the row values and the counters use
-//    device-scope relaxed atomics, ordered by s_waitcnt, so no L2 writeback
-//    is needed;
+//    row over through device memory.  The DTW sweeps give every strip its own
+//    row, filled with a sentinel before the launch: the strip below polls
+//    the values themselves (device-scope loads) until no sentinel is left,
+//    so the producer needs neither a counter nor a store drain.  The
+//    Soft-DTW sweeps publish a per-strip progress counter (columns written
+//    so far) after their device-scope row stores, ordered by s_waitcnt; in
+//    both cases no L2 writeback is needed;
 //  * workgroups pop (pair, strip) items from a queue in which the strips of
 //    one pair are consecutive and pairs are sorted by decreasing size: a
 //    strip only ever waits for an item popped earlier by a running
@@ -40,7 +43,37 @@ struct PairDesc {
   int32_t pad;
   int64_t aux_base;   // first element of this pair's per-strip rows (S * N)
   int64_t state_base; // first double of this pair's Soft-DTW sweep states
+  int64_t row_base;   // DTW sweeps: first element of this pair's strip rows (S * RS)
 };
+
+// Wave-uniform copies (scalar registers) of values every lane holds alike:
+// addresses built from them stay scalar, so buffer resources need no
+// per-lane waterfall loop.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ PairDesc uniform(const PairDesc& p) {
+  PairDesc q;
+  q.x_off = uni(p.x_off);
+  q.y_off = uni(p.y_off);
+  q.code_base = uni(p.code_base);
+  q.bnd_base = uni(p.bnd_base);
+  q.M = uni(p.M);
+  q.N = uni(p.N);
+  q.S = uni(p.S);
+  q.out = uni(p.out);
+  q.flag_base = uni(p.flag_base);
+  q.WT = uni(p.WT);
+  q.item_base = uni(p.item_base);
+  q.pad = 0;
+  q.aux_base = uni(p.aux_base);
+  q.state_base = uni(p.state_base);
+  q.row_base = uni(p.row_base);
+  return q;
+}
 
 // Rows per lane of the Soft-DTW sweeps (the backward keeps 3 weights per cell
 // for 16 steps in registers).
@@ -54,15 +87,13 @@ struct FwdArgs {
   int n_items;
   int* queue;            // item counter, zeroed before the launch
   int* status;           // device status word (bit 0: a boundary wait gave up)
-  int* progress;         // per strip: columns of its bottom row published
   const void* x;         // X rows (float64 barycenter, or cycles for the medoid)
   const void* y;         // cycle values
-  double* bnd_r;         // boundary rows: cumulative cost
-  int* bnd_aux;          // boundary rows: path length (DIST_LEN) or entry code (PATH)
+  double* bnd_r;         // strip rows (S * RS per pair, sentinel-filled): cumulative cost
+  int* bnd_aux;          // strip rows: path length (DIST_LEN) or entry code (PATH)
   uint32_t* codes;       // 2-bit argmin codes (PATH)
   double* out_dist;      // [pair slot] r(M-1, N-1)
   int* out_aux;          // [pair slot] |pi| (DIST_LEN) or entry code of (M-1, N-1) (PATH)
-  int aux_per_strip;     // 1: bnd_aux keeps every strip's bottom row (PATH)
   int cost_kind;         // 0 squared, 1 Euclidean (sqrt)
 };
 

@@ -8,6 +8,7 @@
 // Euclidean).  The argmin code of a cell is the first of diag (0), up (1),
 // left (2) that attains the minimum; following the codes back from
 // (M-1, N-1) gives the optimal path that Eq. 8 divides by.
+#include <climits>
 #include <type_traits>
 
 #include "wts_device.h"
@@ -29,12 +30,38 @@ __device__ __forceinline__ double sq_cost(const double (&x)[D], const double (&y
   return s;
 }
 
-#ifndef WTS_CHUNK
-#define WTS_CHUNK 64
-#endif
-constexpr int kChunk = WTS_CHUNK;   // sweep steps between two boundary hand-overs
-static_assert(kChunk == 32 || kChunk == 64, "chunk must be 32 or 64 steps");
+constexpr int kChunk = 64;          // sweep steps per Y staging round
 constexpr int kRing = 128;          // Y columns kept in LDS (>= kChunk + 63, power of 2)
+
+// Strip boundary rows.  Strip s writes the bottom row of its rows into its own
+// row of the pair's boundary block, column j at index j + 63 (the 16 columns
+// lane 63 produces in the steps tg .. tg+15 land at indices tg .. tg+15),
+// after the whole block was filled with sentinels.  The strip below polls the values
+// themselves: a value is ready once it is no longer the sentinel, so no
+// progress counter, fence or store drain is needed between strips.
+constexpr unsigned long long kSentR = 0xFFF4DEADBEEF0000ull;   // a NaN no arithmetic makes
+constexpr int kSentX = INT_MIN;
+__device__ __forceinline__ int row_stride(int N) { return (N + 63 + 3) & ~3; }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+// Device-scope (sc1) buffer accesses: stores write through to the point of
+// coherence for all CUs of the device.  Every lane issues the instruction; a
+// lane that must not access memory passes kDrop, an offset past the buffer's
+// record count, and the hardware range check discards its access (a load
+// returns 0).  No branch around the access is needed.
+constexpr int kDrop = 0x7ffffff0;   // > any strip row (rows are < 2^28 bytes)
+typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, v), r, byte_off, 0, 16);
+}
+__device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, int v) {
+  __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 16);
+}
+__device__ __forceinline__ bool is_sent(double v) {
+  return (unsigned long long)__double_as_longlong(v) == kSentR;
+}
 
 // One wavefront sweeps one strip of one pair.  State per lane: RHO rows of X
 // (float64 registers), the cumulative cost of those rows at the previous
@@ -43,11 +70,12 @@ constexpr int kRing = 128;          // Y columns kept in LDS (>= kChunk + 63, po
 template <typename TX, typename TY, int D, int RHO, int MODE, bool EUC>
 __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
   constexpr int H = kWave * RHO;
+  constexpr bool kAux = MODE != MODE_DIST;
   __shared__ double ys[D][kRing];
-  __shared__ double binr[kChunk];
-  __shared__ int binx[kChunk];
-  __shared__ double bor[kRing];
-  __shared__ int box[kRing];
+  __shared__ double binr[16];   // strip above, this group's 16 columns
+  __shared__ int binx[16];
+  __shared__ double stg_r[16];  // lane 63's bottom row of the last group
+  __shared__ int stg_x[16];
   __shared__ int s_item;
 
   const int lane = threadIdx.x;
@@ -58,24 +86,26 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
   for (;;) {
     if (lane == 0) s_item = atomicAdd(a.queue, 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: scalar loads below
     __syncthreads();
     if (item >= a.n_items) break;
     const int2 it = a.items[item];
-    const PairDesc pd = a.pairs[it.x];
-    const int s = it.y;
+    const PairDesc pd = uniform(a.pairs[uni(it.x)]);
+    const int s = uni(it.y);
     const int M = pd.M, N = pd.N;
     const int i0 = s * H;
     const int ib = i0 + lane * RHO;
     const bool has_prev = s > 0;
     const bool has_next = s + 1 < pd.S;
     const int Tend = pd.WT * 16;
+    const int RS = row_stride(N);
 
-    double* r_row = a.bnd_r + pd.bnd_base;                       // rolling boundary row
-    int* aux_in = a.bnd_aux + (a.aux_per_strip ? pd.aux_base + (int64_t)(s - 1) * N : pd.bnd_base);
-    int* aux_out = a.bnd_aux + (a.aux_per_strip ? pd.aux_base + (int64_t)s * N : pd.bnd_base);
-    int* prog_in = a.progress + pd.flag_base + s - 1;
-    int* prog_out = a.progress + pd.flag_base + s;
+    const double* r_in = a.bnd_r + pd.row_base + (int64_t)(s - 1) * RS;
+    double* r_out = a.bnd_r + pd.row_base + (int64_t)s * RS;   // written via rr_out
+    const int* x_in = a.bnd_aux + pd.row_base + (int64_t)(s - 1) * RS;
+    int* x_out = a.bnd_aux + pd.row_base + (int64_t)s * RS;
+    const __amdgpu_buffer_rsrc_t rr_out = rsrc(r_out, RS * 8);
+    const __amdgpu_buffer_rsrc_t rx_out = rsrc(x_out, RS * 4);
 
     double xr[RHO][D];
 #pragma unroll
@@ -96,56 +126,91 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
     int botx = 0;
     bool gave_up = false;   // set once a wait times out: the strip never waits again
 
-    double yv[D];
-    if (lane < kChunk) {
-      const int j = lane;
+    // The strip above's bottom row, 16 columns at a time: lanes 0..15 hold the
+    // next group's values in (pr, px) -- loaded one group ahead -- and wait
+    // until none of them is a sentinel any more.  The prefetch is one
+    // unconditional buffer load per value (lanes without a value read past
+    // the record count and get 0; strip 0 has no records at all), so the
+    // only wait for it is the check after the group's sweep steps.
+    const __amdgpu_buffer_rsrc_t rr_in = rsrc(r_in, has_prev ? RS * 8 : 0);
+    const __amdgpu_buffer_rsrc_t rx_in = rsrc(x_in, has_prev ? RS * 4 : 0);
+    double pr = 0.0;
+    int px = 0;
+    auto fetch = [&](int tg) {
+      const int j = tg + lane;
+      const bool want = lane < 16 && j < N;
+      pr = __builtin_bit_cast(
+          double, __builtin_amdgcn_raw_buffer_load_b64(rr_in, want ? (j + 63) * 8 : kDrop, 0, 16));
+      if (kAux)
+        px = (int)__builtin_amdgcn_raw_buffer_load_b32(rx_in, want ? (j + 63) * 4 : kDrop, 0, 16);
+    };
+    auto settle = [&](int tg) {
+      if (!has_prev || gave_up) return;
+      const int j = tg + lane;
+      auto ready = [&]() {
+        return lane >= 16 || j >= N || (!is_sent(pr) && (!kAux || px != kSentX));
+      };
+      if (__all(ready())) return;   // the usual case: the prefetch found every value
+      int polls = 0;
+      do {
+        __builtin_amdgcn_s_sleep(2);
+        if (++polls > kSpinLimit) {   // never expected: report and carry on
+          if (lane == 0) atomicOr(a.status, kStatusSpinTimeout);
+          gave_up = true;
+          break;
+        }
+        if (!ready()) {
+          pr = ld_dev(r_in + j + 63);
+          if (kAux) px = ld_dev(x_in + j + 63);
+        }
+      } while (!__all(ready()));
+    };
+    // Stores of group tg: lane 63's bottom row (columns tg-63 .. tg-48, at
+    // indices tg .. tg+15 of the strip's row, by lanes 0..15 in one
+    // coalesced store) and, for PATH, the group's argmin code words.
+    auto publish = [&](int tg) {
+      const int j = tg - 63 + lane;
+      const bool w = has_next && lane < 16 && j >= 0 && j < N;
+      st_dev(rr_out, w ? (tg + lane) * 8 : kDrop, stg_r[lane & 15]);
+      if (kAux) st_dev(rx_out, w ? (tg + lane) * 4 : kDrop, stg_x[lane & 15]);
+      if (MODE == MODE_PATH) {
+        const int64_t cw = pd.code_base + (int64_t)(s * pd.WT + (tg >> 4)) * RHO * kWave + lane;
 #pragma unroll
-      for (int c = 0; c < D; ++c)
-        yv[c] = j < N ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0;
+        for (int r = 0; r < RHO; ++r) a.codes[cw + r * kWave] = acc[r];
+      }
+    };
+    fetch(0);
+    settle(0);
+
+    // Y values are read from a clamped column (always in bounds) and zeroed
+    // past N, so the loads are unconditional
+    double yv[D];
+    {
+      const int j = lane;
+      const int64_t row = (pd.y_off + min(j, N - 1)) * D;
+#pragma unroll
+      for (int c = 0; c < D; ++c) yv[c] = static_cast<double>(Y[row + c]);
+#pragma unroll
+      for (int c = 0; c < D; ++c) yv[c] = j < N ? yv[c] : 0.0;
 #pragma unroll
       for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
     }
-    __syncthreads();
 
     for (int t0 = 0; t0 < Tend; t0 += kChunk) {
       const int tcnt = min(kChunk, Tend - t0);
       const bool more = t0 + kChunk < Tend;
-      if (more && lane < kChunk) {   // next chunk of Y into registers; to LDS after this sweep
+      if (more) {   // next chunk of Y into registers; stored to LDS after this sweep
         const int j = t0 + kChunk + lane;
+        const int64_t row = (pd.y_off + min(j, N - 1)) * D;
 #pragma unroll
-        for (int c = 0; c < D; ++c)
-          yv[c] = j < N ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0;
+        for (int c = 0; c < D; ++c) yv[c] = static_cast<double>(Y[row + c]);
+#pragma unroll
+        for (int c = 0; c < D; ++c) yv[c] = j < N ? yv[c] : 0.0;
       }
-      if (has_prev) {
-        const int need = min(N, t0 + kChunk);
-        if (lane == 0 && !gave_up) {
-          int polls = 0;
-          while (ld_dev(prog_in) < need) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++polls > kSpinLimit) {   // never expected: report and carry on
-              atomicOr(a.status, kStatusSpinTimeout);
-              gave_up = true;
-              break;
-            }
-          }
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        const int j = t0 + lane;
-        if (lane < kChunk) {
-          binr[lane] = j < N ? ld_dev(r_row + j) : INF;
-          if (MODE != MODE_DIST) binx[lane] = j < N ? ld_dev(aux_in + j) : 0;
-        }
-      }
-      __syncthreads();
 
       // 16 sweep steps; FULL: every lane is inside the grid (no masking)
       auto group16 = [&](auto full_tag, int tb) {
         constexpr bool FULL = decltype(full_tag)::value;
-        // PATH / DIST_LEN sweeps run at low occupancy: keep the bottom row of
-        // 16 steps in registers instead of a lane-masked LDS store per step.
-        constexpr bool kHist = MODE != MODE_DIST;
-        double bhist[kHist ? 16 : 1];
-        int bxhist[kHist ? 16 : 1];
         const int tg = t0 + tb;
         // LDS operands of step u+1 are read during step u (software pipelining)
         double yn[D];
@@ -153,8 +218,8 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
         int bxn = 0;
 #pragma unroll
         for (int c = 0; c < D; ++c) yn[c] = ys[c][(tg - lane) & (kRing - 1)];
-        bn = has_prev ? binr[tb] : INF;
-        if (MODE == MODE_DIST_LEN) bxn = has_prev ? binx[tb] : 0;
+        bn = binr[0];
+        if (MODE == MODE_DIST_LEN) bxn = binx[0];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int t = tg + u;
@@ -167,8 +232,8 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
           if (u + 1 < 16) {
 #pragma unroll
             for (int c = 0; c < D; ++c) yn[c] = ys[c][(j + 1) & (kRing - 1)];
-            bn = has_prev ? binr[tb + u + 1] : INF;
-            if (MODE == MODE_DIST_LEN) bxn = has_prev ? binx[tb + u + 1] : 0;
+            bn = binr[u + 1];
+            if (MODE == MODE_DIST_LEN) bxn = binx[u + 1];
           }
           const double upin = shr1_f64(bot, bval);
           int upinx = 0, dgx0 = 0;
@@ -207,6 +272,9 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
                   const uint32_t c1 = __builtin_unpredictable(isu) ? 1u : 2u;
                   const uint32_t code = __builtin_unpredictable(isd) ? 0u : c1;
                   acc[r] = (u == 0) ? code : (acc[r] | (code << (2 * u)));
+                  // fold the step's code now: without this the scheduler keeps
+                  // every step's comparison masks alive in scalar registers
+                  __asm__ volatile("" : "+v"(acc[r]));
                 }
               }
               dg = lf;
@@ -219,51 +287,39 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
             bot = left[RHO - 1];
             botx = lx[RHO - 1];
           }
-          if (kHist && FULL) {
-            bhist[u] = bot;
-            if (MODE != MODE_DIST) bxhist[u] = botx;
-          } else if (has_next && lane == kWave - 1 && (FULL || (j >= 0 && j < N))) {
-            bor[j & (kRing - 1)] = bot;
-            if (MODE != MODE_DIST) box[j & (kRing - 1)] = botx;
+          if (lane == kWave - 1) {   // staged in LDS, stored at the next group's start
+            stg_r[u] = bot;
+            if (kAux) stg_x[u] = botx;
           }
-        }
-        if (kHist && FULL && has_next && lane == kWave - 1) {   // 16 bottom-row cells at once
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            bor[(tg + u - (kWave - 1)) & (kRing - 1)] = bhist[u];
-            if (MODE != MODE_DIST) box[(tg + u - (kWave - 1)) & (kRing - 1)] = bxhist[u];
-          }
-        }
-        if (MODE == MODE_PATH) {
-          const int w = tg >> 4;
-#pragma unroll
-          for (int r = 0; r < RHO; ++r)
-            a.codes[pd.code_base + ((int64_t)(s * pd.WT + w) * RHO + r) * kWave + lane] = acc[r];
         }
       };
+
+      // Memory order within a group: the previous group's stores, then the
+      // next group's loads, then 16 sweep steps with no global memory access,
+      // then the check of the loads.  Loads and stores share one in-order
+      // counter, so a store issued after a load would have to complete
+      // before the load's value may be used.
       for (int tb = 0; tb < tcnt; tb += 16) {
         const int tg = t0 + tb;
+        if (lane < 16) {   // this group's upper input, ready and checked
+          binr[lane] = has_prev && tg + lane < N ? pr : INF;
+          if (kAux) binx[lane] = has_prev ? px : 0;
+        }
+        __syncthreads();
+        if (tg > 0) publish(tg - 16);
+        fetch(tg + 16);                // next group's input, in flight during the sweep
         if (tg >= kWave - 1 && tg + 16 <= N) group16(std::true_type{}, tb);
         else group16(std::false_type{}, tb);
+        if (tg + 16 < Tend) settle(tg + 16);
       }
-      __syncthreads();
-      if (has_next) {   // publish the bottom-row columns finished in this chunk
-        const int jend = t0 + tcnt - (kWave - 1);
-        const int j = t0 - (kWave - 1) + lane;
-        if (j >= 0 && j < N && j < jend) {
-          st_dev(r_row + j, bor[j & (kRing - 1)]);
-          if (MODE != MODE_DIST) st_dev(aux_out + j, box[j & (kRing - 1)]);
-        }
-        mem_drain();
-        if (lane == 0) st_dev(prog_out, min(N, max(0, jend)));
-      }
-      if (more && lane < kChunk) {
+      if (more) {
         const int j = t0 + kChunk + lane;
 #pragma unroll
         for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
       }
       __syncthreads();
     }
+    publish(Tend - 16);
     // every lane ends with left[r] = r(ib + r, N - 1)
     if (ib <= M - 1 && M - 1 < ib + RHO) {
       const int rl = M - 1 - ib;
@@ -307,7 +363,7 @@ __global__ void chain_kernel(const PairDesc* __restrict__ pairs, int n_pairs,
       for (int q = s - 1; q >= 0; --q) seg[pd.item_base + q] = make_int2(-1, -1);
       return;
     }
-    e = bnd_aux[pd.aux_base + (int64_t)(s - 1) * pd.N + jp];
+    e = bnd_aux[pd.row_base + (int64_t)(s - 1) * row_stride(pd.N) + jp + 63];
     jx = jp;
   }
 }
@@ -419,6 +475,15 @@ __global__ void zero_i32_kernel(int* p, int64_t n) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x)
     p[k] = 0;
+}
+
+// Sentinel fill of the strip boundary rows before a sweep.
+__global__ void fill_sent_kernel(unsigned long long* r, int64_t nr, int* x, int64_t nx) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nr; k += stride)
+    r[k] = kSentR;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nx; k += stride)
+    x[k] = kSentX;
 }
 
 // Segment offsets in forward path order (strip 0 first) and |pi| per pair.
@@ -539,19 +604,20 @@ __global__ void init_kernel(const TY* __restrict__ Y, const int64_t* __restrict_
 
 template <typename TX, typename TY, int D, int RHO>
 static hipError_t launch_fwd_t(int mode, bool euc, const FwdArgs& a, int grid, hipStream_t st) {
+  const size_t pad = 0;
   if (mode == MODE_DIST) {
     hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST, false>), dim3(grid),
-                       dim3(kWave), 0, st, a);
+                       dim3(kWave), pad, st, a);
   } else if (mode == MODE_DIST_LEN) {
     if (euc)
       hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST_LEN, true>), dim3(grid),
-                         dim3(kWave), 0, st, a);
+                         dim3(kWave), pad, st, a);
     else
       hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST_LEN, false>), dim3(grid),
-                         dim3(kWave), 0, st, a);
+                         dim3(kWave), pad, st, a);
   } else {
     hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_PATH, false>), dim3(grid),
-                       dim3(kWave), 0, st, a);
+                       dim3(kWave), pad, st, a);
   }
   return hipGetLastError();
 }
@@ -625,6 +691,15 @@ hipError_t launch_zero(int* p, int64_t n, hipStream_t st) {
   const int64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256),
                      0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_sentinels(double* r, int64_t nr, int* x, int64_t nx, hipStream_t st) {
+  const int64_t n = nr > nx ? nr : nx;
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(fill_sent_kernel, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(256), 0,
+                     st, reinterpret_cast<unsigned long long*>(r), nr, x, nx);
   return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ hipError_t launch_walk(int d, int rho, int ydtype, bool emit, const WalkArgs& a,
 hipError_t launch_chain(const PairDesc* pairs, int n_pairs, const int* bnd_aux,
                         const int* out_aux, int2* seg, int* status, hipStream_t st);
 hipError_t launch_zero(int* p, int64_t n, hipStream_t st);
+hipError_t launch_fill_sentinels(double* r, int64_t nr, int* x, int64_t nx, hipStream_t st);
 hipError_t launch_seg_prefix(const PairDesc* pairs, int n_pairs, const int* seg_len,
                              int* seg_off, int64_t* path_len, hipStream_t st);
 hipError_t launch_dba_reduce(const double* psum, const int* pcnt, const double* w, int n,

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
   for (;;) {
     if (lane == 0) s_item = atomicAdd(a.queue, 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: scalar loads below
     __syncthreads();
     if (item >= a.n_items) break;
     const int2 it = a.items[item];
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
   for (;;) {
     if (lane == 0) s_item = atomicAdd(a.queue, 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: scalar loads below
     __syncthreads();
     if (item >= a.n_items) break;
     const int2 it = a.items[item];

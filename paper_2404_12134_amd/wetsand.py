@@ -59,6 +59,8 @@ def load():
         "wts_medoid": [P, P, P, P, P, P, SZ, P],
         "wts_init_barycenter": [P, P, I32, I32, P, P, P],
         "wts_precond_step": [P, P, P, I64, I32, D, P],
+        "wts_plan_timing": [P, I32],
+        "wts_plan_sweep_ms": [P, ctypes.c_int, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -77,7 +79,8 @@ def exported_symbols():
     """Names the binding expects the library to export."""
     return ["wts_plan_create", "wts_plan_destroy", "wts_workspace_bytes", "wts_last_error",
             "wts_dtw_align", "wts_dba_iterate", "wts_anomaly_score", "wts_softdtw_forward",
-            "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step"]
+            "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step",
+            "wts_plan_timing", "wts_plan_sweep_ms"]
 
 
 def _check(rc: int):
@@ -133,6 +136,17 @@ class Plan:
             ws = (raw, nbytes, raw[shift:shift + nbytes])
             self._ws[op] = ws
         return ws[2]
+
+    def enable_timing(self, max_launches: int = 256):
+        """Bracket every sweep kernel of this plan with HIP events (eager use only)."""
+        _check(load().wts_plan_timing(self._h, int(max_launches)))
+
+    def sweep_ms(self, op: int):
+        """(total ms, launches) of the sweep kernels of `op` recorded since the last query."""
+        tot = ctypes.c_double(0.0)
+        cnt = ctypes.c_int32(0)
+        _check(load().wts_plan_sweep_ms(self._h, int(op), ctypes.byref(tot), ctypes.byref(cnt)))
+        return tot.value, cnt.value
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -303,3 +317,102 @@ def precond_step(bary: torch.Tensor, grad: torch.Tensor, row_mass: torch.Tensor,
     _check(load().wts_precond_step(_ptr(bary), _ptr(grad), _ptr(row_mass), int(L), int(d),
                                    float(eta), _stream()))
     return bary
+
+
+# ------------------------------------------------------------------ drivers
+
+class DBARunner:
+    """Runs DBA iterations on a fixed plan.  With graph=True the two
+    ping-pong iterations (A -> B -> A) are captured once into a hipGraph
+    (torch.cuda.CUDAGraph on the plan's device) and replayed; every kernel of
+    an iteration, including the zeroing of the sweep's counters, is in it."""
+
+    def __init__(self, plan: Plan, cycles: torch.Tensor, bary0: torch.Tensor,
+                 weights: Optional[torch.Tensor] = None, graph: bool = True):
+        self.plan, self.cycles, self.weights = plan, cycles, weights
+        dev = _dev(plan)
+        self.A = bary0.detach().to(device=dev, dtype=torch.float64).contiguous().clone()
+        self.B = torch.empty_like(self.A)
+        self.counts = torch.empty(plan.L, dtype=torch.int64, device=dev)
+        self.dist = torch.empty(plan.n, dtype=torch.float64, device=dev)
+        plan.workspace(OP_DBA)
+        self.graph = None
+        if graph:
+            s = torch.cuda.Stream(device=dev)
+            s.wait_stream(torch.cuda.current_stream(dev))
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                self._two()
+            torch.cuda.current_stream(dev).wait_stream(s)
+            self.graph = g
+
+    def _two(self):
+        dba_iterate(self.plan, self.A, self.cycles, self.weights, self.B, self.counts, self.dist)
+        dba_iterate(self.plan, self.B, self.cycles, self.weights, self.A, self.counts, self.dist)
+
+    def run(self, iters: int) -> torch.Tensor:
+        """Applies `iters` DBA iterations to the current barycenter; returns it."""
+        for _ in range(iters // 2):
+            if self.graph is not None:
+                self.graph.replay()
+            else:
+                self._two()
+        if iters % 2:
+            dba_iterate(self.plan, self.A, self.cycles, self.weights, self.B, self.counts,
+                        self.dist)
+            self.A, self.B = self.B, self.A
+        return self.A
+
+
+def subset_plans(offsets, d: int, dtype: str, L: int, max_ckpt_bytes: int, device: int = 0):
+    """Splits a batch into consecutive cycle groups whose Soft-DTW checkpoint
+    buffer stays below max_ckpt_bytes.  Returns [(first, last+1, plan)].
+
+    Groups are grown greedily with a per-cycle size estimate (strip rows plus
+    the 16-step sweep states) and then checked against the plan's own count."""
+    off = np.asarray(offsets, dtype=np.int64)
+    n = off.size - 1
+    strips = -(-L // 128)
+
+    def est(k):
+        N = int(off[k + 1] - off[k])
+        wt = -(-(N + 63) // 16)
+        return strips * N * 8 + strips * wt * 3 * 64 * 8
+
+    groups, a = [], 0
+    while a < n:
+        b, tot = a, 0
+        while b < n and (b == a or tot + est(b) <= max_ckpt_bytes):
+            tot += est(b)
+            b += 1
+        while True:
+            plan = Plan(off[a:b + 1] - off[a], d, dtype, L, device=device)
+            if b == a + 1 or plan.workspace_bytes(OP_SOFT_FWD) <= max_ckpt_bytes:
+                break
+            plan.close()
+            b -= 1
+        groups.append((a, b, plan))
+        a = b
+    return groups
+
+
+def softdtw_descent_step(groups, cycles: torch.Tensor, offsets, bary: torch.Tensor,
+                         gamma: float, grad_value: torch.Tensor, eta: float):
+    """One preconditioned Soft-DTW descent step over cycle groups: forward and
+    backward per group (checkpoints freed between groups), gradients and row
+    masses summed group by group, then bary <- bary - eta G / (2 h)."""
+    off = np.asarray(offsets, dtype=np.int64)
+    G = torch.zeros_like(bary)
+    H = torch.zeros(bary.shape[0], dtype=torch.float64, device=bary.device)
+    values = torch.empty(off.size - 1, dtype=torch.float64, device=bary.device)
+    for a, b, plan in groups:
+        Y = cycles[int(off[a]):int(off[b])]
+        v, ck = softdtw_forward(plan, bary, Y, gamma)
+        g, h = softdtw_backward(plan, bary, Y, gamma, ck, grad_value[a:b].contiguous(),
+                                with_mass=True)
+        del ck
+        values[a:b] = v
+        G += g
+        H += h
+    precond_step(bary, G, H, eta)
+    return values
