@@ -5,9 +5,10 @@
 //   r(-1,-1) = 0, r(i,-1) = r(-1,j) = +inf,
 //   r(i,j) = delta(x_i, y_j) + min(r(i-1,j-1), r(i-1,j), r(i,j-1)),
 // all in float64, delta = e_0*e_0 then fma(e_c, e_c, s) (Def. 3, squared
-// Euclidean).  The argmin code of a cell is the first of diag (0), up (1),
-// left (2) that attains the minimum; following the codes back from
-// (M-1, N-1) gives the optimal path that Eq. 8 divides by.
+// Euclidean).  The argmin of a cell is the first of diag, up, left that
+// attains the minimum, kept as two bits (diagonal chosen; else up chosen);
+// following them back from (M-1, N-1) gives the optimal path that Eq. 8
+// divides by.
 #include <climits>
 #include <type_traits>
 
@@ -59,6 +60,15 @@ __device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, d
 __device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, int v) {
   __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 16);
 }
+// acc * 2 + b in one instruction: the carry-in of v_addc is the lane mask of
+// the comparison that produced b.
+__device__ __forceinline__ uint32_t push_bit(uint32_t acc, bool b) {
+  uint32_t r;
+  unsigned long long carry_out;
+  const unsigned long long m = __builtin_amdgcn_ballot_w64(b);
+  __asm__("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(r), "=s"(carry_out) : "v"(acc), "s"(m));
+  return r;
+}
 __device__ __forceinline__ bool is_sent(double v) {
   return (unsigned long long)__double_as_longlong(v) == kSentR;
 }
@@ -71,11 +81,15 @@ template <typename TX, typename TY, int D, int RHO, int MODE, bool EUC>
 __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
   constexpr int H = kWave * RHO;
   constexpr bool kAux = MODE != MODE_DIST;
-  __shared__ double ys[D][kRing];
+  // Y ring; slots kRing .. kRing+15 mirror slots 0 .. 15, so a group of 16
+  // steps reads consecutive slots from one base without wrapping
+  __shared__ double ys[D][kRing + 16];
   __shared__ double binr[16];   // strip above, this group's 16 columns
   __shared__ int binx[16];
-  __shared__ double stg_r[16];  // lane 63's bottom row of the last group
-  __shared__ int stg_x[16];
+  // lane 63's bottom row of the last group; the other lanes write the same
+  // steps into a scratch area (no exec-mask switch around the write)
+  __shared__ double stg_r[16 + kWave + 16];
+  __shared__ int stg_x[16 + kWave + 16];
   __shared__ int s_item;
 
   const int lane = threadIdx.x;
@@ -194,6 +208,10 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
       for (int c = 0; c < D; ++c) yv[c] = j < N ? yv[c] : 0.0;
 #pragma unroll
       for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
+      if ((j & (kRing - 1)) < 16) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) ys[c][(j & (kRing - 1)) + kRing] = yv[c];
+      }
     }
 
     for (int t0 = 0; t0 < Tend; t0 += kChunk) {
@@ -216,8 +234,10 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
         double yn[D];
         double bn;
         int bxn = 0;
+        const int yb = (tg - lane) & (kRing - 1);   // slot of step 0's column
+        const int sb = lane == kWave - 1 ? 0 : 16 + lane;   // staging slot of step 0
 #pragma unroll
-        for (int c = 0; c < D; ++c) yn[c] = ys[c][(tg - lane) & (kRing - 1)];
+        for (int c = 0; c < D; ++c) yn[c] = ys[c][yb];
         bn = binr[0];
         if (MODE == MODE_DIST_LEN) bxn = binx[0];
 #pragma unroll
@@ -231,7 +251,7 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
           const int bxv = bxn;
           if (u + 1 < 16) {
 #pragma unroll
-            for (int c = 0; c < D; ++c) yn[c] = ys[c][(j + 1) & (kRing - 1)];
+            for (int c = 0; c < D; ++c) yn[c] = ys[c][yb + u + 1];
             bn = binr[u + 1];
             if (MODE == MODE_DIST_LEN) bxn = binx[u + 1];
           }
@@ -249,6 +269,9 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
           const double dg0 = upprev;
           upprev = upin;
           upprevx = upinx;
+          bool isd_r[RHO], isu_r[RHO];   // argmin of each row's cell (PATH)
+#pragma unroll
+          for (int r = 0; r < RHO; ++r) { isd_r[r] = false; isu_r[r] = false; }
           if (FULL || (j >= 0 && j < N)) {
             double dg = dg0, up = upin;
             int dgx = dgx0, upx = upinx;
@@ -268,14 +291,8 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
                 const int t1 = __builtin_unpredictable(isu) ? upx : lx[r];
                 const int sel = __builtin_unpredictable(isd) ? dgx : t1;
                 rxv = MODE == MODE_DIST_LEN ? sel + 1 : sel;
-                if (MODE == MODE_PATH) {
-                  const uint32_t c1 = __builtin_unpredictable(isu) ? 1u : 2u;
-                  const uint32_t code = __builtin_unpredictable(isd) ? 0u : c1;
-                  acc[r] = (u == 0) ? code : (acc[r] | (code << (2 * u)));
-                  // fold the step's code now: without this the scheduler keeps
-                  // every step's comparison masks alive in scalar registers
-                  __asm__ volatile("" : "+v"(acc[r]));
-                }
+                isd_r[r] = isd;
+                isu_r[r] = isu;
               }
               dg = lf;
               dgx = lx[r];
@@ -287,10 +304,14 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
             bot = left[RHO - 1];
             botx = lx[RHO - 1];
           }
-          if (lane == kWave - 1) {   // staged in LDS, stored at the next group's start
-            stg_r[u] = bot;
-            if (kAux) stg_x[u] = botx;
+          if (MODE == MODE_PATH) {
+            // every step of every lane shifts two bits into the row's code
+            // word (cells outside the grid shift in don't-care bits)
+#pragma unroll
+            for (int r = 0; r < RHO; ++r) acc[r] = push_bit(push_bit(acc[r], isd_r[r]), isu_r[r]);
           }
+          stg_r[sb + u] = bot;   // staged in LDS, stored at the next group's start
+          if (kAux) stg_x[sb + u] = botx;
         }
       };
 
@@ -316,6 +337,10 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
         const int j = t0 + kChunk + lane;
 #pragma unroll
         for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
+        if ((j & (kRing - 1)) < 16) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) ys[c][(j & (kRing - 1)) + kRing] = yv[c];
+        }
       }
       __syncthreads();
     }
@@ -438,13 +463,14 @@ __global__ __launch_bounds__(kWave) void walk_kernel(WalkArgs a) {
           blk[ww - wlo][rr][lane] = codes[((int64_t)ww * RHO + rr) * kWave + lane];
       __syncthreads();
     }
-    const uint32_t code = (blk[w - wlo][r][k] >> (2 * (t & 15))) & 3u;
-    if (code == 2u) {
+    // step u of a word: bit 31-2u = diagonal chosen, bit 30-2u = up chosen
+    const uint32_t code = (blk[w - wlo][r][k] >> (30 - 2 * (t & 15))) & 3u;
+    if (code == 0u) {   // left
       --j;
     } else {
       if (!EMIT && lane == 0) { run_lo[q] = j; run_hi[q] = hi; }
       --i;
-      if (code == 0u) --j;
+      if (code & 2u) --j;   // diagonal
       hi = j;
     }
   }
