@@ -84,8 +84,8 @@ enum { WTS_INIT_EUCLID_MEAN = 0, WTS_INIT_NEAREST = 1, WTS_INIT_COPY = 2 };
 typedef struct {
   int32_t cost;       /* WTS_COST_* for wts_dtw_align / wts_anomaly_score; DBA, Soft-DTW and
                          the medoid always use the squared cost                              */
-  int32_t rho;        /* barycenter rows per lane in the wavefront sweep (0 = tuned default;
-                         1, 2, 4 or 8)                                                        */
+  int32_t rho;        /* barycenter rows per lane in the wavefront sweep (0 = default 4;
+                         2 or 4)                                                              */
   int32_t grid;       /* workgroups of the persistent sweep (0 = tuned default)              */
   int32_t reserved;   /* must be 0                                                           */
 } wts_opts;

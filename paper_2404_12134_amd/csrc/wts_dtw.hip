@@ -77,8 +77,10 @@ __device__ __forceinline__ bool is_sent(double v) {
 // (float64 registers), the cumulative cost of those rows at the previous
 // column (`left`) and, for the row above its first row, the value received
 // one step earlier (`upprev`, the diagonal predecessor).
+// The value sweep (medoid) runs on many items at once and is held to five
+// resident wavefronts per SIMD; the other modes keep their registers.
 template <typename TX, typename TY, int D, int RHO, int MODE, bool EUC>
-__global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
+__global__ __launch_bounds__(kWave, MODE == MODE_DIST && D <= 4 ? 5 : 1) void dtw_fwd_kernel(FwdArgs a) {
   constexpr int H = kWave * RHO;
   constexpr bool kAux = MODE != MODE_DIST;
   // Y ring; slots kRing .. kRing+15 mirror slots 0 .. 15, so a group of 16
@@ -167,7 +169,11 @@ __global__ __launch_bounds__(kWave) void dtw_fwd_kernel(FwdArgs a) {
       if (__all(ready())) return;   // the usual case: the prefetch found every value
       int polls = 0;
       do {
-        __builtin_amdgcn_s_sleep(2);
+        // back off: a strip that has caught up with the one above waits for
+        // up to a group of its steps
+        if (polls < 4) __builtin_amdgcn_s_sleep(2);
+        else if (polls < 16) __builtin_amdgcn_s_sleep(8);
+        else __builtin_amdgcn_s_sleep(32);
         if (++polls > kSpinLimit) {   // never expected: report and carry on
           if (lane == 0) atomicOr(a.status, kStatusSpinTimeout);
           gave_up = true;
@@ -428,6 +434,8 @@ __global__ __launch_bounds__(kWave) void walk_kernel(WalkArgs a) {
     return;
   }
   int wlo = 1 << 30, whi = -1;
+  uint32_t cw[RHO];
+  int ck = -1, cwk = -1;
   int cnt = 0;
   int32_t* out = nullptr;
   int seg_len = 0;
@@ -453,20 +461,39 @@ __global__ __launch_bounds__(kWave) void walk_kernel(WalkArgs a) {
     const int k = q / RHO, r = q - k * RHO;
     const int t = j + k;
     const int w = t >> 4;
-    if (w < wlo || w > whi) {
-      __syncthreads();
-      wlo = max(0, w - kWalkWords + 1);
-      whi = w;
-      for (int ww = wlo; ww <= whi; ++ww)
+    if (k != ck || w != cwk) {   // the RHO words of (lane k, word w) into registers
+      if (w < wlo || w > whi) {
+        __syncthreads();
+        wlo = max(0, w - kWalkWords + 1);
+        whi = w;
+        for (int ww = wlo; ww <= whi; ++ww)
 #pragma unroll
-        for (int rr = 0; rr < RHO; ++rr)
-          blk[ww - wlo][rr][lane] = codes[((int64_t)ww * RHO + rr) * kWave + lane];
-      __syncthreads();
+          for (int rr = 0; rr < RHO; ++rr)
+            blk[ww - wlo][rr][lane] = codes[((int64_t)ww * RHO + rr) * kWave + lane];
+        __syncthreads();
+      }
+#pragma unroll
+      for (int rr = 0; rr < RHO; ++rr) cw[rr] = blk[w - wlo][rr][k];
+      ck = k;
+      cwk = w;
     }
+    uint32_t word = cw[0];
+#pragma unroll
+    for (int rr = 1; rr < RHO; ++rr) word = r == rr ? cw[rr] : word;
     // step u of a word: bit 31-2u = diagonal chosen, bit 30-2u = up chosen
-    const uint32_t code = (blk[w - wlo][r][k] >> (30 - 2 * (t & 15))) & 3u;
+    const int u = t & 15;
+    const uint32_t code = (word >> (30 - 2 * u)) & 3u;
     if (code == 0u) {   // left
       --j;
+      if (!EMIT && u > 0) {
+        // the cells (i, j), (i, j-1), ... of this word that are left moves
+        // too: their fields (steps u-1, u-2, ...) sit above this one
+        const uint32_t rest = word >> (32 - 2 * u);
+        int more = rest == 0u ? u : (int)(__builtin_ctz(rest) >> 1);
+        if (i == i0) more = min(more, j - jstop);   // the run ends at the entry cell
+        j -= more;
+        cnt += more;
+      }
     } else {
       if (!EMIT && lane == 0) { run_lo[q] = j; run_hi[q] = hi; }
       --i;
