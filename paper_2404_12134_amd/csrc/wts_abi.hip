@@ -45,9 +45,12 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // sweep items and the sizes of the buffers the sweep needs.
 struct PairSet {
   std::vector<PairDesc> pairs;
-  std::vector<int2> items, items_rev;   // strips ascending / descending within each pair
+  std::vector<int2> items;         // pair-major, strips ascending (walk, chain, segments)
+  std::vector<int2> sweep_items;   // pop order of the forward sweeps
+  std::vector<int2> items_rev;     // pop order of the Soft-DTW backward (strips descending)
   PairDesc* d_pairs = nullptr;
   int2* d_items = nullptr;
+  int2* d_sweep_items = nullptr;
   int2* d_items_rev = nullptr;
   int n_pairs = 0, n_items = 0, n_flags = 0;
   int64_t code_words = 0, bnd_elems = 0, aux_strip_elems = 0, state_elems = 0, row_elems = 0;
@@ -58,6 +61,8 @@ struct Job {
   int64_t x_off, y_off;
   int32_t M, N, out;
 };
+
+constexpr size_t kSweepBlock = 64;   // pairs per block of the sweep pop order
 
 void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
   const int H = wts::kWave * rho;
@@ -92,9 +97,26 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
     flags += d.S;
     rows += (int64_t)d.S * ((jb.N + wts::kWave - 1 + 3) & ~3);   // strip row stride RS
     for (int s = 0; s < d.S; ++s) ps.items.push_back(make_int2((int)p, s));
-    for (int s = d.S - 1; s >= 0; --s) ps.items_rev.push_back(make_int2((int)p, s));
     ps.pairs.push_back(d);
     ps.max_rows = std::max<int64_t>(ps.max_rows, jb.M);
+  }
+  // Sweep pop order: blocks of kSweepBlock pairs (largest first), strip-major
+  // inside a block.  A strip is popped a block's worth of items after the
+  // strip it waits on, which by then has usually moved ahead, instead of
+  // right after it.  Every strip still follows its predecessor in the list,
+  // so a wait is always on an item some running workgroup already holds.
+  ps.sweep_items.clear();
+  ps.items_rev.clear();
+  for (size_t b0 = 0; b0 < ps.pairs.size(); b0 += kSweepBlock) {
+    const size_t b1 = std::min(ps.pairs.size(), b0 + kSweepBlock);
+    int smax = 0;
+    for (size_t q = b0; q < b1; ++q) smax = std::max(smax, ps.pairs[q].S);
+    for (int s = 0; s < smax; ++s)
+      for (size_t q = b0; q < b1; ++q)
+        if (s < ps.pairs[q].S) ps.sweep_items.push_back(make_int2((int)q, s));
+    for (int s = smax - 1; s >= 0; --s)
+      for (size_t q = b0; q < b1; ++q)
+        if (s < ps.pairs[q].S) ps.items_rev.push_back(make_int2((int)q, s));
   }
   ps.n_pairs = (int)ps.pairs.size();
   ps.n_items = (int)ps.items.size();
@@ -244,7 +266,7 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
                                      mode == wts::MODE_DIST ? 0 : ps.row_elems, st));
   wts::FwdArgs a{};
   a.pairs = ps.d_pairs;
-  a.items = ps.d_items;
+  a.items = ps.d_sweep_items;
   a.n_items = ps.n_items;
   a.queue = at<int>(ws, l.queue);
   a.status = at<int>(ws, l.queue) + 1;
@@ -376,6 +398,9 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
     if ((e = hipMalloc(&ps->d_pairs, sizeof(PairDesc) * ps->pairs.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
     if ((e = hipMalloc(&ps->d_items, sizeof(int2) * ps->items.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
     if ((e = hipMalloc(&ps->d_items_rev, sizeof(int2) * ps->items_rev.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&ps->d_sweep_items, sizeof(int2) * ps->sweep_items.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+    if ((e = hipMemcpy(ps->d_sweep_items, ps->sweep_items.data(), sizeof(int2) * ps->sweep_items.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup_fail(e, "hipMemcpy");
     if ((e = hipMemcpy(ps->d_items_rev, ps->items_rev.data(), sizeof(int2) * ps->items_rev.size(), hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup_fail(e, "hipMemcpy");
     if ((e = hipMemcpy(ps->d_pairs, ps->pairs.data(), sizeof(PairDesc) * ps->pairs.size(), hipMemcpyHostToDevice)) != hipSuccess)
@@ -435,6 +460,7 @@ void wts_plan_destroy(wts_plan* p) {
     if (ps->d_pairs) (void)hipFree(ps->d_pairs);
     if (ps->d_items) (void)hipFree(ps->d_items);
     if (ps->d_items_rev) (void)hipFree(ps->d_items_rev);
+    if (ps->d_sweep_items) (void)hipFree(ps->d_sweep_items);
   }
   if (p->d_off) (void)hipFree(p->d_off);
   if (p->d_path_base) (void)hipFree(p->d_path_base);
@@ -552,7 +578,7 @@ wts_status wts_softdtw_forward(const wts_plan* p, const double* bary, const void
   HIP_TRY(wts::launch_zero(at<int>(ckpt, l.progress), ps.n_flags, st));
   wts::SoftArgs a{};
   a.pairs = ps.d_pairs;
-  a.items = ps.d_items;
+  a.items = ps.d_sweep_items;
   a.n_items = ps.n_items;
   a.queue = at<int>(ckpt, l.queue);
   a.status = at<int>(ckpt, l.queue) + 1;
