@@ -278,6 +278,7 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
   a.out_dist = out_dist ? out_dist : at<double>(ws, l.out_dist);
   a.out_aux = at<int>(ws, l.out_aux);
   a.cost_kind = euc ? 1 : 0;
+  a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
   const int tk = timing_begin(p, x_is_cycle ? WTS_OP_MEDOID : (mode == wts::MODE_PATH ? WTS_OP_DBA : WTS_OP_SCORE), st);
   HIP_TRY(wts::launch_fwd(p->d, p->rho, mode, euc, x_is_cycle, p->dtype, a,
                           default_grid(p, ps), st));

@@ -95,6 +95,7 @@ struct FwdArgs {
   double* out_dist;      // [pair slot] r(M-1, N-1)
   int* out_aux;          // [pair slot] |pi| (DIST_LEN) or entry code of (M-1, N-1) (PATH)
   int cost_kind;         // 0 squared, 1 Euclidean (sqrt)
+  int relaxed_wait;      // 1: far more items than resident wavefronts; wait with long sleeps
 };
 
 struct SoftArgs {

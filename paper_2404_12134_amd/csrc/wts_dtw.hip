@@ -170,10 +170,12 @@ __global__ __launch_bounds__(kWave, MODE == MODE_DIST && D <= 4 ? 5 : 1) void dt
       int polls = 0;
       do {
         // back off: a strip that has caught up with the one above waits for
-        // up to a group of its steps
-        if (polls < 4) __builtin_amdgcn_s_sleep(2);
-        else if (polls < 16) __builtin_amdgcn_s_sleep(8);
-        else __builtin_amdgcn_s_sleep(32);
+        // up to a group of the other strip's steps.  With many items per
+        // SIMD the other resident wavefronts use the time, so the strip
+        // sleeps long and polls rarely (each poll costs issue slots).
+        if (polls < 2) __builtin_amdgcn_s_sleep(2);
+        else if (!a.relaxed_wait) __builtin_amdgcn_s_sleep(8);
+        else __builtin_amdgcn_s_sleep(64);
         if (++polls > kSpinLimit) {   // never expected: report and carry on
           if (lane == 0) atomicOr(a.status, kStatusSpinTimeout);
           gave_up = true;
