@@ -428,13 +428,11 @@ __global__ __launch_bounds__(kWave) void walk_kernel(WalkArgs a) {
 
   int i = iend, j = sg.x, hi = sg.x;
   const int jstop = sg.y;
-  if (sg.x < 0 || sg.x >= pd.N || sg.y < 0 || sg.y > sg.x) {   // chain reported a bad path
-    if (lane == 0 && !EMIT) {
-      a.seg_len[item] = 0;
-      atomicOr(a.status, kStatusBadPath);
-    }
-    return;
-  }
+  // An inconsistent path (the chain reported one, or the walk leaves the
+  // strip) is flagged in the status word; the strip then contributes empty
+  // row runs, so no later access depends on the bad path.
+  bool bad = sg.x < 0 || sg.x >= pd.N || sg.y < 0 || sg.y > sg.x;
+  if (bad && lane == 0) atomicOr(a.status, kStatusBadPath);
   int wlo = 1 << 30, whi = -1;
   uint32_t cw[RHO];
   int ck = -1, cwk = -1;
@@ -445,9 +443,10 @@ __global__ __launch_bounds__(kWave) void walk_kernel(WalkArgs a) {
     out = a.paths + 2 * (a.path_base[pd.out] + a.seg_off[item]);
     seg_len = a.seg_len[item];
   }
-  for (;;) {
+  while (!bad) {
     if (i < i0 || j < 0 || (EMIT && cnt >= seg_len)) {   // left the strip: inconsistent tags
       if (lane == 0) atomicOr(a.status, kStatusBadPath);
+      bad = true;
       break;
     }
     if (EMIT && lane == 0) {
@@ -504,13 +503,13 @@ __global__ __launch_bounds__(kWave) void walk_kernel(WalkArgs a) {
     }
   }
   if (EMIT) return;
-  if (lane == 0) a.seg_len[item] = cnt;
+  if (lane == 0) a.seg_len[item] = bad ? 0 : cnt;
   if (a.psum == nullptr) return;
   __syncthreads();
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const int nrows = iend - i0 + 1;
   for (int q = lane; q < nrows; q += kWave) {
-    const int lo = run_lo[q], h = run_hi[q];
+    const int lo = bad ? 0 : run_lo[q], h = bad ? -1 : run_hi[q];
     const int64_t o = ((int64_t)pd.out * a.L + i0 + q);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
