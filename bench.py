@@ -85,11 +85,17 @@ def traffic_from_profiles(kernel: str):
     return rec.get("bytes_per_launch")
 
 
-KERNELS = {   # rocprofv3 kernel-name prefix -> key used in profiles/traffic.json
-    "medoid": "void wts::(anonymous namespace)::dtw_fwd_kernel<float, float, 3, 4, 0, false>",
-    "dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, 4, 2, false>",
-    "score": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, 4, 1, false>",
+KERNELS = {   # sweep -> rocprofv3 kernel name, by rows per lane (rho) of the plan
+    "medoid": "void wts::(anonymous namespace)::dtw_fwd_kernel<float, float, 3, {rho}, 0, false>",
+    "dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, {rho}, 2, false>",
+    "score": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, {rho}, 1, false>",
 }
+
+
+def kernel_pattern(key: str):
+    import re
+    pre, post = KERNELS[key].split("{rho}")
+    return re.compile(re.escape(pre) + r"\d+" + re.escape(post))
 
 
 def ingest_traffic(root: str):
@@ -100,6 +106,15 @@ def ingest_traffic(root: str):
     writes), tagged with the current kernel source hash."""
     import csv
     import glob
+    # every pass must have run the current kernel source (its --only line says which)
+    hashes = set()
+    for f in glob.glob(os.path.join(root, "**", "*.out"), recursive=True):
+        for line in open(f, errors="replace"):
+            if line.startswith("{") and '"phase"' in line:
+                hashes.add(json.loads(line).get("source_hash"))
+    if hashes != {kernel_source_hash()}:
+        raise SystemExit("counter passes under %s ran kernel sources %s, not the current %s"
+                         % (root, sorted(map(str, hashes)), kernel_source_hash()))
     per_dispatch = {}      # counters come in several rows per dispatch: sum them
     for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(f)):
@@ -118,11 +133,14 @@ def ingest_traffic(root: str):
     f_scale, w_scale = gib / f_cal, gib / w_cal        # bytes per counted KiB
     out = {"_calibration": {"copy_bytes": int(gib), "fetch_kib": f_cal, "write_kib": w_cal,
                             "fetch_scale": f_scale, "write_scale": w_scale}}
-    for key, prefix in KERNELS.items():
-        fk = [avg[k] for k in avg if k[0].startswith(prefix) and k[1] == "FETCH_SIZE"]
-        wk = [avg[k] for k in avg if k[0].startswith(prefix) and k[1] == "WRITE_SIZE"]
+    for key in KERNELS:
+        pat = kernel_pattern(key)
+        fk = [(k[0], avg[k]) for k in avg if pat.match(k[0]) and k[1] == "FETCH_SIZE"]
+        wk = [avg[k] for k in avg if pat.match(k[0]) and k[1] == "WRITE_SIZE"]
         if fk and wk:
-            out[key] = {"kernel": prefix, "source_hash": kernel_source_hash(),
+            name = fk[0][0].split("(wts::")[0]
+            fk = [v for _, v in fk]
+            out[key] = {"kernel": name, "source_hash": kernel_source_hash(),
                         "fetch_bytes": fk[0] * f_scale, "write_bytes": wk[0] * w_scale,
                         "bytes_per_launch": fk[0] * f_scale + wk[0] * w_scale}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
@@ -217,12 +235,13 @@ def only_phase(args, wts, dev):
         for _ in range(args.steps):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"phase": "copy", "bytes_read": a.numel() * 8, "bytes_written": b.numel() * 8}))
+        print(json.dumps({"phase": "copy", "bytes_read": a.numel() * 8, "bytes_written": b.numel() * 8,
+                          "source_hash": kernel_source_hash()}))
         return
     if args.only == "soft":
         soft_section(wts, dev, args.steps)
         torch.cuda.synchronize()
-        print(json.dumps({"phase": "soft"}))
+        print(json.dumps({"phase": "soft", "source_hash": kernel_source_hash()}))
         return
     w = synth.make(2)
     Y, off, dt = wts.pack_cycles(w.cycles)
@@ -242,7 +261,7 @@ def only_phase(args, wts, dev):
         else:
             wts.anomaly_score(plan, B, Y)
     torch.cuda.synchronize()
-    print(json.dumps({"phase": args.only, "L": L}))
+    print(json.dumps({"phase": args.only, "L": L, "source_hash": kernel_source_hash()}))
 
 
 def main():
@@ -361,7 +380,7 @@ def main():
     launch_s = kt[dom][0] / max(1, kt[dom][1]) / 1e3
     achieved = cells * cm / launch_s / 1e12
     peak = VALU_LANE_OPS_PEAK / 1e12
-    roofline = {"bound": "alu", "kernel": KERNELS[dom].replace("void ", ""),
+    roofline = {"bound": "alu", "kernel": KERNELS[dom].format(rho=pl.rho(op)).replace("void ", ""),
                 "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(dom),
                 "ops_per_cell": cm, "cells_per_launch": cells,

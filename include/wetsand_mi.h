@@ -84,8 +84,9 @@ enum { WTS_INIT_EUCLID_MEAN = 0, WTS_INIT_NEAREST = 1, WTS_INIT_COPY = 2 };
 typedef struct {
   int32_t cost;       /* WTS_COST_* for wts_dtw_align / wts_anomaly_score; DBA, Soft-DTW and
                          the medoid always use the squared cost                              */
-  int32_t rho;        /* barycenter rows per lane in the wavefront sweep (0 = default 4;
-                         2 or 4)                                                              */
+  int32_t rho;        /* rows per lane in the wavefront sweeps: 0 = automatic (4, or 5 for
+                         barycenter plans whose strips would just about fill every SIMD);
+                         2 or 4 for any plan, 5 for barycenter plans (the medoid then uses 4) */
   int32_t grid;       /* workgroups of the persistent sweep (0 = tuned default)              */
   int32_t reserved;   /* must be 0                                                           */
 } wts_opts;
@@ -119,6 +120,12 @@ size_t wts_workspace_bytes(const wts_plan* plan, int op);
  * forgets them. */
 wts_status wts_plan_timing(wts_plan* plan, int32_t max_launches);
 wts_status wts_plan_sweep_ms(wts_plan* plan, int op, double* total_ms, int32_t* launches);
+
+/* Rows per lane (rho) of the wavefront sweeps that operation `op` runs on this
+ * plan, as chosen at plan creation (opts.rho, or the automatic choice); it
+ * names the kernel instance a profiler shows.  Returns a value >= 1, or
+ * WTS_E_ARG for a null plan or an operation the plan cannot run. */
+int32_t wts_plan_rho(const wts_plan* plan, int op);
 
 /* Message describing the last non-OK status returned on this thread. */
 const char* wts_last_error(void);

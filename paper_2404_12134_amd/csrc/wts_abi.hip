@@ -55,6 +55,7 @@ struct PairSet {
   int n_pairs = 0, n_items = 0, n_flags = 0;
   int64_t code_words = 0, bnd_elems = 0, aux_strip_elems = 0, state_elems = 0, row_elems = 0;
   int64_t max_rows = 0;
+  int rho = 4;   // barycenter rows per lane of this set's sweeps
 };
 
 struct Job {
@@ -66,6 +67,7 @@ constexpr size_t kSweepBlock = 64;   // pairs per block of the sweep pop order
 
 void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
   const int H = wts::kWave * rho;
+  ps.rho = rho;
   std::stable_sort(jobs.begin(), jobs.end(), [](const Job& a, const Job& b) {
     return (int64_t)a.M * a.N > (int64_t)b.M * b.N;
   });
@@ -135,6 +137,21 @@ struct Layout {
   size_t rows = 0, states = 0, push_up = 0, push_dg = 0, gsum = 0, hsum = 0;
   size_t total = 0;
 };
+
+// Rows per lane of the barycenter sweeps when the caller leaves it open.
+// With about one strip per SIMD, a strip that shares its SIMD slows its whole
+// chain, and the dispatcher does not spread workgroups perfectly once they
+// cover nearly every compute unit: such batches take 5 rows per lane when
+// that brings them under ~80 % of the SIMDs.  Small batches (one strip per
+// SIMD or less) and large ones (several per SIMD) keep 4.
+int bary_rho(int64_t L, int n, int cus) {
+  auto items = [&](int r) { return (int64_t)n * ((L + 64 * r - 1) / (64 * r)); };
+  const int64_t simds = 4 * (int64_t)cus;
+  const int64_t cap = simds * 13 / 16;
+  const int64_t i4 = items(4);
+  if (i4 > cap && i4 <= 2 * simds && items(5) <= cap) return 5;
+  return 4;
+}
 
 }  // namespace
 
@@ -280,7 +297,7 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
   a.cost_kind = euc ? 1 : 0;
   a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
   const int tk = timing_begin(p, x_is_cycle ? WTS_OP_MEDOID : (mode == wts::MODE_PATH ? WTS_OP_DBA : WTS_OP_SCORE), st);
-  HIP_TRY(wts::launch_fwd(p->d, p->rho, mode, euc, x_is_cycle, p->dtype, a,
+  HIP_TRY(wts::launch_fwd(p->d, ps.rho, mode, euc, x_is_cycle, p->dtype, a,
                           default_grid(p, ps), st));
   timing_end(p, tk, st);
   return WTS_OK;
@@ -307,7 +324,7 @@ wts_status run_paths(const wts_plan* p, const double* bary, const void* cycles, 
   w.L = p->L;
   w.seg_len = at<int>(ws, l.seg_len);
   w.status = at<int>(ws, l.queue) + 1;
-  HIP_TRY(wts::launch_walk(p->d, p->rho, p->dtype, false, w, ps.n_items, st));
+  HIP_TRY(wts::launch_walk(p->d, ps.rho, p->dtype, false, w, ps.n_items, st));
   return WTS_OK;
 }
 
@@ -335,8 +352,8 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   wts_opts o{};
   if (opts) o = *opts;
   if (o.cost != WTS_COST_SQEUCLID && o.cost != WTS_COST_EUCLID) return fail(WTS_E_ARG, "opts.cost");
-  if (o.rho != 0 && o.rho != 2 && o.rho != 4)
-    return fail(WTS_E_UNSUPPORTED, "opts.rho = %d: 2 or 4 supported", o.rho);
+  if (o.rho != 0 && o.rho != 2 && o.rho != 4 && o.rho != 5)
+    return fail(WTS_E_UNSUPPORTED, "opts.rho = %d: 2, 4 or 5 supported", o.rho);
   if (o.grid < 0 || o.reserved != 0) return fail(WTS_E_ARG, "opts.grid / opts.reserved");
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev));
@@ -349,7 +366,7 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   p->dtype = dtype;
   p->L = L;
   p->opts = o;
-  p->rho = o.rho ? o.rho : 4;
+  p->rho = (o.rho == 2 || o.rho == 4) ? o.rho : 4;   // medoid sweeps: 2 or 4
   p->off.assign(offsets_host, offsets_host + n + 1);
   for (int k = 0; k < n; ++k) p->nmax = std::max(p->nmax, p->off[k + 1] - p->off[k]);
 
@@ -366,7 +383,7 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   if (L > 0) {
     for (int k = 0; k < n; ++k)
       jobs.push_back(Job{0, p->off[k], (int32_t)L, (int32_t)(p->off[k + 1] - p->off[k]), k});
-    build_set(p->bary, jobs, p->rho);
+    build_set(p->bary, jobs, o.rho ? o.rho : bary_rho(L, n, p->cus));
     build_set(p->soft, jobs, wts::kSoftRho);
     std::vector<int64_t> base(n);
     for (int k = 0; k < n; ++k) base[k] = (int64_t)k * (L - 1) + p->off[k];
@@ -453,6 +470,27 @@ wts_status wts_plan_sweep_ms(wts_plan* p, int op, double* total_ms, int32_t* lau
   return WTS_OK;
 }
 
+int32_t wts_plan_rho(const wts_plan* p, int op) {
+  if (!p) return fail(WTS_E_ARG, "plan is null");
+  switch (op) {
+    case WTS_OP_ALIGN:
+    case WTS_OP_ALIGN_PATHS:
+    case WTS_OP_DBA:
+    case WTS_OP_SCORE:
+      if (p->L <= 0) return fail(WTS_E_ARG, "plan was created with L = 0 (medoid/init only)");
+      return p->bary.rho;
+    case WTS_OP_SOFT_FWD:
+    case WTS_OP_SOFT_BWD:
+      if (p->L <= 0) return fail(WTS_E_ARG, "plan was created with L = 0 (medoid/init only)");
+      return p->soft.rho;
+    case WTS_OP_MEDOID:
+      if (p->L != 0) return fail(WTS_E_ARG, "medoid needs a plan with L = 0");
+      return p->med.rho;
+    default:
+      return fail(WTS_E_ARG, "unknown op %d", op);
+  }
+}
+
 void wts_plan_destroy(wts_plan* p) {
   if (!p) return;
   DeviceGuard g(p->device);
@@ -523,7 +561,7 @@ wts_status wts_dtw_align(const wts_plan* p, const double* bary, const void* cycl
   w.path_base = p->d_path_base;
   w.paths = paths;
   w.status = at<int>(ws, l.queue) + 1;
-  HIP_TRY(wts::launch_walk(p->d, p->rho, p->dtype, true, w, ps.n_items, st));
+  HIP_TRY(wts::launch_walk(p->d, ps.rho, p->dtype, true, w, ps.n_items, st));
   return WTS_OK;
 }
 

@@ -73,6 +73,18 @@ __device__ __forceinline__ bool is_sent(double v) {
   return (unsigned long long)__double_as_longlong(v) == kSentR;
 }
 
+// Waves per sweep workgroup.  Each wave works alone (own items, own LDS);
+// grouping four of them makes the dispatcher place one wave on each SIMD of a
+// compute unit, which one-wave workgroups do not get reliably.
+constexpr int kSweepWaves = 4;
+// Orders a wave's own LDS accesses around a point of the program; a wave's
+// LDS operations execute in order, so no hardware barrier is needed.
+__device__ __forceinline__ void wave_sync() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_wave_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // One wavefront sweeps one strip of one pair.  State per lane: RHO rows of X
 // (float64 registers), the cumulative cost of those rows at the previous
 // column (`left`) and, for the row above its first row, the value received
@@ -80,30 +92,39 @@ __device__ __forceinline__ bool is_sent(double v) {
 // The value sweep (medoid) runs on many items at once and is held to five
 // resident wavefronts per SIMD; the other modes keep their registers.
 template <typename TX, typename TY, int D, int RHO, int MODE, bool EUC>
-__global__ __launch_bounds__(kWave, MODE == MODE_DIST && D <= 4 ? 5 : 1) void dtw_fwd_kernel(FwdArgs a) {
+__global__ __launch_bounds__(kWave * kSweepWaves, MODE == MODE_DIST && D <= 4 ? 5 : 1)
+void dtw_fwd_kernel(FwdArgs a) {
   constexpr int H = kWave * RHO;
   constexpr bool kAux = MODE != MODE_DIST;
   // Y ring; slots kRing .. kRing+15 mirror slots 0 .. 15, so a group of 16
   // steps reads consecutive slots from one base without wrapping
-  __shared__ double ys[D][kRing + 16];
-  __shared__ double binr[16];   // strip above, this group's 16 columns
-  __shared__ int binx[16];
+  __shared__ double ys_[kSweepWaves][D][kRing + 16];
+  __shared__ double binr_[kSweepWaves][16];   // strip above, this group's 16 columns
+  __shared__ int binx_[kSweepWaves][16];
   // lane 63's bottom row of the last group; the other lanes write the same
   // steps into a scratch area (no exec-mask switch around the write)
-  __shared__ double stg_r[16 + kWave + 16];
-  __shared__ int stg_x[16 + kWave + 16];
-  __shared__ int s_item;
+  __shared__ double stg_r_[kSweepWaves][16 + kWave + 16];
+  __shared__ int stg_x_[kSweepWaves][16 + kWave + 16];
+  __shared__ int s_item_[kSweepWaves];
 
-  const int lane = threadIdx.x;
+  // Every wave of the workgroup is an independent sweeper with its own LDS.
+  const int wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  auto& ys = ys_[wv];
+  auto& binr = binr_[wv];
+  auto& binx = binx_[wv];
+  auto& stg_r = stg_r_[wv];
+  auto& stg_x = stg_x_[wv];
+  int& s_item = s_item_[wv];
   const TX* __restrict__ X = static_cast<const TX*>(a.x);
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const double INF = inf_d();
 
   for (;;) {
     if (lane == 0) s_item = atomicAdd(a.queue, 1);
-    __syncthreads();
+    wave_sync();
     const int item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: scalar loads below
-    __syncthreads();
+    wave_sync();
     if (item >= a.n_items) break;
     const int2 it = a.items[item];
     const PairDesc pd = uniform(a.pairs[uni(it.x)]);
@@ -334,7 +355,7 @@ __global__ __launch_bounds__(kWave, MODE == MODE_DIST && D <= 4 ? 5 : 1) void dt
           binr[lane] = has_prev && tg + lane < N ? pr : INF;
           if (kAux) binx[lane] = has_prev ? px : 0;
         }
-        __syncthreads();
+        wave_sync();
         if (tg > 0) publish(tg - 16);
         fetch(tg + 16);                // next group's input, in flight during the sweep
         if (tg >= kWave - 1 && tg + 16 <= N) group16(std::true_type{}, tb);
@@ -350,7 +371,7 @@ __global__ __launch_bounds__(kWave, MODE == MODE_DIST && D <= 4 ? 5 : 1) void dt
           for (int c = 0; c < D; ++c) ys[c][(j & (kRing - 1)) + kRing] = yv[c];
         }
       }
-      __syncthreads();
+      wave_sync();
     }
     publish(Tend - 16);
     // every lane ends with left[r] = r(ib + r, N - 1)
@@ -364,7 +385,7 @@ __global__ __launch_bounds__(kWave, MODE == MODE_DIST && D <= 4 ? 5 : 1) void dt
       a.out_dist[pd.out] = v;
       if (MODE != MODE_DIST) a.out_aux[pd.out] = vx;
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -656,22 +677,26 @@ __global__ void init_kernel(const TY* __restrict__ Y, const int64_t* __restrict_
 
 // ------------------------------------------------------------------ dispatch
 
+// `grid` counts sweep waves; the launch uses workgroups of kSweepWaves waves.
+static inline unsigned sweep_groups(int grid) {
+  return (unsigned)((grid + kSweepWaves - 1) / kSweepWaves);
+}
+
 template <typename TX, typename TY, int D, int RHO>
 static hipError_t launch_fwd_t(int mode, bool euc, const FwdArgs& a, int grid, hipStream_t st) {
-  const size_t pad = 0;
   if (mode == MODE_DIST) {
-    hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST, false>), dim3(grid),
-                       dim3(kWave), pad, st, a);
+    hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST, false>), dim3(sweep_groups(grid)),
+                       dim3(kWave * kSweepWaves), 0, st, a);
   } else if (mode == MODE_DIST_LEN) {
     if (euc)
-      hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST_LEN, true>), dim3(grid),
-                         dim3(kWave), pad, st, a);
+      hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST_LEN, true>), dim3(sweep_groups(grid)),
+                         dim3(kWave * kSweepWaves), 0, st, a);
     else
-      hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST_LEN, false>), dim3(grid),
-                         dim3(kWave), pad, st, a);
+      hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST_LEN, false>), dim3(sweep_groups(grid)),
+                         dim3(kWave * kSweepWaves), 0, st, a);
   } else {
-    hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_PATH, false>), dim3(grid),
-                       dim3(kWave), pad, st, a);
+    hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_PATH, false>), dim3(sweep_groups(grid)),
+                       dim3(kWave * kSweepWaves), 0, st, a);
   }
   return hipGetLastError();
 }
@@ -682,8 +707,8 @@ static hipError_t launch_fwd_d(int mode, bool euc, bool x_is_cycle, int ydtype,
   if (ydtype == 0) {
     if (x_is_cycle) {
       if (mode != MODE_DIST) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((dtw_fwd_kernel<float, float, D, RHO, MODE_DIST, false>), dim3(grid),
-                         dim3(kWave), 0, st, a);
+      hipLaunchKernelGGL((dtw_fwd_kernel<float, float, D, RHO, MODE_DIST, false>), dim3(sweep_groups(grid)),
+                         dim3(kWave * kSweepWaves), 0, st, a);
       return hipGetLastError();
     }
     return launch_fwd_t<double, float, D, RHO>(mode, euc, a, grid, st);
@@ -705,11 +730,38 @@ static hipError_t launch_fwd_d(int mode, bool euc, bool x_is_cycle, int ydtype,
     default: return hipErrorInvalidValue; \
   }
 
+// rho = 5 serves barycenter plans only (value+length and path sweeps).
+template <int D, int RHO>
+static hipError_t launch_fwd_bary(int mode, bool euc, bool x_is_cycle, int ydtype,
+                                  const FwdArgs& a, int grid, hipStream_t st) {
+  if (x_is_cycle || mode == MODE_DIST) return hipErrorInvalidValue;
+  const dim3 g(sweep_groups(grid)), b(kWave * kSweepWaves);
+  if (ydtype == 0) {
+    if (mode == MODE_PATH)
+      hipLaunchKernelGGL((dtw_fwd_kernel<double, float, D, RHO, MODE_PATH, false>), g, b, 0, st, a);
+    else if (euc)
+      hipLaunchKernelGGL((dtw_fwd_kernel<double, float, D, RHO, MODE_DIST_LEN, true>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((dtw_fwd_kernel<double, float, D, RHO, MODE_DIST_LEN, false>), g, b, 0, st, a);
+  } else {
+    if (mode == MODE_PATH)
+      hipLaunchKernelGGL((dtw_fwd_kernel<double, double, D, RHO, MODE_PATH, false>), g, b, 0, st, a);
+    else if (euc)
+      hipLaunchKernelGGL((dtw_fwd_kernel<double, double, D, RHO, MODE_DIST_LEN, true>), g, b, 0, st, a);
+    else
+      hipLaunchKernelGGL((dtw_fwd_kernel<double, double, D, RHO, MODE_DIST_LEN, false>), g, b, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_fwd(int d, int rho, int mode, bool euc, bool x_is_cycle, int ydtype,
                       const FwdArgs& a, int grid, hipStream_t st) {
 #define CALLF(D, R) launch_fwd_d<D, R>(mode, euc, x_is_cycle, ydtype, a, grid, st)
+#define CALLB(D, R) launch_fwd_bary<D, R>(mode, euc, x_is_cycle, ydtype, a, grid, st)
   if (rho == 4) { WTS_D_SWITCH(d, 4, CALLF) }
   if (rho == 2) { WTS_D_SWITCH(d, 2, CALLF) }
+  if (rho == 5) { WTS_D_SWITCH(d, 5, CALLB) }
+#undef CALLB
 #undef CALLF
   return hipErrorInvalidValue;
 }
@@ -729,6 +781,7 @@ hipError_t launch_walk(int d, int rho, int ydtype, bool emit, const WalkArgs& a,
                                  : launch_walk_t<double, D, R>(emit, a, n_items, st))
   if (rho == 4) { WTS_D_SWITCH(d, 4, CALLW) }
   if (rho == 2) { WTS_D_SWITCH(d, 2, CALLW) }
+  if (rho == 5) { WTS_D_SWITCH(d, 5, CALLW) }
 #undef CALLW
   return hipErrorInvalidValue;
 }

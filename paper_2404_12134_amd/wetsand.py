@@ -61,6 +61,7 @@ def load():
         "wts_precond_step": [P, P, P, I64, I32, D, P],
         "wts_plan_timing": [P, I32],
         "wts_plan_sweep_ms": [P, ctypes.c_int, P, P],
+        "wts_plan_rho": [P, ctypes.c_int],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -80,7 +81,7 @@ def exported_symbols():
     return ["wts_plan_create", "wts_plan_destroy", "wts_workspace_bytes", "wts_last_error",
             "wts_dtw_align", "wts_dba_iterate", "wts_anomaly_score", "wts_softdtw_forward",
             "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step",
-            "wts_plan_timing", "wts_plan_sweep_ms"]
+            "wts_plan_timing", "wts_plan_sweep_ms", "wts_plan_rho"]
 
 
 def _check(rc: int):
@@ -147,6 +148,12 @@ class Plan:
         cnt = ctypes.c_int32(0)
         _check(load().wts_plan_sweep_ms(self._h, int(op), ctypes.byref(tot), ctypes.byref(cnt)))
         return tot.value, cnt.value
+
+    def rho(self, op: int) -> int:
+        """Rows per lane of the sweeps `op` runs on this plan (names the kernel instance)."""
+        r = int(load().wts_plan_rho(self._h, int(op)))
+        _check(min(r, 0))
+        return r
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

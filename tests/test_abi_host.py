@@ -69,6 +69,10 @@ def test_plan_create_rejects_bad_shapes_before_any_gpu_call(lib):
     assert _create(lib, offsets=(0, 3, 3))[0] == WTS_E_SHAPE          # empty cycle
     assert _create(lib, L=-1)[0] == WTS_E_SHAPE
     assert b"length" in lib.wts_last_error() or len(lib.wts_last_error()) > 0
+    from paper_2404_12134_amd.wetsand import _Opts
+    for rho in (1, 3, 6, 8):   # rows per lane: 2, 4 or 5 only
+        assert _create(lib, opts=ctypes.byref(_Opts(0, rho, 0, 0)))[0] == WTS_E_UNSUPPORTED
+    assert _create(lib, opts=ctypes.byref(_Opts(0, 4, -1, 0)))[0] == WTS_E_ARG
 
 
 def test_null_plan_is_rejected(lib):

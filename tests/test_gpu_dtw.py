@@ -111,7 +111,7 @@ def test_euclid_cost_bitwise(wts):
     np.testing.assert_array_equal(plen, ol)
 
 
-@pytest.mark.parametrize("rho,grid", [(2, 0), (4, 1), (4, 3), (2, 7)])
+@pytest.mark.parametrize("rho,grid", [(2, 0), (4, 1), (4, 3), (2, 7), (5, 0), (5, 3)])
 def test_tile_shape_and_grid_invariance(wts, rho, grid):
     r = rng(13)
     B = r.standard_normal((600, 2))
@@ -172,10 +172,10 @@ def test_anomaly_score_bitwise(wts):
 
 # ----------------------------------------------------------------------- DBA
 
-def _dba_case(wts, w, B0, iters, weights=None):
+def _dba_case(wts, w, B0, iters, weights=None, rho=0):
     import torch
     Y, off, dt = wts.pack_cycles(w.cycles)
-    plan = wts.Plan(off, w.d, dt, B0.shape[0])
+    plan = wts.Plan(off, w.d, dt, B0.shape[0], rho=rho)
     Bg = torch.from_numpy(np.ascontiguousarray(B0)).cuda()
     Wt = None if weights is None else torch.from_numpy(np.asarray(weights, np.float64)).cuda()
     Bo = np.ascontiguousarray(B0)
@@ -211,6 +211,24 @@ def test_dba_uneven_several_strips_weighted(wts):
     _dba_case(wts, w, B0, 3)
     say("case dba c3-like weighted")
     _dba_case(wts, w, B0, 2, weights=np.linspace(0.5, 2.0, w.n))
+
+
+def test_dba_and_score_five_rows_per_lane(wts):
+    """5 rows per lane (320-row strips), the layout the plan picks by itself
+    for batches whose strips would just about fill every SIMD."""
+    import torch
+    w = synth.make(3, n=7, len_range=(40, 1400), L=970)
+    _, B0 = oracle.nearest_init(as64(w.cycles), 970)
+    say("case dba rho 5")
+    _dba_case(wts, w, B0, 2, rho=5)
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    plan = wts.Plan(off, w.d, dt, 970, rho=5)
+    assert plan.rho(wts.OP_SCORE) == 5 and plan.rho(wts.OP_DBA) == 5
+    say("case score rho 5")
+    score, dist, plen = wts.anomaly_score(plan, torch.from_numpy(B0).cuda(), Y)
+    os_, od, ol = oracle.score_batch(B0, as64(w.cycles))
+    np.testing.assert_array_equal(score.cpu().numpy(), os_)
+    np.testing.assert_array_equal(plen.cpu().numpy(), ol)
 
 
 def test_dba_fixed_point(wts):
