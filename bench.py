@@ -239,9 +239,9 @@ def only_phase(args, wts, dev):
                           "source_hash": kernel_source_hash()}))
         return
     if args.only == "soft":
-        soft_section(wts, dev, args.steps)
+        rec = soft_section(wts, dev, args.steps)
         torch.cuda.synchronize()
-        print(json.dumps({"phase": "soft", "source_hash": kernel_source_hash()}))
+        print(json.dumps({"phase": "soft", "source_hash": kernel_source_hash(), "soft_dtw": rec}))
         return
     w = synth.make(2)
     Y, off, dt = wts.pack_cycles(w.cycles)

@@ -63,7 +63,7 @@ struct Job {
   int32_t M, N, out;
 };
 
-constexpr size_t kSweepBlock = 64;   // pairs per block of the sweep pop order
+constexpr size_t kSweepBlock = 1024;   // pairs per block of the sweep pop order
 
 void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
   const int H = wts::kWave * rho;
