@@ -223,6 +223,50 @@ def soft_section(wts, dev, steps: int = 2, gamma: float = 0.1):
             "cells_per_pass": cells, "ops_per_cell": cm, "alu_frac": round(frac, 4)}
 
 
+def dba_large_section(wts, dev, iters: int = 10):
+    """DBA on the 512-cycle workload (6 channels, lengths log-uniform
+    1000..20000, L = 10000, nearest-length init): `iters` iterations replayed
+    from a captured hipGraph (two iterations per graph), plus the path
+    sweep's own launch time measured eagerly for its ALU fraction."""
+    import numpy as np
+    import torch
+    from paper_2404_12134_amd import synth
+    w = synth.make(3)
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    plan = wts.Plan(off, w.d, dt, w.L)
+    B0, _ = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
+    cells = w.L * int(w.lengths.sum())
+    plan.enable_timing(8)
+    for _ in range(3):
+        wts.dba_iterate(plan, B0, Y)
+    torch.cuda.synchronize()
+    plan.sweep_ms(wts.OP_DBA)
+    for _ in range(3):
+        wts.dba_iterate(plan, B0, Y)
+    tot, cnt = plan.sweep_ms(wts.OP_DBA)
+    sweep_s = tot / max(cnt, 1) / 1e3
+    plan.enable_timing(0)
+    st = wts.device_status(plan, wts.OP_DBA)
+    if st != 0:
+        raise RuntimeError("device status %d after the large DBA" % st)
+    runner = wts.DBARunner(plan, Y, B0, graph=True)
+    runner.run(2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    runner.run(iters)
+    e1.record()
+    torch.cuda.synchronize()
+    it_s = e0.elapsed_time(e1) / 1e3 / iters
+    cm = c_min_path(w.d)
+    return {"workload": w.name + ": %d DBA iterations replayed from a hipGraph, nearest-length "
+                                 "init" % iters,
+            "s_per_dba_iteration": round(it_s, 5), "gcups": round(cells / it_s / 1e9, 2),
+            "cells_per_iteration": cells, "rows_per_lane": plan.rho(wts.OP_DBA),
+            "path_sweep_ms": round(sweep_s * 1e3, 3), "ops_per_cell": cm,
+            "path_sweep_alu_frac": round(cells * cm / sweep_s / VALU_LANE_OPS_PEAK, 4)}
+
+
 def only_phase(args, wts, dev):
     """One phase of the step, --steps times, for rocprofv3 counter passes.  The
     'copy' phase is a plain 1 GiB device-to-device copy: the reference for
@@ -273,6 +317,8 @@ def main():
     ap.add_argument("--no-speedup", action="store_true",
                     help="skip the batched vs one-cycle-per-launch comparison")
     ap.add_argument("--no-soft", action="store_true", help="skip the Soft-DTW section")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 512-cycle DBA section")
     ap.add_argument("--soft-steps", type=int, default=2)
     ap.add_argument("--only", choices=["medoid", "dba", "score", "soft", "copy"],
                     help="run only one phase --steps times (for hardware-counter passes)")
@@ -408,6 +454,7 @@ def main():
                  "batched_s": round(tc - tb, 5), "speedup": round((tb - ta) / (tc - tb), 2)}
 
     soft = None if args.no_soft else soft_section(wts, dev, args.soft_steps)
+    large = None if args.no_large else dba_large_section(wts, dev)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
 
     line = {
@@ -424,6 +471,7 @@ def main():
         "roofline": roofline,
         "batched_vs_per_cycle": speed,
         "soft_dtw": soft,
+        "dba_large": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
