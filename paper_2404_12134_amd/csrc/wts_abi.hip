@@ -621,6 +621,7 @@ wts_status wts_softdtw_forward(const wts_plan* p, const double* bary, const void
   a.n_items = ps.n_items;
   a.queue = at<int>(ckpt, l.queue);
   a.status = at<int>(ckpt, l.queue) + 1;
+  a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
   a.progress = at<int>(ckpt, l.progress);
   a.x = bary;
   a.y = cycles;
@@ -659,6 +660,7 @@ wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const voi
   a.n_items = ps.n_items;
   a.queue = at<int>(ws, l.queue);
   a.status = at<int>(ws, l.queue) + 1;
+  a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
   a.progress = at<int>(ws, l.progress);
   a.x = bary;
   a.y = cycles;

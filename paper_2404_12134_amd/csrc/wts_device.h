@@ -116,6 +116,7 @@ struct SoftArgs {
   double* gsum;          // [n][L][d] per-cycle gradient rows
   double* hsum;          // [n][L] per-cycle row mass
   int64_t L;
+  int relaxed_wait;      // 1: far more items than resident wavefronts; wait with long sleeps
 };
 
 __device__ __forceinline__ double inf_d() { return __builtin_huge_val(); }
@@ -123,6 +124,15 @@ __device__ __forceinline__ double inf_d() { return __builtin_huge_val(); }
 // Status bits reported in the workspace status word.
 constexpr int kStatusSpinTimeout = 1;   // a strip gave up waiting for its predecessor
 constexpr int kStatusBadPath = 2;       // path recovery left the strip (inconsistent tags)
+// Sleep between two polls of a strip that waits for its neighbour: two quick
+// polls, then short sleeps, or long ones when far more items than resident
+// wavefronts keep the SIMD busy meanwhile (each poll costs issue slots).
+__device__ __forceinline__ void poll_backoff(int polls, int relaxed) {
+  if (polls < 2) __builtin_amdgcn_s_sleep(2);
+  else if (!relaxed) __builtin_amdgcn_s_sleep(8);
+  else __builtin_amdgcn_s_sleep(64);
+}
+
 // Polls of a progress counter before a strip gives up (about a second);
 // a legitimate wait is bounded by one chunk of the predecessor strip.
 constexpr int kSpinLimit = 1 << 20;

@@ -190,13 +190,9 @@ void dtw_fwd_kernel(FwdArgs a) {
       if (__all(ready())) return;   // the usual case: the prefetch found every value
       int polls = 0;
       do {
-        // back off: a strip that has caught up with the one above waits for
-        // up to a group of the other strip's steps.  With many items per
-        // SIMD the other resident wavefronts use the time, so the strip
-        // sleeps long and polls rarely (each poll costs issue slots).
-        if (polls < 2) __builtin_amdgcn_s_sleep(2);
-        else if (!a.relaxed_wait) __builtin_amdgcn_s_sleep(8);
-        else __builtin_amdgcn_s_sleep(64);
+        // a strip that has caught up with the one above waits for up to a
+        // group of the other strip's steps
+        poll_backoff(polls, a.relaxed_wait);
         if (++polls > kSpinLimit) {   // never expected: report and carry on
           if (lane == 0) atomicOr(a.status, kStatusSpinTimeout);
           gave_up = true;

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
         if (lane == 0 && !gave_up) {
           int polls = 0;
           while (ld_dev(prog_in) < need) {
-            __builtin_amdgcn_s_sleep(1);
+            poll_backoff(polls, a.relaxed_wait);
             if (++polls > kSpinLimit) {
               atomicOr(a.status, kStatusSpinTimeout);
               gave_up = true;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
         if (lane == 0 && !gave_up && need > 0) {
           int polls = 0;
           while (ld_dev(prog_below) < need) {
-            __builtin_amdgcn_s_sleep(1);
+            poll_backoff(polls, a.relaxed_wait);
             if (++polls > kSpinLimit) {
               atomicOr(a.status, kStatusSpinTimeout);
               gave_up = true;
