@@ -349,7 +349,12 @@ def main():
     mplan = wts.Plan(off, w.d, dt, 0)
     k0 = int(wts.medoid(mplan, Y, with_matrix=False)[0].item())
     L = int(lens[k0])
-    plan = wts.Plan(off, w.d, dt, L)
+    # sweep shape of the barycenter plan: picked by timing the candidates on
+    # this batch (outside the timed region)
+    from paper_2404_12134_amd import autotune
+    B0, _ = wts.init_barycenter(wts.Plan(off, w.d, dt, L), Y, wts.INIT_COPY, k0)
+    plan, tuned = autotune.tuned_plan(off, w.d, dt, L, op="dba", cycles=Y, bary=B0,
+                                      cache_path=None)
     n = w.n
     Ba = torch.empty((L, w.d), dtype=torch.float64, device=dev)
     Bb = torch.empty_like(Ba)
@@ -469,6 +474,8 @@ def main():
                         "dba_iteration": round(cells_bary / t_dba / 1e9, 2),
                         "score": round(cells_bary / t_score / 1e9, 2)},
         "roofline": roofline,
+        "autotune": {"op": "dba", "rows_per_lane": tuned["rho"], "grid": tuned["grid"],
+                     "candidates_ms": tuned["table"]},
         "batched_vs_per_cycle": speed,
         "soft_dtw": soft,
         "dba_large": large,
