@@ -148,7 +148,17 @@ def ingest_traffic(root: str):
     print(json.dumps(out))
 
 
-def cpu_baseline(w, n_sample: int = 16):
+def guarded(fn, *a, **kw):
+    """Runs an optional section; an error is reported in its record instead of
+    ending the run before the JSON line."""
+    try:
+        return fn(*a, **kw)
+    except Exception as exc:   # noqa: BLE001 -- reported, not hidden
+        print("section %s failed: %r" % (fn.__name__, exc), file=sys.stderr)
+        return {"error": repr(exc)}
+
+
+def cpu_baseline(w, n_sample: int = 40):
     """The FP64 oracle on the first n_sample cycles: all-pairs medoid, one DBA
     iteration from it and the scores.  Returns the record for the JSON line."""
     import numpy as np
@@ -223,7 +233,58 @@ def soft_section(wts, dev, steps: int = 2, gamma: float = 0.1):
             "cells_per_pass": cells, "ops_per_cell": cm, "alu_frac": round(frac, 4)}
 
 
-def dba_large_section(wts, dev, iters: int = 10):
+def dba_per_cycle_speedup(wts, plan, off, d, dt, L, Y, B, sequential=False):
+    """Batched vs one-cycle-per-launch DBA iteration: the same kernels, run
+    once on the batched plan and once per cycle on a one-cycle plan.  With
+    sequential=True the one-cycle plans are built, run and freed one at a
+    time (for batches whose workspaces do not fit side by side) and their
+    launch times, taken with HIP events, are summed; otherwise the n calls run
+    back to back between two events.  Workspaces are allocated before timing."""
+    import torch
+    n = len(off) - 1
+    Bo = torch.empty_like(B)
+    counts = torch.empty(L, dtype=torch.int64, device=B.device)
+    dist = torch.empty(n, dtype=torch.float64, device=B.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wts.dba_iterate(plan, B, Y, bary_out=Bo, counts=counts, dist=dist)
+    torch.cuda.synchronize()
+    e0.record()
+    wts.dba_iterate(plan, B, Y, bary_out=Bo, counts=counts, dist=dist)
+    e1.record()
+    torch.cuda.synchronize()
+    batched = e0.elapsed_time(e1) / 1e3
+    Ys = [Y[int(off[k]):int(off[k + 1])] for k in range(n)]
+    d1 = torch.empty(1, dtype=torch.float64, device=B.device)
+    per = 0.0
+    if sequential:
+        for k in range(n):
+            one = wts.Plan(off[k:k + 2] - off[k], d, dt, L)
+            wts.dba_iterate(one, B, Ys[k], bary_out=Bo, counts=counts, dist=d1)
+            e0.record()
+            wts.dba_iterate(one, B, Ys[k], bary_out=Bo, counts=counts, dist=d1)
+            e1.record()
+            torch.cuda.synchronize()
+            per += e0.elapsed_time(e1) / 1e3
+            one.close()
+    else:
+        single = [wts.Plan(off[k:k + 2] - off[k], d, dt, L) for k in range(n)]
+        for k in range(n):
+            wts.dba_iterate(single[k], B, Ys[k], bary_out=Bo, counts=counts, dist=d1)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(n):
+            wts.dba_iterate(single[k], B, Ys[k], bary_out=Bo, counts=counts, dist=d1)
+        e1.record()
+        torch.cuda.synchronize()
+        per = e0.elapsed_time(e1) / 1e3
+        for one in single:
+            one.close()
+    return {"op": "dba_iterate", "one_cycle_per_launch_s": round(per, 5),
+            "batched_s": round(batched, 5), "speedup": round(per / batched, 2),
+            "per_cycle_timing": "sum of per-launch events" if sequential else "back to back"}
+
+
+def dba_large_section(wts, dev, iters: int = 10, speedup: bool = True):
     """DBA on the 512-cycle workload (6 channels, lengths log-uniform
     1000..20000, L = 10000, nearest-length init): `iters` iterations replayed
     from a captured hipGraph (two iterations per graph), plus the path
@@ -258,13 +319,99 @@ def dba_large_section(wts, dev, iters: int = 10):
     e1.record()
     torch.cuda.synchronize()
     it_s = e0.elapsed_time(e1) / 1e3 / iters
+    del runner
+    speed = dba_per_cycle_speedup(wts, plan, off, w.d, dt, w.L, Y, B0) if speedup else None
     cm = c_min_path(w.d)
     return {"workload": w.name + ": %d DBA iterations replayed from a hipGraph, nearest-length "
                                  "init" % iters,
             "s_per_dba_iteration": round(it_s, 5), "gcups": round(cells / it_s / 1e9, 2),
             "cells_per_iteration": cells, "rows_per_lane": plan.rho(wts.OP_DBA),
             "path_sweep_ms": round(sweep_s * 1e3, 3), "ops_per_cell": cm,
-            "path_sweep_alu_frac": round(cells * cm / sweep_s / VALU_LANE_OPS_PEAK, 4)}
+            "path_sweep_alu_frac": round(cells * cm / sweep_s / VALU_LANE_OPS_PEAK, 4),
+            "batched_vs_per_cycle": speed}
+
+
+def irregular_section(wts, dev, dba_iters: int = 10, soft_steps: int = 10, gamma: float = 0.1,
+                      max_ckpt_gib: float = 48.0, speedup: bool = True):
+    """The 256-cycle workload (6 channels, lengths 40000..50000 with 1 % of the
+    samples dropped in gaps, L = max N): nearest-length init, `dba_iters` DBA
+    iterations replayed from a hipGraph, then `soft_steps` preconditioned
+    Soft-DTW (gamma) descent steps over checkpoint-bounded cycle groups, then
+    the anomaly scores of all cycles.  Each phase is timed on its own."""
+    import numpy as np
+    import torch
+    from paper_2404_12134_amd import synth
+    w = synth.make(5)
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    L = w.L
+    cells = L * int(w.lengths.sum())
+    plan = wts.Plan(off, w.d, dt, L)
+    B0, _ = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
+    plan.enable_timing(4)
+    wts.dba_iterate(plan, B0, Y)
+    torch.cuda.synchronize()
+    plan.sweep_ms(wts.OP_DBA)
+    wts.dba_iterate(plan, B0, Y)
+    tot, cnt = plan.sweep_ms(wts.OP_DBA)
+    sweep_s = tot / max(cnt, 1) / 1e3
+    plan.enable_timing(0)
+    st = wts.device_status(plan, wts.OP_DBA)
+    if st != 0:
+        raise RuntimeError("device status %d after the DBA iteration" % st)
+    dba_ws_gib = plan.workspace_bytes(wts.OP_DBA) / 2 ** 30
+    speed = dba_per_cycle_speedup(wts, plan, off, w.d, dt, L, Y, B0, sequential=True) \
+        if speedup else None
+    runner = wts.DBARunner(plan, Y, B0, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = runner.run(dba_iters).clone()
+    torch.cuda.synchronize()
+    t_dba = (time.perf_counter() - t0) / dba_iters
+    del runner
+    plan.close()
+    torch.cuda.empty_cache()
+
+    groups = wts.subset_plans(off, w.d, dt, L, int(max_ckpt_gib * 2 ** 30))
+    gv = torch.from_numpy(1.0 / w.lengths.astype(np.float64)).to(dev)   # Eq. 7: lambda / m
+    t_soft = []
+    for _ in range(soft_steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        wts.softdtw_descent_step(groups, Y, off, B, gamma, gv, 0.5)
+        torch.cuda.synchronize()
+        t_soft.append(time.perf_counter() - t0)
+    for a, b, gp in groups:
+        st = wts.device_status(gp, wts.OP_SOFT_BWD)
+        if st != 0:
+            raise RuntimeError("device status %d after the Soft-DTW backward" % st)
+        gp.close()
+    torch.cuda.empty_cache()
+
+    splan = wts.Plan(off, w.d, dt, L)
+    wts.anomaly_score(splan, B, Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wts.anomaly_score(splan, B, Y)
+    torch.cuda.synchronize()
+    t_score = time.perf_counter() - t0
+    splan.close()
+    torch.cuda.empty_cache()
+    s_soft = float(np.median(t_soft))
+    cm = c_min_path(w.d)
+    return {"workload": w.name + ": nearest-length init, %d DBA iterations (hipGraph), %d "
+                                 "Soft-DTW gamma=%g descent steps in %d checkpoint groups, "
+                                 "scores" % (dba_iters, soft_steps, gamma, len(groups)),
+            "cells_per_pass": cells,
+            "s_per_dba_iteration": round(t_dba, 4), "dba_gcups": round(cells / t_dba / 1e9, 2),
+            "path_sweep_ms": round(sweep_s * 1e3, 2), "ops_per_cell": cm,
+            "path_sweep_alu_frac": round(cells * cm / sweep_s / VALU_LANE_OPS_PEAK, 4),
+            "dba_workspace_gib": round(dba_ws_gib, 1),
+            "s_per_soft_step": round(s_soft, 3),
+            "soft_gcups_fwd_bwd": round(2 * cells / s_soft / 1e9, 2),
+            "soft_alu_frac": round(2 * cells * c_min_soft(w.d) / s_soft / VALU_LANE_OPS_PEAK, 4),
+            "score_s": round(t_score, 4),
+            "workload_s": round(dba_iters * t_dba + float(np.sum(t_soft)) + t_score, 2),
+            "batched_vs_per_cycle": speed}
 
 
 def only_phase(args, wts, dev):
@@ -281,6 +428,12 @@ def only_phase(args, wts, dev):
         torch.cuda.synchronize()
         print(json.dumps({"phase": "copy", "bytes_read": a.numel() * 8, "bytes_written": b.numel() * 8,
                           "source_hash": kernel_source_hash()}))
+        return
+    if args.only in ("large", "irregular"):
+        fn = dba_large_section if args.only == "large" else irregular_section
+        rec = fn(wts, dev, speedup=not args.no_speedup)
+        print(json.dumps({"phase": args.only, "source_hash": kernel_source_hash(),
+                          args.only: rec}))
         return
     if args.only == "soft":
         rec = soft_section(wts, dev, args.steps)
@@ -319,8 +472,11 @@ def main():
     ap.add_argument("--no-soft", action="store_true", help="skip the Soft-DTW section")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 512-cycle DBA section")
+    ap.add_argument("--no-irregular", action="store_true",
+                    help="skip the 256-cycle 40k..50k section (DBA, Soft-DTW, scores)")
     ap.add_argument("--soft-steps", type=int, default=2)
-    ap.add_argument("--only", choices=["medoid", "dba", "score", "soft", "copy"],
+    ap.add_argument("--only", choices=["medoid", "dba", "score", "soft", "copy", "large",
+                                       "irregular"],
                     help="run only one phase --steps times (for hardware-counter passes)")
     ap.add_argument("--traffic-from", metavar="DIR",
                     help="write profiles/traffic.json from rocprofv3 FETCH/WRITE_SIZE passes")
@@ -458,8 +614,11 @@ def main():
         speed = {"op": "dba_iterate", "one_cycle_per_launch_s": round(tb - ta, 5),
                  "batched_s": round(tc - tb, 5), "speedup": round((tb - ta) / (tc - tb), 2)}
 
-    soft = None if args.no_soft else soft_section(wts, dev, args.soft_steps)
-    large = None if args.no_large else dba_large_section(wts, dev)
+    soft = None if args.no_soft else guarded(soft_section, wts, dev, args.soft_steps)
+    large = None if args.no_large else guarded(dba_large_section, wts, dev,
+                                               speedup=not args.no_speedup)
+    irregular = None if args.no_irregular else guarded(irregular_section, wts, dev,
+                                                       speedup=not args.no_speedup)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
 
     line = {
@@ -479,6 +638,7 @@ def main():
         "batched_vs_per_cycle": speed,
         "soft_dtw": soft,
         "dba_large": large,
+        "irregular": irregular,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -7,6 +7,7 @@ DBA (and of the Soft-DTW gradient) equals the fold over those few cycles
 alone, so the comparison stays bit-exact (DBA) or within 1e-4 (Soft-DTW).
 """
 
+import functools
 import sys
 
 import numpy as np
@@ -139,12 +140,17 @@ def test_config4_full_soft_sampled(wts):
     check_vec(h.cpu().numpy(), oh)
 
 
+@functools.lru_cache(maxsize=1)
+def _config5():
+    return synth.make(5)
+
+
 @pytest.mark.timeout(900)
 def test_config5_full_scores_sampled(wts):
     """256 x 6 ch, 40000..50000 with 1 % gaps, L = max N: scores of all cycles
     on the GPU, two of them checked against the oracle bit for bit."""
     import torch
-    w = synth.make(5)
+    w = _config5()
     Y, off, dt = wts.pack_cycles(w.cycles)
     plan = wts.Plan(off, 6, dt, w.L)
     cyc = f64(w.cycles)
@@ -160,3 +166,78 @@ def test_config5_full_scores_sampled(wts):
     os_, od, ol = oracle.score_batch(Bo, [cyc[q] for q in pick])
     np.testing.assert_array_equal(score.cpu().numpy()[pick], os_)
     np.testing.assert_array_equal(plen.cpu().numpy()[pick], ol)
+
+
+@pytest.mark.timeout(900)
+def test_config5_full_dba_and_soft(wts):
+    """256 x 6 ch, 40000..50000 with 1 % gaps, L = max N (the DBA workspace is
+    about 160 GB): one DBA iteration on all cycles weighted onto three of
+    them, bit-exact against the oracle on those three; then one Soft-DTW
+    (gamma 0.1) pass over checkpoint-bounded cycle groups, checked by
+    properties that hold at any size: each value is at most the hard DTW of
+    its cycle, each row mass is at least the sum of the weights (every path
+    visits every row), and the eta = 1 update is a convex combination of
+    samples."""
+    import torch
+    w = _config5()
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    plan = wts.Plan(off, 6, dt, w.L)
+    cyc = f64(w.cycles)
+    lens = w.lengths
+    pick = sorted({int(np.argmin(lens)), int(np.argmax(lens)), 100})
+    B0, kn = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
+    say("c5: DBA iteration on 256 cycles, workspace %.1f GiB"
+        % (plan.workspace_bytes(wts.OP_DBA) / 2 ** 30))
+    wv = np.zeros(w.n)
+    wv[pick] = [1.0, 0.5, 2.0][:len(pick)]
+    B1, counts, dist = wts.dba_iterate(plan, B0, Y, torch.from_numpy(wv).cuda())
+    torch.cuda.synchronize()
+    assert wts.device_status(plan, wts.OP_DBA) == 0
+    B1, counts, hard = B1.cpu().numpy(), counts.cpu().numpy(), dist.cpu().numpy()
+    plan.close()
+    torch.cuda.empty_cache()
+    aplan = wts.Plan(off, 6, dt, w.L)
+    _, plen, _ = wts.dtw_align(aplan, B0, Y, paths=False)
+    plen = plen.cpu().numpy()
+    assert wts.device_status(aplan, wts.OP_ALIGN) == 0
+    aplan.close()
+    assert int(counts.sum()) == int(plen.sum())
+    assert (counts >= w.n).all()
+    ko, Bo = oracle.nearest_init(cyc, w.L)
+    assert kn == ko
+    say("c5: oracle DBA on cycles", pick)
+    Bn, _, od, _ = oracle.dba_iterate(Bo, [cyc[q] for q in pick], wv[pick])
+    np.testing.assert_array_equal(B1, Bn)
+    np.testing.assert_array_equal(hard[pick], od)
+    torch.cuda.empty_cache()
+
+    gamma = 0.1
+    groups = wts.subset_plans(off, 6, dt, w.L, 48 << 30)
+    say("c5: Soft-DTW forward + backward in %d groups" % len(groups))
+    gv = torch.from_numpy(1.0 / lens.astype(np.float64)).cuda()
+    G = torch.zeros_like(B0)
+    H = torch.zeros(w.L, dtype=torch.float64, device=B0.device)
+    vals = torch.empty(w.n, dtype=torch.float64, device=B0.device)
+    for a, b, gp in groups:
+        Yg = Y[int(off[a]):int(off[b])]
+        v, ck = wts.softdtw_forward(gp, B0, Yg, gamma)
+        g, h = wts.softdtw_backward(gp, B0, Yg, gamma, ck, gv[a:b].contiguous(), with_mass=True)
+        del ck
+        vals[a:b] = v
+        G += g
+        H += h
+        torch.cuda.synchronize()
+        assert wts.device_status(gp, wts.OP_SOFT_BWD) == 0
+        gp.close()
+    v = vals.cpu().numpy()
+    assert np.isfinite(v).all()
+    assert (v <= hard + 1e-12 * np.abs(hard)).all(), np.max(v - hard)
+    h = H.cpu().numpy()
+    assert (h >= (1.0 - 1e-4) * gv.sum().item()).all(), h.min()
+    B2 = B0.clone()
+    wts.precond_step(B2, G, H, 1.0)
+    B2 = B2.cpu().numpy()
+    yall = np.concatenate(cyc)
+    lo, hi = yall.min(axis=0), yall.max(axis=0)
+    tol = 1e-9 * (hi - lo)
+    assert ((B2 >= lo - tol) & (B2 <= hi + tol)).all()
