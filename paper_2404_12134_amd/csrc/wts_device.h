@@ -164,11 +164,36 @@ __device__ __forceinline__ void st_dev(int* p, int v) {
 __device__ __forceinline__ int ld_dev(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
+}
+// Device-scope (sc1) buffer accesses: stores write through to the point of
+// coherence for all CUs of the device.  Every lane issues the instruction; a
+// lane that must not access memory passes kDrop, an offset past the buffer's
+// record count, and the hardware range check discards its access (a load
+// returns 0).  No branch around the access is needed.
+constexpr int kDrop = 0x7ffffff0;   // > any row these kernels address (< 2^28 bytes)
+typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, v), r, byte_off, 0, 16);
+}
+__device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, int v) {
+  __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 16);
+}
 // Wait for every outstanding memory operation of this wave (orders the
 // relaxed stores above before a following progress-counter store).
 __device__ __forceinline__ void mem_drain() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// Wait until at most the two most recent vector memory operations of this
+// wave are outstanding (gfx9 s_waitcnt: vmcnt 2, expcnt and lgkmcnt not
+// waited on).  Vector loads and stores share one in-order counter, so every
+// older access is complete.
+__device__ __forceinline__ void mem_wait_all_but_2() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F72);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 

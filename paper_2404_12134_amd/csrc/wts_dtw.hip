@@ -44,22 +44,6 @@ constexpr unsigned long long kSentR = 0xFFF4DEADBEEF0000ull;   // a NaN no arith
 constexpr int kSentX = INT_MIN;
 __device__ __forceinline__ int row_stride(int N) { return (N + 63 + 3) & ~3; }
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
-}
-// Device-scope (sc1) buffer accesses: stores write through to the point of
-// coherence for all CUs of the device.  Every lane issues the instruction; a
-// lane that must not access memory passes kDrop, an offset past the buffer's
-// record count, and the hardware range check discards its access (a load
-// returns 0).  No branch around the access is needed.
-constexpr int kDrop = 0x7ffffff0;   // > any strip row (rows are < 2^28 bytes)
-typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, v), r, byte_off, 0, 16);
-}
-__device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, int v) {
-  __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 16);
-}
 // acc * 2 + b in one instruction: the carry-in of v_addc is the lane mask of
 // the comparison that produced b.
 __device__ __forceinline__ uint32_t push_bit(uint32_t acc, bool b) {

@@ -296,7 +296,10 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
     }
     double up0 = 0.0, dg0 = 0.0;              // this lane's row-0 pushes, sent up next step
     double recv_dg = 0.0;                     // diagonal push received last step
-    bool gave_up = false;
+    bool gave_up = false;                     // wave-uniform
+    int seen_below = 0;                       // last progress read from the strip below (uniform)
+    const __amdgpu_buffer_rsrc_t pu_out = rsrc(pu_row, N * 8);
+    const __amdgpu_buffer_rsrc_t pd_out = rsrc(pd_row, N * 8);
 
     // Y columns of the last tile
     {
@@ -328,16 +331,25 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
       if (has_below) {
         const int jlo = max(0, tg - (kWave - 1));
         const int need = N - jlo;            // columns >= jlo published
-        if (lane == 0 && !gave_up && need > 0) {
-          int polls = 0;
-          while (ld_dev(prog_below) < need) {
-            poll_backoff(polls, a.relaxed_wait);
-            if (++polls > kSpinLimit) {
-              atomicOr(a.status, kStatusSpinTimeout);
-              gave_up = true;
-              break;
+        // the strip below usually runs far ahead: one read of its counter
+        // covers many tiles, and only a counter short of `need` is read again
+        if (need > seen_below && !gave_up) {
+          int got = 0, quit = 0;
+          if (lane == 0) {
+            int polls = 0;
+            got = ld_dev(prog_below);
+            while (got < need) {
+              poll_backoff(polls, a.relaxed_wait);
+              if (++polls > kSpinLimit) {
+                atomicOr(a.status, kStatusSpinTimeout);
+                quit = 1;
+                break;
+              }
+              got = ld_dev(prog_below);
             }
           }
+          seen_below = __builtin_amdgcn_readfirstlane(got);
+          gave_up = __builtin_amdgcn_readfirstlane(quit) != 0;
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (lane < kTile) {
@@ -439,22 +451,27 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
         recv_dg = recv_dg_next;
       }
       __syncthreads();
-      if (has_above) {   // publish the top row's pushes for columns tg .. tg+15
-        if (lane < kTile) {
-          const int j = tg + lane;
-          if (j < N) {
-            st_dev(pu_row + j, bout_up[lane]);
-            st_dev(pd_row + j, bout_dg[lane]);
-          }
-        }
-        mem_drain();
-        if (lane == 0) st_dev(prog_self, N - min(N, tg));
+      if (has_above) {
+        // publish the top row's pushes for columns tg .. tg+15 (two stores,
+        // issued by every lane, dropped past the row), then announce the
+        // previous tile's columns: waiting until at most these two stores are
+        // outstanding completes every older store without waiting for them
+        const int j = tg + lane;
+        const bool w = lane < kTile && j < N;
+        st_dev(pu_out, w ? j * 8 : kDrop, bout_up[lane & (kTile - 1)]);
+        st_dev(pd_out, w ? j * 8 : kDrop, bout_dg[lane & (kTile - 1)]);
+        mem_wait_all_but_2();
+        if (lane == 0) st_dev(prog_self, N - min(N, tg + 16));
       }
       if (g > 0 && lane < 16) {
 #pragma unroll
         for (int c = 0; c < D; ++c) ys[c][jn & (kRing - 1)] = yv[c];
       }
       __syncthreads();
+    }
+    if (has_above) {   // the last tile's columns
+      mem_drain();
+      if (lane == 0) st_dev(prog_self, N);
     }
     // per-row sums of this cycle: gradient 2 (b sum_j e - sum_j e y_j) and mass
 #pragma unroll
