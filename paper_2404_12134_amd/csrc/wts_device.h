@@ -187,6 +187,13 @@ __device__ __forceinline__ void mem_drain() {
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
+// Wait until at most the most recent vector memory operation of this wave is
+// outstanding (vmcnt 1).
+__device__ __forceinline__ void mem_wait_all_but_1() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F71);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 // Wait until at most the two most recent vector memory operations of this
 // wave are outstanding (gfx9 s_waitcnt: vmcnt 2, expcnt and lgkmcnt not
 // waited on).  Vector loads and stores share one in-order counter, so every

@@ -98,8 +98,8 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     __syncthreads();
     if (item >= a.n_items) break;
     const int2 it = a.items[item];
-    const PairDesc pd = a.pairs[it.x];
-    const int s = it.y;
+    const PairDesc pd = uniform(a.pairs[uni(it.x)]);
+    const int s = uni(it.y);
     const int M = pd.M, N = pd.N;
     const int i0 = s * H;
     const int ib = i0 + lane * RHO;
@@ -123,7 +123,11 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     for (int r = 0; r < RHO; ++r) left[r] = INF;
     double upprev = (s == 0 && lane == 0) ? 0.0 : INF;
     double bot = INF;
-    bool gave_up = false;
+    bool gave_up = false;       // wave-uniform
+    int seen_prev = 0;          // last progress read from the strip above (uniform)
+    bool have_next = false;     // pr_next holds the next chunk's upper input (uniform)
+    double pr_next = INF;
+    const __amdgpu_buffer_rsrc_t ro = rsrc(row_out, has_next ? N * 8 : 0);
 
     double yv[D];
     {
@@ -145,21 +149,39 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
           yv[c] = j < N ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0;
       }
       if (has_prev) {
-        const int need = min(N, t0 + kChunk);
-        if (lane == 0 && !gave_up) {
-          int polls = 0;
-          while (ld_dev(prog_in) < need) {
-            poll_backoff(polls, a.relaxed_wait);
-            if (++polls > kSpinLimit) {
-              atomicOr(a.status, kStatusSpinTimeout);
-              gave_up = true;
-              break;
+        // the strip above's bottom row for this chunk: prefetched during the
+        // previous chunk when its counter already covered it, else read now
+        // (one read of the counter usually covers many chunks)
+        double pr = pr_next;
+        if (!have_next) {
+          const int need = min(N, t0 + kChunk);
+          if (need > seen_prev && !gave_up) {
+            int got = 0, quit = 0;
+            if (lane == 0) {
+              int polls = 0;
+              got = ld_dev(prog_in);
+              while (got < need) {
+                poll_backoff(polls, a.relaxed_wait);
+                if (++polls > kSpinLimit) {
+                  atomicOr(a.status, kStatusSpinTimeout);
+                  quit = 1;
+                  break;
+                }
+                got = ld_dev(prog_in);
+              }
             }
+            seen_prev = __builtin_amdgcn_readfirstlane(got);
+            gave_up = __builtin_amdgcn_readfirstlane(quit) != 0;
           }
+          __atomic_signal_fence(__ATOMIC_SEQ_CST);
+          const int j = t0 + lane;
+          pr = j < N ? ld_dev(row_in + j) : INF;
         }
+        binr[lane] = pr;
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        const int j = t0 + lane;
-        binr[lane] = j < N ? ld_dev(row_in + j) : INF;
+        const int jn = t0 + kChunk + lane;
+        have_next = more && seen_prev >= min(N, t0 + 2 * kChunk);
+        if (have_next) pr_next = jn < N ? ld_dev(row_in + jn) : INF;
       }
       __syncthreads();
 
@@ -206,11 +228,15 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
       }
       __syncthreads();
       if (has_next) {
+        // this chunk's columns of the bottom row (one store, dropped outside
+        // the row), then the previous chunk's columns are announced: waiting
+        // until at most this store is outstanding completes every older one
         const int jend = t0 + tcnt - (kWave - 1);
         const int j = t0 - (kWave - 1) + lane;
-        if (j >= 0 && j < N && j < jend) st_dev(row_out + j, bor[j & (kRing - 1)]);
-        mem_drain();
-        if (lane == 0) st_dev(prog_out, min(N, max(0, jend)));
+        const bool w = j >= 0 && j < N && j < jend;
+        st_dev(ro, w ? j * 8 : kDrop, bor[j & (kRing - 1)]);
+        mem_wait_all_but_1();
+        if (lane == 0) st_dev(prog_out, min(N, max(0, t0 - (kWave - 1))));
       }
       if (more) {
         const int j = t0 + kChunk + lane;
@@ -218,6 +244,10 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
         for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
       }
       __syncthreads();
+    }
+    if (has_next) {   // the last chunk's columns
+      mem_drain();
+      if (lane == 0) st_dev(prog_out, N);
     }
     if (ib <= M - 1 && M - 1 < ib + RHO) {
       const int rl = M - 1 - ib;
@@ -255,8 +285,8 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
     __syncthreads();
     if (item >= a.n_items) break;
     const int2 it = a.items[item];
-    const PairDesc pd = a.pairs[it.x];
-    const int s = it.y;
+    const PairDesc pd = uniform(a.pairs[uni(it.x)]);
+    const int s = uni(it.y);
     const int M = pd.M, N = pd.N;
     const int i0 = s * H;
     const int ib = i0 + lane * RHO;
