@@ -187,6 +187,13 @@ __device__ __forceinline__ void mem_drain() {
   __builtin_amdgcn_s_waitcnt(0);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
+// Wait for every outstanding vector memory operation (vmcnt 0) but not for
+// LDS or scalar memory.
+__device__ __forceinline__ void mem_wait_vm0() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 // Wait until at most the most recent vector memory operation of this wave is
 // outstanding (vmcnt 1).
 __device__ __forceinline__ void mem_wait_all_but_1() {

@@ -142,11 +142,14 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     for (int t0 = 0; t0 < Tend; t0 += kChunk) {
       const int tcnt = min(kChunk, Tend - t0);
       const bool more = t0 + kChunk < Tend;
-      if (more) {
-        const int j = t0 + kChunk + lane;
+      // next chunk's Y columns: unconditional loads from a clamped column,
+      // kept in the storage type until they are written to LDS after this
+      // chunk (a conditional load would be waited for on the spot)
+      TY yraw[D];
+      {
+        const int j = min(t0 + kChunk + lane, N - 1);
 #pragma unroll
-        for (int c = 0; c < D; ++c)
-          yv[c] = j < N ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0;
+        for (int c = 0; c < D; ++c) yraw[c] = Y[(pd.y_off + j) * D + c];
       }
       if (has_prev) {
         // the strip above's bottom row for this chunk: prefetched during the
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
       if (more) {
         const int j = t0 + kChunk + lane;
 #pragma unroll
-        for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = yv[c];
+        for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = j < N ? static_cast<double>(yraw[c]) : 0.0;
       }
       __syncthreads();
     }
@@ -345,12 +348,14 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
     for (int g = G - 1; g >= 0; --g) {
       const int tg = 16 * g;
       // next tile's 16 new Y columns, stored after this tile
-      double yv[D];
+      // (unconditional loads from a clamped column, kept in the storage type
+      // until the store: a conditional load would be waited for on the spot)
+      TY yraw[D];
       const int jn = tg - 16 - (kWave - 1) + lane;
-      if (g > 0 && lane < 16) {
+      {
+        const int jc = min(max(jn, 0), N - 1);
 #pragma unroll
-        for (int c = 0; c < D; ++c)
-          yv[c] = (jn >= 0 && jn < N) ? static_cast<double>(Y[(pd.y_off + jn) * D + c]) : 0.0;
+        for (int c = 0; c < D; ++c) yraw[c] = Y[(pd.y_off + jc) * D + c];
       }
       // lane 0's upper input for the replay (bottom row of the strip above)
       if (lane < kTile) {
@@ -494,8 +499,9 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
         if (lane == 0) st_dev(prog_self, N - min(N, tg + 16));
       }
       if (g > 0 && lane < 16) {
+        const bool in = jn >= 0 && jn < N;
 #pragma unroll
-        for (int c = 0; c < D; ++c) ys[c][jn & (kRing - 1)] = yv[c];
+        for (int c = 0; c < D; ++c) ys[c][jn & (kRing - 1)] = in ? static_cast<double>(yraw[c]) : 0.0;
       }
       __syncthreads();
     }
