@@ -177,6 +177,9 @@ typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, v), r, byte_off, 0, 16);
 }
+__device__ __forceinline__ double ld_dev(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 16));
+}
 __device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, int v) {
   __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 16);
 }

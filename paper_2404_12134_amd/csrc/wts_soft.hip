@@ -333,6 +333,8 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
     int seen_below = 0;                       // last progress read from the strip below (uniform)
     const __amdgpu_buffer_rsrc_t pu_out = rsrc(pu_row, N * 8);
     const __amdgpu_buffer_rsrc_t pd_out = rsrc(pd_row, N * 8);
+    const __amdgpu_buffer_rsrc_t pu_in = rsrc(pu_row, has_below ? N * 8 : 0);
+    const __amdgpu_buffer_rsrc_t pd_in = rsrc(pd_row, has_below ? N * 8 : 0);
 
     // Y columns of the last tile
     {
@@ -387,15 +389,16 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
           gave_up = __builtin_amdgcn_readfirstlane(quit) != 0;
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if (lane < kTile) {
-          const int j = tg - (kWave - 1) + lane;
-          const bool in = j >= 0 && j < N;
-          bin_up[lane] = in ? ld_dev(pu_row + j) : 0.0;
-          bin_dg[lane] = in ? ld_dev(pd_row + j) : 0.0;
-        }
-      } else if (lane < kTile) {
-        bin_up[lane] = 0.0;
-        bin_dg[lane] = 0.0;
+      }
+      // the pushes are only needed by the backward half: loaded now (one
+      // unconditional load each, zero outside the row or without a strip
+      // below) and written to LDS after the replay
+      double in_up, in_dg;
+      {
+        const int j = tg - (kWave - 1) + lane;
+        const int off = lane < kTile && j >= 0 && j < N ? j * 8 : kDrop;
+        in_up = ld_dev(pu_in, off);
+        in_dg = ld_dev(pd_in, off);
       }
       __syncthreads();
 
@@ -434,6 +437,12 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
           bot = left[RHO - 1];
         }
       }
+
+      if (lane < kTile) {
+        bin_up[lane] = in_up;
+        bin_dg[lane] = in_dg;
+      }
+      __syncthreads();
 
       // ---- backward over the tile
 #pragma unroll
