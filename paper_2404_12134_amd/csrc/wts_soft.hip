@@ -298,6 +298,7 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
     const int G = pd.WT;                     // 16-step tiles
     const double* row_fwd = a.rows + pd.aux_base + (int64_t)(s - 1) * N;
     const double* st = a.states + pd.state_base + (int64_t)s * G * (RHO + 1) * kWave;
+    const __amdgpu_buffer_rsrc_t rf_in = rsrc(row_fwd, has_above ? N * 8 : 0);
     // rolling push rows: the strip below wrote them for us, we overwrite them
     // for the strip above after reading
     double* pu_row = a.push_up + pd.bnd_base;
@@ -335,6 +336,19 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
     const __amdgpu_buffer_rsrc_t pd_out = rsrc(pd_row, N * 8);
     const __amdgpu_buffer_rsrc_t pu_in = rsrc(pu_row, has_below ? N * 8 : 0);
     const __amdgpu_buffer_rsrc_t pd_in = rsrc(pd_row, has_below ? N * 8 : 0);
+    // a tile's replay inputs: the forward's sweep state at its first step and
+    // (lanes 0..15) the strip above's bottom row at its 16 columns (the top
+    // strip reads an empty buffer and uses +inf; columns past N are never used)
+    double st_n[RHO + 1];
+    double rf_n;
+    auto load_tile_inputs = [&](int gg) {
+#pragma unroll
+      for (int r = 0; r <= RHO; ++r) st_n[r] = st[((int64_t)gg * (RHO + 1) + r) * kWave + lane];
+      const int j = 16 * gg + lane;
+      rf_n = __builtin_bit_cast(
+          double, __builtin_amdgcn_raw_buffer_load_b64(rf_in, lane < kTile && j < N ? j * 8 : kDrop, 0, 0));
+    };
+    load_tile_inputs(G - 1);
 
     // Y columns of the last tile
     {
@@ -359,11 +373,9 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
 #pragma unroll
         for (int c = 0; c < D; ++c) yraw[c] = Y[(pd.y_off + jc) * D + c];
       }
-      // lane 0's upper input for the replay (bottom row of the strip above)
-      if (lane < kTile) {
-        const int j = tg + lane;
-        bin_fwd[lane] = (has_above && j < N) ? row_fwd[j] : INF;
-      }
+      // lane 0's upper input for the replay (bottom row of the strip above),
+      // loaded during the previous tile
+      if (lane < kTile) bin_fwd[lane] = has_above ? rf_n : INF;
       // lane 63's inputs: pushes of the strip below's top row at columns tg-63 ..
       if (has_below) {
         const int jlo = max(0, tg - (kWave - 1));
@@ -405,8 +417,8 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
       // ---- replay the tile forward, keeping the soft-min weights
       double left[RHO];
 #pragma unroll
-      for (int r = 0; r < RHO; ++r) left[r] = st[((int64_t)g * (RHO + 1) + r) * kWave + lane];
-      double upprev = st[((int64_t)g * (RHO + 1) + RHO) * kWave + lane];
+      for (int r = 0; r < RHO; ++r) left[r] = st_n[r];
+      double upprev = st_n[RHO];
       double bot = left[RHO - 1];
       float wd[16][RHO], wu[16][RHO], wl[16][RHO];
       const bool full = tg >= kWave - 1 && tg + 16 <= N;
@@ -442,6 +454,9 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
         bin_up[lane] = in_up;
         bin_dg[lane] = in_dg;
       }
+      // the next tile's replay inputs, in flight during the backward half
+      // (unconditional: the last tile reloads its own)
+      load_tile_inputs(max(g - 1, 0));
       __syncthreads();
 
       // ---- backward over the tile
