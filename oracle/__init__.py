@@ -54,13 +54,16 @@ def lib():
         L.wts_o_softdtw_grad.argtypes = [P, I64, P, I64, I32, D, P, P, P, P]
         L.wts_o_softdtw_batch.argtypes = [P, I64, P, P, I32, I32, D, P, P, P, P]
         L.wts_o_medoid.argtypes = [P, P, I32, I32, P, P]
+        L.wts_o_subdtw.argtypes = [P, I64, P, I64, I32, I32, P, P, P]
+        L.wts_o_subdtw_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P, P]
         L.wts_o_resample.argtypes = [P, I64, I32, I64, P]
         L.wts_o_resample.restype = None
         L.wts_o_euclid_mean.argtypes = [P, P, I32, I32, I64, P]
         L.wts_o_nearest_init.argtypes = [P, P, I32, I32, I64, P]
         for f in ("wts_o_dtw", "wts_o_dtw_batch", "wts_o_score_batch", "wts_o_dba_iterate",
                   "wts_o_softdtw", "wts_o_softdtw_grad", "wts_o_softdtw_batch", "wts_o_medoid",
-                  "wts_o_euclid_mean", "wts_o_nearest_init", "wts_o_num_threads"):
+                  "wts_o_euclid_mean", "wts_o_nearest_init", "wts_o_num_threads",
+                  "wts_o_subdtw", "wts_o_subdtw_batch"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -216,3 +219,51 @@ def nearest_init(cycles, L):
     out = np.zeros((L, Y.shape[1]))
     k = lib().wts_o_nearest_init(_p(Y), _p(off), len(cycles), Y.shape[1], L, _p(out))
     return int(k), out
+
+
+def subdtw(X, Y, kind=SQEUCLID):
+    """Sub-DTW (Sec. III-A, Eq. 2): (value, a*, b*), 0-based columns of Y."""
+    X, Y = _series(X), _series(Y)
+    v = np.zeros(1)
+    a = np.zeros(1, dtype=np.int64)
+    b = np.zeros(1, dtype=np.int64)
+    _check(lib().wts_o_subdtw(_p(X), X.shape[0], _p(Y), Y.shape[0], X.shape[1], kind, _p(v),
+                              _p(a), _p(b)))
+    return float(v[0]), int(a[0]), int(b[0])
+
+
+def subdtw_batch(X, windows, kind=SQEUCLID):
+    """Sub-DTW of X against every window: (values, a*, b*) arrays."""
+    X = _series(X)
+    Y, off = _packed(windows)
+    n = len(windows)
+    v = np.zeros(n)
+    a = np.zeros(n, dtype=np.int64)
+    b = np.zeros(n, dtype=np.int64)
+    _check(lib().wts_o_subdtw_batch(_p(X), X.shape[0], _p(Y), _p(off), n, X.shape[1], kind,
+                                    _p(v), _p(a), _p(b)))
+    return v, a, b
+
+
+def segment_alpha(M: int) -> int:
+    """alpha = 0.15 M (Sec. III-A), rounded down to whole samples."""
+    return int(0.15 * M)
+
+
+def segment(X, Y, kind=SQEUCLID):
+    """The segmentation loop of Sec. III-A, 0-based and half-open windows:
+    ws = 0; repeat: window Y[ws : min(ws + 2M, N)], (a*, b*) of its Sub-DTW
+    made absolute, cycle Y[a* .. b*] kept, ws <- b* - alpha (and at least
+    ws + 1, so that the loop always advances), while ws < N.
+    Returns [(a*, b*, value)] in order."""
+    X, Y = _series(X), _series(Y)
+    M, N = X.shape[0], Y.shape[0]
+    alpha = segment_alpha(M)
+    out = []
+    ws = 0
+    while ws < N:
+        we = min(ws + 2 * M, N)
+        v, a, b = subdtw(X, Y[ws:we], kind)
+        out.append((ws + a, ws + b, v))
+        ws = max(ws + b - alpha, ws + 1)
+    return out

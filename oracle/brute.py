@@ -102,6 +102,27 @@ def dtw(X, Y, kind="sq"):
     return best, chosen, len(opt)
 
 
+def subdtw(X, Y, kind="sq"):
+    """Sub-DTW by enumeration: every complete path of X against every
+    subsequence Y[a..b].  Returns (min cost, a*, b*) where b* is the lowest
+    end column of an optimal path and a* the start of the optimal path ending
+    there whose backward steps, followed by the entry from the row above
+    (ranked as a diagonal step), are lexicographically smallest."""
+    X, Y = _series(X), _series(Y)
+    M, N = X.shape[0], Y.shape[0]
+    cands = []
+    for a in range(N):
+        for b in range(a, N):
+            for p in all_paths(M, b - a + 1):
+                path = [(i, j + a) for i, j in p]
+                cands.append((path_cost(X, Y, path, kind), b, path))
+    best = min(c for c, _, _ in cands)
+    b_star = min(b for c, b, _ in cands if c == best)
+    opt = [p for c, b, p in cands if c == best and b == b_star]
+    chosen = min(opt, key=lambda p: backward_steps(p) + (DIAG,))
+    return best, chosen[0][1], b_star
+
+
 def softdtw(X, Y, gamma):
     X, Y = _series(X), _series(Y)
     costs = np.array([path_cost(X, Y, p) for p in all_paths(X.shape[0], Y.shape[0])])

@@ -323,6 +323,69 @@ int wts_o_softdtw_grad(const double* X, int64_t M, const double* Y, int64_t N, i
   return 0;
 }
 
+/* Sub-DTW (Sec. III-A, Eq. 2): the minimum cost over subsequence alignment
+ * paths, which run from row 1 to row M of X but may start and end at any
+ * column of Y.  The dynamic program is Eq. 1's with a free start: the row
+ * above the first one is 0 at every column (r_{0,j} = 0 in the paper's
+ * 1-based cells), the column left of the first one +inf below row 0.  The
+ * path is backtracked from (M-1, b*) with the DTW tie-break (diag, up,
+ * left), where b* is the lowest column whose last-row cost is minimal; the
+ * first cell it reaches in row 0 gives a*.  Outputs: value, a*, b* (0-based
+ * columns of Y).  Needs M*N bytes for the argmin codes. */
+int wts_o_subdtw(const double* X, int64_t M, const double* Y, int64_t N, int d, int kind,
+                 double* value, int64_t* a_star, int64_t* b_star) {
+  uint8_t* code = (uint8_t*)malloc((size_t)(M * N));
+  double* prev = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* cur = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  if (!code || !prev || !cur) { free(code); free(prev); free(cur); return -1; }
+  /* prev[j+1] = r(i-1, j); row -1 is 0 everywhere (free start), prev[0] is
+   * the corner r(-1, -1) = 0 */
+  for (int64_t j = 0; j <= N; ++j) prev[j] = 0.0;
+  for (int64_t i = 0; i < M; ++i) {
+    cur[0] = INFINITY;
+    for (int64_t j = 0; j < N; ++j) {
+      double dg = prev[j], up = prev[j + 1], lf = cur[j];
+      double m = dg;
+      uint8_t c = CODE_DIAG;
+      if (up < m) { m = up; c = CODE_UP; }
+      if (lf < m) { m = lf; c = CODE_LEFT; }
+      cur[j + 1] = wts_o_cost(X + i * d, Y + j * d, d, kind) + m;
+      code[i * N + j] = c;
+    }
+    double* t = prev; prev = cur; cur = t;
+  }
+  /* last row: lowest column with the minimal cost */
+  int64_t b = 0;
+  for (int64_t j = 1; j < N; ++j)
+    if (prev[j + 1] < prev[b + 1]) b = j;
+  *value = prev[b + 1];
+  *b_star = b;
+  /* backtrack to row 0 */
+  int64_t i = M - 1, j = b;
+  while (i > 0) {
+    uint8_t c = code[i * N + j];
+    if (c == CODE_DIAG) { --i; --j; }
+    else if (c == CODE_UP) { --i; }
+    else { --j; }
+  }
+  /* in row 0 the diagonal predecessor (row -1, cost 0) is never worse than
+   * the left one, so the path enters row 0 at the column it reaches */
+  *a_star = j;
+  free(code); free(prev); free(cur);
+  return 0;
+}
+
+/* Sub-DTW of one X against many windows of Y (OpenMP across windows). */
+int wts_o_subdtw_batch(const double* X, int64_t M, const double* Yall, const int64_t* off, int n,
+                       int d, int kind, double* value, int64_t* a_star, int64_t* b_star) {
+  int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int p = 0; p < n; ++p)
+    err |= wts_o_subdtw(X, M, Yall + off[p] * d, off[p + 1] - off[p], d, kind, &value[p],
+                        &a_star[p], &b_star[p]);
+  return err ? -1 : 0;
+}
+
 /* Batched Soft-DTW values and the weighted gradient of sum_i w_i SDTW(X, Y_i)
  * (Eq. 7 with w_i = lambda_i / m_i supplied by the caller).  grad (M*d) and
  * rowmass (M, may be NULL) receive sum_i w_i * (per-pair quantity), summed in

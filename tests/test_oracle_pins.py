@@ -373,3 +373,73 @@ def test_euclid_mean_and_nearest_init():
     np.testing.assert_array_equal(oracle.euclid_mean(short, 5).ravel(), [3, 3.5, 4, 4, 4])
     k, out = oracle.nearest_init([np.zeros((3, 1)), np.ones((9, 1)), np.ones((11, 1))], 10)
     assert k == 1 and out.shape == (10, 1)
+
+
+# ---------------------------------------------------------------- Sub-DTW
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_subdtw_brute_random_reals(d):
+    """Sec. III-A, Eq. 2: the free-start dynamic program equals the minimum
+    over every subsequence alignment path, with the same (a*, b*)."""
+    r = rng(40 + d)
+    for _ in range(25):
+        M, N = int(r.integers(1, 5)), int(r.integers(1, 7))
+        X, Y = r.standard_normal((M, d)), r.standard_normal((N, d))
+        v, a, b = oracle.subdtw(X, Y)
+        bv, ba, bb = brute.subdtw(X, Y)
+        assert v == bv and (a, b) == (ba, bb), (M, N, v, bv, a, ba, b, bb)
+
+
+def test_subdtw_brute_integer_ties():
+    """Ties (small integers): lowest end column, then the diag > up > left
+    backtrack, as enumerated."""
+    r = rng(44)
+    for _ in range(40):
+        M, N = int(r.integers(1, 5)), int(r.integers(1, 7))
+        X = r.integers(0, 3, (M, 1)).astype(np.float64)
+        Y = r.integers(0, 3, (N, 1)).astype(np.float64)
+        assert oracle.subdtw(X, Y) == brute.subdtw(X, Y)
+
+
+def test_subdtw_is_min_over_subsequences_of_dtw():
+    """Eq. 2 second form: min over a <= b of DTW(X, Y[a..b]), at sizes past
+    brute force; the optimum is attained on Y[a*..b*]."""
+    r = rng(45)
+    X, Y = r.standard_normal((9, 2)), r.standard_normal((26, 2))
+    v, a, b = oracle.subdtw(X, Y)
+    full = {(p, q): oracle.dtw(X, Y[p:q + 1], with_path=False)[0]
+            for p in range(26) for q in range(p, 26)}
+    assert v == min(full.values())
+    assert full[(a, b)] == v
+    assert b == min(q for (p, q), c in full.items() if c == v)
+    assert v <= oracle.dtw(X, Y, with_path=False)[0]
+
+
+def test_subdtw_embedded_copy_and_single_row():
+    r = rng(46)
+    X = r.standard_normal((20, 3))
+    Y = np.concatenate([r.standard_normal((7, 3)), X, r.standard_normal((9, 3))])
+    assert oracle.subdtw(X, Y) == (0.0, 7, 26)
+    x = r.standard_normal((1, 3))
+    v, a, b = oracle.subdtw(x, Y)
+    costs = [oracle.cost(x[0], Y[j]) for j in range(Y.shape[0])]
+    assert v == min(costs) and a == b == int(np.argmin(costs))
+
+
+def test_segmentation_of_exact_copies():
+    """Sec. III-A segmentation loop on a stream of exact copies of X with idle
+    stretches between them: every copy is found with cost 0."""
+    r = rng(47)
+    M = 30
+    X = r.standard_normal((M, 2))
+    parts, starts, pos = [], [], 0
+    for k in range(6):
+        idle = np.full((int(r.integers(0, 12)), 2), 8.0)
+        parts += [idle, X]
+        pos += idle.shape[0]
+        starts.append(pos)
+        pos += M
+    Y = np.concatenate(parts)
+    segs = oracle.segment(X, Y)
+    assert [(a, b, v) for a, b, v in segs[:6]] == [(s, s + M - 1, 0.0) for s in starts]
+    assert oracle.segment_alpha(M) == 4
