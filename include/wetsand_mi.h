@@ -14,6 +14,9 @@
  *   wts_softdtw_backward gradient of sum_k w_k Soft-DTW(B, C_k) w.r.t. B
  *                        through the E matrix                  (Eq. 6, Eq. 7)
  *   wts_anomaly_score    d_score = DTW(B, C_k) / |pi_k|        (Sec. III-D, Eq. 8)
+ *   wts_subdtw           Sub-DTW of a reference cycle X against many windows,
+ *                        with the first and last matched window columns
+ *                        (Sec. III-A, Eq. 2: the segmentation step)
  *   wts_precond_step     one preconditioned gradient step on B (Eq. 7 driver)
  *   wts_medoid           all-pairs DTW and the medoid cycle (barycenter init)
  *   wts_init_barycenter  Euclidean-mean / nearest-length / copy initialisation
@@ -76,7 +79,8 @@ enum {
   WTS_OP_SCORE = 3,        /* wts_anomaly_score                     */
   WTS_OP_SOFT_FWD = 4,     /* checkpoint buffer of the Soft-DTW pair */
   WTS_OP_SOFT_BWD = 5,     /* workspace of wts_softdtw_backward      */
-  WTS_OP_MEDOID = 6        /* wts_medoid                            */
+  WTS_OP_MEDOID = 6,       /* wts_medoid                            */
+  WTS_OP_SUBDTW = 7        /* wts_subdtw                            */
 };
 
 enum { WTS_INIT_EUCLID_MEAN = 0, WTS_INIT_NEAREST = 1, WTS_INIT_COPY = 2 };
@@ -161,6 +165,20 @@ wts_status wts_dba_iterate(const wts_plan* plan, const double* bary_in, const vo
 wts_status wts_anomaly_score(const wts_plan* plan, const double* bary, const void* cycles,
                              double* score, double* dist, int64_t* path_len, void* ws,
                              size_t ws_bytes, void* stream);
+
+/* Sec. III-A, Eq. 2: Sub-DTW of the reference X (the plan's L rows, float64
+ * [L][d], passed where the other calls take the barycenter) against every
+ * window C_k of the batch: the minimum over alignment paths that cover all
+ * rows of X and any run of columns of C_k,
+ *   value_k = min_{a <= b} DTW(X, C_k[a..b])   (squared cost only),
+ * b*_k = the lowest column of C_k where the last row of X reaches that
+ * minimum, a*_k = the column at which the optimal path ending there (the
+ * diag > up > left backtrack) enters the first row.  value [n] float64,
+ * a_star / b_star [n] int64 (0-based columns of window k).  Plans created
+ * with cost WTS_COST_EUCLID return WTS_E_UNSUPPORTED.  ws: workspace of
+ * wts_workspace_bytes(WTS_OP_SUBDTW) bytes. */
+wts_status wts_subdtw(const wts_plan* plan, const double* x, const void* windows, double* value,
+                      int64_t* a_star, int64_t* b_star, void* ws, size_t ws_bytes, void* stream);
 
 /* Eq. 3-5 with gamma > 0: value_k = Soft-DTW^gamma(B, C_k) (squared cost).
  * ckpt: checkpoint buffer of wts_workspace_bytes(WTS_OP_SOFT_FWD) bytes that

@@ -253,8 +253,9 @@ def segment_alpha(M: int) -> int:
 def segment(X, Y, kind=SQEUCLID):
     """The segmentation loop of Sec. III-A, 0-based and half-open windows:
     ws = 0; repeat: window Y[ws : min(ws + 2M, N)], (a*, b*) of its Sub-DTW
-    made absolute, cycle Y[a* .. b*] kept, ws <- b* - alpha (and at least
-    ws + 1, so that the loop always advances), while ws < N.
+    made absolute, cycle Y[a* .. b*] kept, ws <- b* - alpha, while ws < N.
+    Where b* - alpha would not move the window forward (the paper does not
+    say what then), it restarts just past the match: ws <- b* + 1.
     Returns [(a*, b*, value)] in order."""
     X, Y = _series(X), _series(Y)
     M, N = X.shape[0], Y.shape[0]
@@ -265,5 +266,5 @@ def segment(X, Y, kind=SQEUCLID):
         we = min(ws + 2 * M, N)
         v, a, b = subdtw(X, Y[ws:we], kind)
         out.append((ws + a, ws + b, v))
-        ws = max(ws + b - alpha, ws + 1)
+        ws = ws + b - alpha if b - alpha > 0 else ws + b + 1
     return out

@@ -134,7 +134,7 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
 struct Layout {
   size_t queue = 0, progress = 0, bnd_r = 0, bnd_aux = 0, codes = 0, out_dist = 0, out_aux = 0;
   size_t seg = 0, seg_len = 0, seg_off = 0, psum = 0, pcnt = 0, dm = 0, totals = 0;
-  size_t rows = 0, states = 0, push_up = 0, push_dg = 0, gsum = 0, hsum = 0;
+  size_t rows = 0, states = 0, push_up = 0, push_dg = 0, gsum = 0, hsum = 0, out_end = 0;
   size_t total = 0;
 };
 
@@ -202,6 +202,7 @@ Layout layout(const wts_plan* p, int op) {
   if (paths) l.codes = take(sizeof(uint32_t) * (size_t)ps.code_words);
   l.out_dist = take(sizeof(double) * (size_t)ps.n_pairs);
   l.out_aux = take(sizeof(int) * (size_t)ps.n_pairs);
+  if (op == WTS_OP_SUBDTW) l.out_end = take(sizeof(int) * (size_t)ps.n_pairs);
   if (paths) {
     l.seg = take(sizeof(int2) * (size_t)ps.n_items);
     l.seg_len = take(sizeof(int) * (size_t)ps.n_items);
@@ -294,9 +295,12 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
   a.codes = mode == wts::MODE_PATH ? at<uint32_t>(ws, l.codes) : nullptr;
   a.out_dist = out_dist ? out_dist : at<double>(ws, l.out_dist);
   a.out_aux = at<int>(ws, l.out_aux);
+  a.out_end = mode == wts::MODE_SUB ? at<int>(ws, l.out_end) : nullptr;
   a.cost_kind = euc ? 1 : 0;
   a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
-  const int tk = timing_begin(p, x_is_cycle ? WTS_OP_MEDOID : (mode == wts::MODE_PATH ? WTS_OP_DBA : WTS_OP_SCORE), st);
+  const int tk = timing_begin(p, x_is_cycle ? WTS_OP_MEDOID
+                                 : mode == wts::MODE_PATH ? WTS_OP_DBA
+                                 : mode == wts::MODE_SUB ? WTS_OP_SUBDTW : WTS_OP_SCORE, st);
   HIP_TRY(wts::launch_fwd(p->d, ps.rho, mode, euc, x_is_cycle, p->dtype, a,
                           default_grid(p, ps), st));
   timing_end(p, tk, st);
@@ -477,6 +481,7 @@ int32_t wts_plan_rho(const wts_plan* p, int op) {
     case WTS_OP_ALIGN_PATHS:
     case WTS_OP_DBA:
     case WTS_OP_SCORE:
+    case WTS_OP_SUBDTW:
       if (p->L <= 0) return fail(WTS_E_ARG, "plan was created with L = 0 (medoid/init only)");
       return p->bary.rho;
     case WTS_OP_SOFT_FWD:
@@ -516,6 +521,7 @@ size_t wts_workspace_bytes(const wts_plan* p, int op) {
     case WTS_OP_SCORE:
     case WTS_OP_SOFT_FWD:
     case WTS_OP_SOFT_BWD:
+    case WTS_OP_SUBDTW:
       return p->L > 0 ? layout(p, op).total : 0;
     case WTS_OP_MEDOID:
       return p->L == 0 ? layout(p, op).total : 0;
@@ -598,6 +604,25 @@ wts_status wts_anomaly_score(const wts_plan* p, const double* bary, const void* 
                  cycles, ws, l, dv, st);
   if (rc != WTS_OK) return rc;
   HIP_TRY(wts::launch_score(dv, at<int>(ws, l.out_aux), p->n, score, path_len, st));
+  return WTS_OK;
+}
+
+wts_status wts_subdtw(const wts_plan* p, const double* x, const void* windows, double* value,
+                      int64_t* a_star, int64_t* b_star, void* ws, size_t ws_bytes, void* stream) {
+  wts_status rc = check_bary_plan(p);
+  if (rc != WTS_OK) return rc;
+  if (!x || !windows || !value || !a_star || !b_star)
+    return fail(WTS_E_ARG, "null x/windows/value/a_star/b_star");
+  if (p->opts.cost == WTS_COST_EUCLID)
+    return fail(WTS_E_UNSUPPORTED, "Sub-DTW is built for the squared cost only");
+  if ((rc = check_ws(p, WTS_OP_SUBDTW, ws, ws_bytes)) != WTS_OK) return rc;
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout l = layout(p, WTS_OP_SUBDTW);
+  rc = run_sweep(p, p->bary, wts::MODE_SUB, false, false, x, windows, ws, l, value, st);
+  if (rc != WTS_OK) return rc;
+  HIP_TRY(wts::launch_sub_out(at<int>(ws, l.out_aux), at<int>(ws, l.out_end), p->n, a_star,
+                              b_star, st));
   return WTS_OK;
 }
 

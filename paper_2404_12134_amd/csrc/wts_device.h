@@ -79,7 +79,10 @@ __device__ __forceinline__ PairDesc uniform(const PairDesc& p) {
 // for 16 steps in registers).
 constexpr int kSoftRho = 2;
 
-enum Mode { MODE_DIST = 0, MODE_DIST_LEN = 1, MODE_PATH = 2 };
+// DIST: value only; DIST_LEN: value and path length; PATH: value and argmin
+// codes; SUB: Sub-DTW (free start; lowest-column minimum of the last row and
+// the start column of its path).
+enum Mode { MODE_DIST = 0, MODE_DIST_LEN = 1, MODE_PATH = 2, MODE_SUB = 3 };
 
 struct FwdArgs {
   const PairDesc* pairs;
@@ -93,7 +96,8 @@ struct FwdArgs {
   int* bnd_aux;          // strip rows: path length (DIST_LEN) or entry code (PATH)
   uint32_t* codes;       // 2-bit argmin codes (PATH)
   double* out_dist;      // [pair slot] r(M-1, N-1)
-  int* out_aux;          // [pair slot] |pi| (DIST_LEN) or entry code of (M-1, N-1) (PATH)
+  int* out_aux;          // [pair slot] |pi| (DIST_LEN), entry code of (M-1, N-1) (PATH) or a* (SUB)
+  int* out_end;          // [pair slot] b* (SUB)
   int cost_kind;         // 0 squared, 1 Euclidean (sqrt)
   int relaxed_wait;      // 1: far more items than resident wavefronts; wait with long sleeps
 };

@@ -142,6 +142,11 @@ void dtw_fwd_kernel(FwdArgs a) {
 #pragma unroll
     for (int r = 0; r < RHO; ++r) { left[r] = INF; lx[r] = 0; acc[r] = 0u; }
     double upprev = (s == 0 && lane == 0) ? 0.0 : INF;   // r(-1,-1) = 0 at the origin
+    // Sub-DTW: running minimum of the last row (lowest column on ties)
+    const bool last_strip = s + 1 == pd.S;
+    const int rl_last = M - 1 - ib;
+    double sub_best = INF;
+    int sub_end = 0, sub_start = 0;
     int upprevx = 0;
     double bot = INF;
     int botx = 0;
@@ -248,7 +253,7 @@ void dtw_fwd_kernel(FwdArgs a) {
 #pragma unroll
         for (int c = 0; c < D; ++c) yn[c] = ys[c][yb];
         bn = binr[0];
-        if (MODE == MODE_DIST_LEN) bxn = binx[0];
+        if (MODE == MODE_DIST_LEN || MODE == MODE_SUB) bxn = binx[0];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int t = tg + u;
@@ -262,7 +267,7 @@ void dtw_fwd_kernel(FwdArgs a) {
 #pragma unroll
             for (int c = 0; c < D; ++c) yn[c] = ys[c][yb + u + 1];
             bn = binr[u + 1];
-            if (MODE == MODE_DIST_LEN) bxn = binx[u + 1];
+            if (MODE == MODE_DIST_LEN || MODE == MODE_SUB) bxn = binx[u + 1];
           }
           const double upin = shr1_f64(bot, bval);
           int upinx = 0, dgx0 = 0;
@@ -274,6 +279,11 @@ void dtw_fwd_kernel(FwdArgs a) {
             // coded 2j (up) or 2j+1 (diagonal)
             upinx = shr1_i32(botx, 2 * t);
             dgx0 = lane == 0 ? upinx + 1 : upprevx;
+          } else if (MODE == MODE_SUB) {
+            // tags are start columns; a path entering the first row at
+            // column j (from above or diagonally) starts at j
+            upinx = shr1_i32(botx, s == 0 ? t : bxv);
+            dgx0 = s == 0 && lane == 0 ? upinx : upprevx;
           }
           const double dg0 = upprev;
           upprev = upin;
@@ -312,6 +322,19 @@ void dtw_fwd_kernel(FwdArgs a) {
             }
             bot = left[RHO - 1];
             botx = lx[RHO - 1];
+            if (MODE == MODE_SUB && last_strip) {
+              // the lane holding row M-1 keeps the lowest column of minimal
+              // cost, and the start column of its path
+              double v = left[0];
+              int vx = lx[0];
+#pragma unroll
+              for (int r = 1; r < RHO; ++r)
+                if (r == rl_last) { v = left[r]; vx = lx[r]; }
+              const bool better = v < sub_best;
+              sub_best = better ? v : sub_best;
+              sub_end = better ? j : sub_end;
+              sub_start = better ? vx : sub_start;
+            }
           }
           if (MODE == MODE_PATH) {
             // every step of every lane shifts two bits into the row's code
@@ -332,7 +355,8 @@ void dtw_fwd_kernel(FwdArgs a) {
       for (int tb = 0; tb < tcnt; tb += 16) {
         const int tg = t0 + tb;
         if (lane < 16) {   // this group's upper input, ready and checked
-          binr[lane] = has_prev && tg + lane < N ? pr : INF;
+          // above the first strip: +inf, or 0 for Sub-DTW (free start)
+          binr[lane] = has_prev ? (tg + lane < N ? pr : INF) : (MODE == MODE_SUB ? 0.0 : INF);
           if (kAux) binx[lane] = has_prev ? px : 0;
         }
         wave_sync();
@@ -362,8 +386,14 @@ void dtw_fwd_kernel(FwdArgs a) {
 #pragma unroll
       for (int r = 1; r < RHO; ++r)
         if (r == rl) { v = left[r]; vx = lx[r]; }
-      a.out_dist[pd.out] = v;
-      if (MODE != MODE_DIST) a.out_aux[pd.out] = vx;
+      if (MODE == MODE_SUB) {
+        a.out_dist[pd.out] = sub_best;
+        a.out_aux[pd.out] = sub_start;
+        a.out_end[pd.out] = sub_end;
+      } else {
+        a.out_dist[pd.out] = v;
+        if (MODE != MODE_DIST) a.out_aux[pd.out] = vx;
+      }
     }
     wave_sync();
   }
@@ -674,8 +704,12 @@ static hipError_t launch_fwd_t(int mode, bool euc, const FwdArgs& a, int grid, h
     else
       hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_DIST_LEN, false>), dim3(sweep_groups(grid)),
                          dim3(kWave * kSweepWaves), 0, st, a);
-  } else {
+  } else if (mode == MODE_PATH) {
     hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_PATH, false>), dim3(sweep_groups(grid)),
+                       dim3(kWave * kSweepWaves), 0, st, a);
+  } else {
+    if (euc) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((dtw_fwd_kernel<TX, TY, D, RHO, MODE_SUB, false>), dim3(sweep_groups(grid)),
                        dim3(kWave * kSweepWaves), 0, st, a);
   }
   return hipGetLastError();
@@ -710,21 +744,26 @@ static hipError_t launch_fwd_d(int mode, bool euc, bool x_is_cycle, int ydtype,
     default: return hipErrorInvalidValue; \
   }
 
-// rho = 5 serves barycenter plans only (value+length and path sweeps).
+// rho = 5 serves barycenter plans only (value+length, path and Sub-DTW sweeps).
 template <int D, int RHO>
 static hipError_t launch_fwd_bary(int mode, bool euc, bool x_is_cycle, int ydtype,
                                   const FwdArgs& a, int grid, hipStream_t st) {
   if (x_is_cycle || mode == MODE_DIST) return hipErrorInvalidValue;
   const dim3 g(sweep_groups(grid)), b(kWave * kSweepWaves);
+  if (mode == MODE_SUB && euc) return hipErrorInvalidValue;
   if (ydtype == 0) {
-    if (mode == MODE_PATH)
+    if (mode == MODE_SUB)
+      hipLaunchKernelGGL((dtw_fwd_kernel<double, float, D, RHO, MODE_SUB, false>), g, b, 0, st, a);
+    else if (mode == MODE_PATH)
       hipLaunchKernelGGL((dtw_fwd_kernel<double, float, D, RHO, MODE_PATH, false>), g, b, 0, st, a);
     else if (euc)
       hipLaunchKernelGGL((dtw_fwd_kernel<double, float, D, RHO, MODE_DIST_LEN, true>), g, b, 0, st, a);
     else
       hipLaunchKernelGGL((dtw_fwd_kernel<double, float, D, RHO, MODE_DIST_LEN, false>), g, b, 0, st, a);
   } else {
-    if (mode == MODE_PATH)
+    if (mode == MODE_SUB)
+      hipLaunchKernelGGL((dtw_fwd_kernel<double, double, D, RHO, MODE_SUB, false>), g, b, 0, st, a);
+    else if (mode == MODE_PATH)
       hipLaunchKernelGGL((dtw_fwd_kernel<double, double, D, RHO, MODE_PATH, false>), g, b, 0, st, a);
     else if (euc)
       hipLaunchKernelGGL((dtw_fwd_kernel<double, double, D, RHO, MODE_DIST_LEN, true>), g, b, 0, st, a);
@@ -809,6 +848,22 @@ hipError_t launch_score(const double* dist, const int* len, int n, double* score
                         int64_t* path_len, hipStream_t st) {
   hipLaunchKernelGGL(score_kernel, dim3((n + 255) / 256), dim3(256), 0, st, dist, len, n, score,
                      path_len);
+  return hipGetLastError();
+}
+
+// Sub-DTW columns (a*, b*) as int64.
+__global__ void sub_out_kernel(const int* __restrict__ start, const int* __restrict__ end, int n,
+                               int64_t* __restrict__ a_star, int64_t* __restrict__ b_star) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  a_star[p] = start[p];
+  b_star[p] = end[p];
+}
+
+hipError_t launch_sub_out(const int* start, const int* end, int n, int64_t* a_star,
+                          int64_t* b_star, hipStream_t st) {
+  hipLaunchKernelGGL(sub_out_kernel, dim3((n + 255) / 256), dim3(256), 0, st, start, end, n,
+                     a_star, b_star);
   return hipGetLastError();
 }
 

@@ -37,6 +37,8 @@ hipError_t launch_dba_reduce(const double* psum, const int* pcnt, const double* 
                              int64_t L, int d, double* bout, int64_t* counts, hipStream_t st);
 hipError_t launch_score(const double* dist, const int* len, int n, double* score,
                         int64_t* path_len, hipStream_t st);
+hipError_t launch_sub_out(const int* start, const int* end, int n, int64_t* a_star,
+                          int64_t* b_star, hipStream_t st);
 hipError_t launch_medoid(const double* pair_dist, const int2* pair_ab, int n_pairs, int n,
                          double* Dm, double* totals, int32_t* medoid, hipStream_t st);
 hipError_t launch_soft(int d, int ydtype, bool bwd, const SoftArgs& a, int grid, hipStream_t st);

@@ -206,6 +206,32 @@ def make(k: int, *, n: Optional[int] = None, len_range=None, L: Optional[int] = 
     raise ValueError("workload index must be 1..5")
 
 
+def make_stream(seed: int, n_cycles: int, len_range=(15000, 17500), d: int = 3,
+                idle_frac=(0.0, 0.08), dtype: str = "f32"):
+    """A long quasi-periodic stream for the segmentation step (Sec. III-A,
+    Sec. IV-B: a robot repeating its task): ``n_cycles`` warped, noisy copies
+    of one template, each with about 1 % of its samples dropped in gaps, and
+    after each an idle stretch (the last value held, plus noise) of
+    U(idle_frac) times the cycle length.  The reference cycle X is one more
+    such cycle, as an operator would delimit it.  Returns (X, Y, bounds) with
+    bounds[k] = (first, last) sample of cycle k in Y."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = len_range
+    tmpl = _FourierTemplate(rng, d)
+    X, _ = _with_gaps(rng, _cycle(rng, tmpl, int(rng.integers(lo, hi + 1)), d))
+    parts, bounds, pos = [], [], 0
+    for _ in range(n_cycles):
+        c, _ = _with_gaps(rng, _cycle(rng, tmpl, int(rng.integers(lo, hi + 1)), d))
+        idle_n = int(rng.uniform(*idle_frac) * c.shape[0])
+        idle = c[-1][None, :] + rng.normal(0.0, NOISE_STD, (idle_n, d))
+        bounds.append((pos, pos + c.shape[0] - 1))
+        parts += [c, idle]
+        pos += c.shape[0] + idle_n
+    Y = np.concatenate(parts)
+    t = np.float32 if dtype == "f32" else np.float64
+    return X.astype(t), Y.astype(t), bounds
+
+
 def integer_pair(rng: np.random.Generator, L: int, N: int, d: int, hi: int = 3):
     """Small-integer series: exact arithmetic and many tied optimal paths."""
     x = rng.integers(0, hi + 1, (L, d)).astype(np.float64)

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libwetsand_mi.so")
 
 F32, F64 = 0, 1
 COST_SQ, COST_EUCLID = 0, 1
-OP_ALIGN, OP_ALIGN_PATHS, OP_DBA, OP_SCORE, OP_SOFT_FWD, OP_SOFT_BWD, OP_MEDOID = range(7)
+OP_ALIGN, OP_ALIGN_PATHS, OP_DBA, OP_SCORE, OP_SOFT_FWD, OP_SOFT_BWD, OP_MEDOID, OP_SUBDTW = range(8)
 INIT_EUCLID_MEAN, INIT_NEAREST, INIT_COPY = 0, 1, 2
 
 _lib = None
@@ -62,6 +62,7 @@ def load():
         "wts_plan_timing": [P, I32],
         "wts_plan_sweep_ms": [P, ctypes.c_int, P, P],
         "wts_plan_rho": [P, ctypes.c_int],
+        "wts_subdtw": [P, P, P, P, P, P, P, SZ, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -81,7 +82,7 @@ def exported_symbols():
     return ["wts_plan_create", "wts_plan_destroy", "wts_workspace_bytes", "wts_last_error",
             "wts_dtw_align", "wts_dba_iterate", "wts_anomaly_score", "wts_softdtw_forward",
             "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step",
-            "wts_plan_timing", "wts_plan_sweep_ms", "wts_plan_rho"]
+            "wts_plan_timing", "wts_plan_sweep_ms", "wts_plan_rho", "wts_subdtw"]
 
 
 def _check(rc: int):
@@ -245,6 +246,20 @@ def anomaly_score(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor):
     _check(load().wts_anomaly_score(plan.handle, _ptr(bary), _ptr(cycles), _ptr(score),
                                     _ptr(dist), _ptr(plen), _ptr(ws), ws.numel(), _stream()))
     return score, dist, plen
+
+
+def subdtw(plan: Plan, x: torch.Tensor, windows: torch.Tensor):
+    """Sec. III-A, Eq. 2: Sub-DTW of the reference x ([L][d] float64) against
+    every window of the plan's batch: (value [n] f64, a* [n] i64, b* [n] i64),
+    0-based columns of each window."""
+    n = plan.n
+    value = torch.empty(n, dtype=torch.float64, device=_dev(plan))
+    a = torch.empty(n, dtype=torch.int64, device=_dev(plan))
+    b = torch.empty(n, dtype=torch.int64, device=_dev(plan))
+    ws = plan.workspace(OP_SUBDTW)
+    _check(load().wts_subdtw(plan.handle, _ptr(x), _ptr(windows), _ptr(value), _ptr(a), _ptr(b),
+                             _ptr(ws), ws.numel(), _stream()))
+    return value, a, b
 
 
 def medoid(plan: Plan, cycles: torch.Tensor, with_matrix: bool = True):
@@ -423,3 +438,53 @@ def softdtw_descent_step(groups, cycles: torch.Tensor, offsets, bary: torch.Tens
         H += h
     precond_step(bary, G, H, eta)
     return values
+
+
+def segment_alpha(M: int) -> int:
+    """alpha = 0.15 M (Sec. III-A), in whole samples (rounded down)."""
+    return int(0.15 * M)
+
+
+def segment(x: torch.Tensor, streams: Sequence[torch.Tensor], dtype: str,
+            alpha: Optional[int] = None, device: int = 0):
+    """The segmentation of Sec. III-A for several streams at once.
+
+    Each stream s keeps a window start ws_s (0 at first).  Every round runs
+    one Sub-DTW launch over the windows streams[s][ws_s : ws_s + 2M] of the
+    streams not yet finished, records the cycle [ws_s + a*, ws_s + b*] of
+    each, and moves ws_s to ws_s + b* - alpha -- or, where that would not
+    move it forward, to ws_s + b* + 1 -- until ws_s reaches the end of its
+    stream.  x: [M][d] float64 reference;
+    streams: [N_s][d] tensors of the plans' storage dtype.  Returns, per
+    stream, the list of (a*, b*, value) with absolute sample indices.
+
+    Plans are cached by window lengths, so rounds in which every window is
+    2M long reuse one plan."""
+    M, d = int(x.shape[0]), int(x.shape[1])
+    al = segment_alpha(M) if alpha is None else int(alpha)
+    ws = [0] * len(streams)
+    out = [[] for _ in streams]
+    plans = {}
+    try:
+        while True:
+            live = [k for k, y in enumerate(streams) if ws[k] < y.shape[0]]
+            if not live:
+                break
+            ends = [min(ws[k] + 2 * M, streams[k].shape[0]) for k in live]
+            lens = tuple(e - ws[k] for k, e in zip(live, ends))
+            plan = plans.get(lens)
+            if plan is None:
+                off = np.zeros(len(lens) + 1, dtype=np.int64)
+                off[1:] = np.cumsum(lens)
+                plan = plans[lens] = Plan(off, d, dtype, M, device=device)
+            win = torch.cat([streams[k][ws[k]:e] for k, e in zip(live, ends)]).contiguous()
+            v, a, b = subdtw(plan, x, win)
+            v, a, b = v.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy()
+            for q, k in enumerate(live):
+                out[k].append((ws[k] + int(a[q]), ws[k] + int(b[q]), float(v[q])))
+                bq = int(b[q])
+                ws[k] = ws[k] + bq - al if bq - al > 0 else ws[k] + bq + 1
+    finally:
+        for p in plans.values():
+            p.close()
+    return out

@@ -1,0 +1,138 @@
+"""GPU parity of Sub-DTW (Sec. III-A, Eq. 2) and of the segmentation loop
+against the FP64 oracle, through the C ABI.
+
+The Sub-DTW sweep runs the DTW recurrence with a free start in float64 with
+the oracle's operation order, so the value, the end column b* (lowest column
+of the minimal last-row cost) and the start column a* (backtracked with the
+diag > up > left rule) must match BIT FOR BIT.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_12134_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def run_sub(wts, X, windows, dtype=None, **kw):
+    import torch
+    Y, off, dt = wts.pack_cycles(windows, dtype=dtype)
+    plan = wts.Plan(off, X.shape[1], dt, X.shape[0], **kw)
+    Xt = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).cuda()
+    v, a, b = wts.subdtw(plan, Xt, Y)
+    torch.cuda.synchronize()
+    assert wts.device_status(plan, wts.OP_SUBDTW) == 0
+    return v.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy()
+
+
+def stored(windows, dtype):
+    """The window values as the GPU sees them (float32 storage widened)."""
+    t = np.float32 if dtype == "f32" else np.float64
+    return [np.asarray(w, dtype=t).astype(np.float64) for w in windows]
+
+
+SHAPES = [  # (M, window lengths): one and several strips, windows shorter than M
+    (1, [1, 7, 64]),
+    (5, [1, 2, 40, 65]),
+    (64, [128, 30, 200]),
+    (200, [400, 399, 1, 64]),
+    (257, [514, 600]),
+    (700, [1400, 350, 1000]),
+]
+
+
+@pytest.mark.parametrize("d", [1, 3, 6])
+@pytest.mark.parametrize("M,lens", SHAPES)
+def test_subdtw_bitwise(wts, d, M, lens):
+    r = rng(1000 * d + M)
+    X = r.standard_normal((M, d))
+    # windows holding a warped, noisy copy of X somewhere, or only noise
+    wins = []
+    for k, N in enumerate(lens):
+        w = r.standard_normal((N, d))
+        if N >= 4 and k % 2 == 0:
+            m = max(1, min(N - 2, int(0.7 * M)))
+            idx = np.sort(r.integers(0, M, m))
+            p0 = int(r.integers(0, N - m + 1))
+            w[p0:p0 + m] = X[idx] + 0.05 * r.standard_normal((m, d))
+        wins.append(w)
+    for dtype in ("f32", "f64"):
+        say("subdtw d=%d M=%d lens=%s %s" % (d, M, lens, dtype))
+        v, a, b = run_sub(wts, X, wins, dtype=dtype)
+        ov, oa, ob = oracle.subdtw_batch(X, stored(wins, dtype))
+        np.testing.assert_array_equal(v, ov)
+        np.testing.assert_array_equal(a, oa)
+        np.testing.assert_array_equal(b, ob)
+
+
+@pytest.mark.parametrize("rho", [2, 4, 5])
+def test_subdtw_ties_and_tile_shapes(wts, rho):
+    """Small-integer series (many tied paths and tied last-row minima) under
+    every sweep shape."""
+    r = rng(77 + rho)
+    for M in (3, 130, 333):
+        X = r.integers(0, 3, (M, 2)).astype(np.float64)
+        wins = [r.integers(0, 3, (N, 2)).astype(np.float64) for N in (1, 9, M, 2 * M + 5)]
+        say("subdtw ties rho=%d M=%d" % (rho, M))
+        v, a, b = run_sub(wts, X, wins, dtype="f64", rho=rho)
+        ov, oa, ob = oracle.subdtw_batch(X, wins)
+        np.testing.assert_array_equal(v, ov)
+        np.testing.assert_array_equal(a, oa)
+        np.testing.assert_array_equal(b, ob)
+
+
+def test_subdtw_embedded_copies(wts):
+    r = rng(5)
+    X = r.standard_normal((300, 3))
+    wins, where = [], []
+    for p0 in (0, 17, 300):
+        w = r.standard_normal((600, 3))
+        w[p0:p0 + 300] = X
+        wins.append(w)
+        where.append(p0)
+    v, a, b = run_sub(wts, X, wins, dtype="f64")
+    np.testing.assert_array_equal(v, 0.0)
+    np.testing.assert_array_equal(a, where)
+    np.testing.assert_array_equal(b, [p + 299 for p in where])
+
+
+def test_subdtw_rejects_euclid_plans(wts):
+    import torch
+    Y, off, dt = wts.pack_cycles([np.zeros((10, 1))], dtype="f64")
+    plan = wts.Plan(off, 1, dt, 4, cost="euclid")
+    with pytest.raises(wts.WtsError) as e:
+        wts.subdtw(plan, torch.zeros((4, 1), dtype=torch.float64, device="cuda"), Y)
+    assert e.value.status == -8
+
+
+def test_segmentation_matches_oracle(wts):
+    """Sec. III-A loop, three streams segmented together (one Sub-DTW launch
+    per round): the same cycles, in the same order, with the same costs as
+    the oracle's loop on each stream alone."""
+    import torch
+    streams, Xs = [], None
+    X, _, _ = synth.make_stream(11, 1, (190, 210), 3, dtype="f32")
+    Xd = X.astype(np.float64)
+    for seed, n_cyc in ((21, 9), (22, 12), (23, 5)):
+        _, Y, _ = synth.make_stream(seed, n_cyc, (190, 210), 3, dtype="f32")
+        streams.append(Y)
+    say("segment 3 streams, M =", X.shape[0])
+    dev = [torch.from_numpy(np.ascontiguousarray(Y)).cuda() for Y in streams]
+    got = wts.segment(torch.from_numpy(Xd).cuda(), dev, "f32")
+    for Y, g in zip(streams, got):
+        want = oracle.segment(Xd, Y.astype(np.float64))
+        assert g == want
+        assert len(g) >= 3
