@@ -414,6 +414,69 @@ def irregular_section(wts, dev, dba_iters: int = 10, soft_steps: int = 10, gamma
             "batched_vs_per_cycle": speed}
 
 
+def c_min_sub(d: int) -> int:
+    """Sub-DTW sweep: the value recursion (2d + 3), two compares and two
+    selects of the carried start column."""
+    return 2 * d + 7
+
+
+def segmentation_section(wts, dev, n_streams: int = 16, n_cycles: int = 37,
+                         speedup: bool = True):
+    """The segmentation step (Sec. III-A) at the scale the paper reports for
+    its robot (Sec. IV-B: a reference cycle of about 16,300 samples, streams
+    of about 6e5 samples): a reference of 15,500..16,500 samples, 3 channels,
+    float32 streams of `n_cycles` cycles each.  `n_streams` streams are
+    segmented together (one Sub-DTW launch per round over their windows),
+    then the same streams one at a time."""
+    import numpy as np
+    import torch
+    from paper_2404_12134_amd import synth
+    lr = (15500, 16500)
+    X, _, _ = synth.make_stream(500, 1, lr, 3, template_seed=31)
+    streams = [synth.make_stream(600 + k, n_cycles, lr, 3, template_seed=31)[1]
+               for k in range(n_streams)]
+    M = X.shape[0]
+    Xt = torch.from_numpy(X.astype(np.float64)).to(dev)
+    St = [torch.from_numpy(np.ascontiguousarray(Y)).to(dev) for Y in streams]
+    al = wts.segment_alpha(M)
+
+    def cells_of(segs, N):
+        # replay the window starts of the loop: cells = M x window length
+        ws, tot = 0, 0
+        for a, b, _ in segs:
+            tot += M * (min(ws + 2 * M, N) - ws)
+            bq = b - ws
+            ws = ws + bq - al if bq - al > 0 else ws + bq + 1
+        return tot
+
+    wts.segment(Xt, St[:1], "f32")                # warm-up: code paths, allocator
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    segs = wts.segment(Xt, St, "f32")
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    cells = sum(cells_of(sg, Y.shape[0]) for sg, Y in zip(segs, streams))
+    rounds = max(len(sg) for sg in segs)
+    rec = {"workload": "segmentation: %d streams x %d cycles (3 ch f32, %d..%d samples per "
+                       "cycle, ~%d samples per stream), reference of %d samples"
+                       % (n_streams, n_cycles, lr[0], lr[1], int(np.mean([Y.shape[0] for Y in streams])), M),
+           "segments_per_stream": [len(sg) for sg in segs][:4], "rounds": rounds,
+           "cells": cells, "batched_s": round(t_batch, 4),
+           "gcups": round(cells / t_batch / 1e9, 2), "ops_per_cell": c_min_sub(3),
+           "loop_alu_frac": round(cells * c_min_sub(3) / t_batch / VALU_LANE_OPS_PEAK, 4)}
+    if speedup:
+        t0 = time.perf_counter()
+        one = [wts.segment(Xt, [y], "f32")[0] for y in St]
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t0
+        if one != segs:
+            raise RuntimeError("segmentation differs between batched and one-stream runs")
+        rec["one_stream_per_launch_s"] = round(t_one, 4)
+        rec["s_per_stream_alone"] = round(t_one / n_streams, 4)
+        rec["speedup"] = round(t_one / t_batch, 2)
+    return rec
+
+
 def only_phase(args, wts, dev):
     """One phase of the step, --steps times, for rocprofv3 counter passes.  The
     'copy' phase is a plain 1 GiB device-to-device copy: the reference for
@@ -429,8 +492,9 @@ def only_phase(args, wts, dev):
         print(json.dumps({"phase": "copy", "bytes_read": a.numel() * 8, "bytes_written": b.numel() * 8,
                           "source_hash": kernel_source_hash()}))
         return
-    if args.only in ("large", "irregular"):
-        fn = dba_large_section if args.only == "large" else irregular_section
+    if args.only in ("large", "irregular", "segment"):
+        fn = {"large": dba_large_section, "irregular": irregular_section,
+              "segment": segmentation_section}[args.only]
         rec = fn(wts, dev, speedup=not args.no_speedup)
         print(json.dumps({"phase": args.only, "source_hash": kernel_source_hash(),
                           args.only: rec}))
@@ -474,9 +538,11 @@ def main():
                     help="skip the 512-cycle DBA section")
     ap.add_argument("--no-irregular", action="store_true",
                     help="skip the 256-cycle 40k..50k section (DBA, Soft-DTW, scores)")
+    ap.add_argument("--no-segment", action="store_true",
+                    help="skip the Sub-DTW segmentation section")
     ap.add_argument("--soft-steps", type=int, default=2)
     ap.add_argument("--only", choices=["medoid", "dba", "score", "soft", "copy", "large",
-                                       "irregular"],
+                                       "irregular", "segment"],
                     help="run only one phase --steps times (for hardware-counter passes)")
     ap.add_argument("--traffic-from", metavar="DIR",
                     help="write profiles/traffic.json from rocprofv3 FETCH/WRITE_SIZE passes")
@@ -619,6 +685,8 @@ def main():
                                                speedup=not args.no_speedup)
     irregular = None if args.no_irregular else guarded(irregular_section, wts, dev,
                                                        speedup=not args.no_speedup)
+    segment = None if args.no_segment else guarded(segmentation_section, wts, dev,
+                                                   speedup=not args.no_speedup)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
 
     line = {
@@ -639,6 +707,7 @@ def main():
         "soft_dtw": soft,
         "dba_large": large,
         "irregular": irregular,
+        "segmentation": segment,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -207,17 +207,19 @@ def make(k: int, *, n: Optional[int] = None, len_range=None, L: Optional[int] = 
 
 
 def make_stream(seed: int, n_cycles: int, len_range=(15000, 17500), d: int = 3,
-                idle_frac=(0.0, 0.08), dtype: str = "f32"):
+                idle_frac=(0.0, 0.08), dtype: str = "f32", template_seed: Optional[int] = None):
     """A long quasi-periodic stream for the segmentation step (Sec. III-A,
     Sec. IV-B: a robot repeating its task): ``n_cycles`` warped, noisy copies
     of one template, each with about 1 % of its samples dropped in gaps, and
     after each an idle stretch (the last value held, plus noise) of
     U(idle_frac) times the cycle length.  The reference cycle X is one more
-    such cycle, as an operator would delimit it.  Returns (X, Y, bounds) with
-    bounds[k] = (first, last) sample of cycle k in Y."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    such cycle, as an operator would delimit it.  Streams drawn with the same
+    ``template_seed`` (default: ``seed``) repeat the same task.  Returns
+    (X, Y, bounds) with bounds[k] = (first, last) sample of cycle k in Y."""
+    tmpl = _FourierTemplate(
+        np.random.Generator(np.random.PCG64(seed if template_seed is None else template_seed)), d)
+    rng = np.random.Generator(np.random.PCG64((seed, 1)))
     lo, hi = len_range
-    tmpl = _FourierTemplate(rng, d)
     X, _ = _with_gaps(rng, _cycle(rng, tmpl, int(rng.integers(lo, hi + 1)), d))
     parts, bounds, pos = [], [], 0
     for _ in range(n_cycles):

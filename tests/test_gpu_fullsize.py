@@ -241,3 +241,33 @@ def test_config5_full_dba_and_soft(wts):
     lo, hi = yall.min(axis=0), yall.max(axis=0)
     tol = 1e-9 * (hi - lo)
     assert ((B2 >= lo - tol) & (B2 <= hi + tol)).all()
+
+
+@pytest.mark.timeout(600)
+def test_segmentation_robot_scale_sampled(wts):
+    """The segmentation step at the scale of the paper's robot (reference of
+    ~16k samples, a stream of 37 cycles, ~6e5 samples, 3 channels): the whole
+    loop on the GPU, two of its rounds recomputed by the oracle bit for bit."""
+    import torch
+    lr = (15500, 16500)
+    X, _, _ = synth.make_stream(500, 1, lr, 3, template_seed=31)
+    _, Y, bounds = synth.make_stream(600, 37, lr, 3, template_seed=31)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    M, N = X.shape[0], Y.shape[0]
+    say("segment: M = %d, N = %d" % (M, N))
+    segs = wts.segment(torch.from_numpy(X64).cuda(),
+                       [torch.from_numpy(np.ascontiguousarray(Y)).cuda()], "f32")[0]
+    al = oracle.segment_alpha(M)
+    ws = [0]
+    for a, b, _ in segs[:-1]:
+        bq = b - ws[-1]
+        ws.append(ws[-1] + bq - al if bq - al > 0 else ws[-1] + bq + 1)
+    for k in (0, len(segs) // 2):
+        w0 = ws[k]
+        say("segment: oracle on round", k, "window start", w0)
+        v, a, b = oracle.subdtw(X64, Y64[w0:min(w0 + 2 * M, N)])
+        assert segs[k] == (w0 + a, w0 + b, v)
+    # sanity (not a parity gate): how many cycles were delimited within 2 %
+    hits = sum(any(abs(a - lo) <= 0.02 * M and abs(b - hi) <= 0.02 * M for a, b, _ in segs)
+               for lo, hi in bounds)
+    say("segment: %d rounds, %d of %d cycles delimited within 2 %%" % (len(segs), hits, len(bounds)))

@@ -123,11 +123,11 @@ def test_segmentation_matches_oracle(wts):
     per round): the same cycles, in the same order, with the same costs as
     the oracle's loop on each stream alone."""
     import torch
-    streams, Xs = [], None
-    X, _, _ = synth.make_stream(11, 1, (190, 210), 3, dtype="f32")
+    streams = []
+    X, _, _ = synth.make_stream(11, 1, (190, 210), 3, dtype="f32", template_seed=7)
     Xd = X.astype(np.float64)
     for seed, n_cyc in ((21, 9), (22, 12), (23, 5)):
-        _, Y, _ = synth.make_stream(seed, n_cyc, (190, 210), 3, dtype="f32")
+        _, Y, _ = synth.make_stream(seed, n_cyc, (190, 210), 3, dtype="f32", template_seed=7)
         streams.append(Y)
     say("segment 3 streams, M =", X.shape[0])
     dev = [torch.from_numpy(np.ascontiguousarray(Y)).cuda() for Y in streams]
