@@ -623,7 +623,7 @@ def main():
     plan.enable_timing(16 * args.steps)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(True)
+        last = step(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for op in (wts.OP_MEDOID, wts.OP_DBA, wts.OP_SCORE):
@@ -662,6 +662,20 @@ def main():
                 "per_kernel_alu_frac": {k: round(sweeps[k][2] * sweeps[k][3] /
                                                  (kt[k][0] / max(1, kt[k][1]) / 1e3) /
                                                  VALU_LANE_OPS_PEAK, 4) for k in kt}}
+
+    # detection on the step's scores (Sec. IV-D thresholds), against the
+    # cycles that carry an injected drift (a sanity check, not a gate)
+    from paper_2404_12134_amd import detect
+    sc = last[0].cpu().numpy()
+    truth = np.zeros(n, dtype=bool)
+    truth[w.meta["drift"]] = True
+    detection = {"drifted_cycles": [int(i) for i in w.meta["drift"]],
+                 "top_scores": [int(i) for i in np.argsort(-sc)[:len(w.meta["drift"])]]}
+    for name, thr in (("two_sigma", detect.two_sigma_threshold(sc)),
+                      ("boxplot", detect.boxplot_threshold(sc))):
+        tp, fn, fp, tn = detect.confusion(detect.flag(sc, thr), truth)
+        detection[name] = {"threshold": round(thr, 6), "tp": tp, "fn": fn, "fp": fp, "tn": tn,
+                           "f2": round(detect.f_beta(tp, fn, fp), 3)}
 
     speed = None
     if not args.no_speedup:
@@ -704,6 +718,7 @@ def main():
         "autotune": {"op": "dba", "rows_per_lane": tuned["rho"], "grid": tuned["grid"],
                      "candidates_ms": tuned["table"]},
         "batched_vs_per_cycle": speed,
+        "detection": detection,
         "soft_dtw": soft,
         "dba_large": large,
         "irregular": irregular,

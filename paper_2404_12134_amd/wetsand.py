@@ -488,3 +488,34 @@ def segment(x: torch.Tensor, streams: Sequence[torch.Tensor], dtype: str,
         for p in plans.values():
             p.close()
     return out
+
+
+def lbfgs_barycenter(plan: Plan, cycles: torch.Tensor, bary0: torch.Tensor, gamma: float,
+                     weights: Optional[torch.Tensor] = None, max_iter: int = 40,
+                     max_eval: int = 200, tolerance_grad: float = 1e-8,
+                     tolerance_change: float = 1e-5, history_size: int = 10):
+    """Soft-DTW barycenter with the optimizer of the paper's Table I: L-BFGS
+    on f(B) = sum_k w_k Soft-DTW^gamma(B, C_k) (Eq. 7 with w_k = lambda_k / m_k
+    supplied by the caller; default 1), at most `max_iter` iterations and
+    `max_eval` evaluations of f, stopping on a gradient of max-norm below
+    `tolerance_grad` or a change of f or B below `tolerance_change`.  Every
+    evaluation is one forward (checkpoints) and one E-matrix backward on the
+    GPU; torch.optim.LBFGS (strong-Wolfe line search) only combines the
+    resulting [L][d] gradients.  Returns (B, history of f values)."""
+    B = bary0.detach().to(dtype=torch.float64).contiguous().clone().requires_grad_(True)
+    w = (torch.ones(plan.n, dtype=torch.float64, device=B.device) if weights is None
+         else weights.to(device=B.device, dtype=torch.float64))
+    opt = torch.optim.LBFGS([B], lr=1.0, max_iter=max_iter, max_eval=max_eval,
+                            tolerance_grad=tolerance_grad, tolerance_change=tolerance_change,
+                            history_size=history_size, line_search_fn="strong_wolfe")
+    hist = []
+
+    def closure():
+        opt.zero_grad()
+        f = (SoftDTW.apply(B, plan, cycles, gamma) * w).sum()
+        f.backward()
+        hist.append(float(f.detach()))
+        return f.detach()
+
+    opt.step(closure)
+    return B.detach(), hist
