@@ -70,9 +70,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str):
+def traffic_from_profiles(kernel: str, name: str = None):
     """HBM bytes per launch measured with rocprofv3 PMC counters, if the
-    committed measurement was taken on the current kernel source."""
+    committed measurement was taken on the current kernel source (and, when
+    `name` is given, on that kernel instance)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -81,6 +82,8 @@ def traffic_from_profiles(kernel: str):
     except Exception:
         return None
     if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    if name is not None and rec.get("kernel", "").replace("void ", "") != name:
         return None
     return rec.get("bytes_per_launch")
 
@@ -504,13 +507,15 @@ def only_phase(args, wts, dev):
         torch.cuda.synchronize()
         print(json.dumps({"phase": "soft", "source_hash": kernel_source_hash(), "soft_dtw": rec}))
         return
+    from paper_2404_12134_amd import autotune
     w = synth.make(2)
     Y, off, dt = wts.pack_cycles(w.cycles)
-    mplan = wts.Plan(off, w.d, dt, 0)
+    # the same tuned sweep shapes as the full bench
+    mplan, _ = autotune.tuned_plan(off, w.d, dt, 0, op="medoid", cycles=Y, cache_path=None)
     k0 = int(wts.medoid(mplan, Y, with_matrix=False)[0].item())
     L = int(w.lengths[k0])
-    plan = wts.Plan(off, w.d, dt, L)
-    B, _ = wts.init_barycenter(plan, Y, wts.INIT_COPY, k0)
+    B, _ = wts.init_barycenter(wts.Plan(off, w.d, dt, L), Y, wts.INIT_COPY, k0)
+    plan, _ = autotune.tuned_plan(off, w.d, dt, L, op="dba", cycles=Y, bary=B, cache_path=None)
     Bo = torch.empty_like(B)
     counts = torch.empty(L, dtype=torch.int64, device=dev)
     dist = torch.empty(w.n, dtype=torch.float64, device=dev)
@@ -568,12 +573,12 @@ def main():
     w = synth.make(2)
     lens = w.lengths
     Y, off, dt = wts.pack_cycles(w.cycles)
-    mplan = wts.Plan(off, w.d, dt, 0)
+    # sweep shapes of the medoid and barycenter plans: picked by timing the
+    # candidates on this batch (outside the timed region)
+    from paper_2404_12134_amd import autotune
+    mplan, mtuned = autotune.tuned_plan(off, w.d, dt, 0, op="medoid", cycles=Y, cache_path=None)
     k0 = int(wts.medoid(mplan, Y, with_matrix=False)[0].item())
     L = int(lens[k0])
-    # sweep shape of the barycenter plan: picked by timing the candidates on
-    # this batch (outside the timed region)
-    from paper_2404_12134_amd import autotune
     B0, _ = wts.init_barycenter(wts.Plan(off, w.d, dt, L), Y, wts.INIT_COPY, k0)
     plan, tuned = autotune.tuned_plan(off, w.d, dt, L, op="dba", cycles=Y, bary=B0,
                                       cache_path=None)
@@ -653,9 +658,10 @@ def main():
     launch_s = kt[dom][0] / max(1, kt[dom][1]) / 1e3
     achieved = cells * cm / launch_s / 1e12
     peak = VALU_LANE_OPS_PEAK / 1e12
-    roofline = {"bound": "alu", "kernel": KERNELS[dom].format(rho=pl.rho(op)).replace("void ", ""),
+    kname = KERNELS[dom].format(rho=pl.rho(op)).replace("void ", "")
+    roofline = {"bound": "alu", "kernel": kname,
                 "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(dom),
+                "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(dom, kname),
                 "ops_per_cell": cm, "cells_per_launch": cells,
                 "launch_ms": round(launch_s * 1e3, 3),
                 "per_kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in kt.items()},
@@ -715,8 +721,10 @@ def main():
                         "dba_iteration": round(cells_bary / t_dba / 1e9, 2),
                         "score": round(cells_bary / t_score / 1e9, 2)},
         "roofline": roofline,
-        "autotune": {"op": "dba", "rows_per_lane": tuned["rho"], "grid": tuned["grid"],
-                     "candidates_ms": tuned["table"]},
+        "autotune": {"dba": {"rows_per_lane": tuned["rho"], "grid": tuned["grid"],
+                             "candidates_ms": tuned["table"]},
+                     "medoid": {"rows_per_lane": mtuned["rho"], "grid": mtuned["grid"],
+                                "candidates_ms": mtuned["table"]}},
         "batched_vs_per_cycle": speed,
         "detection": detection,
         "soft_dtw": soft,

@@ -90,7 +90,8 @@ typedef struct {
                          the medoid always use the squared cost                              */
   int32_t rho;        /* rows per lane in the wavefront sweeps: 0 = automatic (4, or 5 for
                          barycenter plans whose strips would just about fill every SIMD);
-                         2 or 4 for any plan, 5 for barycenter plans (the medoid then uses 4) */
+                         2, 4 or 5 for any plan (Soft-DTW sweeps always use 2); other
+                         values return WTS_E_UNSUPPORTED                                     */
   int32_t grid;       /* workgroups of the persistent sweep (0 = tuned default)              */
   int32_t reserved;   /* must be 0                                                           */
 } wts_opts;

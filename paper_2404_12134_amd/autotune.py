@@ -1,7 +1,7 @@
 """Autotuner for the sweep shape of a plan.
 
 A plan's wavefront sweeps have two shape parameters (`wts_opts`): the rows per
-lane of a strip (rho: 2, 4, or 5 for barycenter plans) and the number of
+lane of a strip (rho: 2, 4 or 5) and the number of
 persistent sweep wavefronts (grid).  Which shape is fastest depends on the
 batch: with few long pairs the chain fill and the one-wave-per-SIMD issue rate
 dominate, with many pairs the per-cell instruction count does.  `tune` times
@@ -67,7 +67,7 @@ def store_cache(path: str, key: str, entry: dict) -> None:
 
 def candidates(op: str) -> Iterable[Tuple[int, int]]:
     """(rho, grid) shapes to try; grid 0 is the library's default."""
-    rhos = (2, 4) if op == "medoid" else (2, 4, 5)
+    rhos = (2, 4, 5)
     for rho in rhos:
         yield rho, 0
 

@@ -370,7 +370,7 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   p->dtype = dtype;
   p->L = L;
   p->opts = o;
-  p->rho = (o.rho == 2 || o.rho == 4) ? o.rho : 4;   // medoid sweeps: 2 or 4
+  p->rho = o.rho ? o.rho : 4;   // medoid sweeps: 2, 4 or 5 (4 when automatic)
   p->off.assign(offsets_host, offsets_host + n + 1);
   for (int k = 0; k < n; ++k) p->nmax = std::max(p->nmax, p->off[k + 1] - p->off[k]);
 

@@ -773,13 +773,28 @@ static hipError_t launch_fwd_bary(int mode, bool euc, bool x_is_cycle, int ydtyp
   return hipGetLastError();
 }
 
+// rho = 5 for the medoid: the value sweep between two cycles.
+template <int D, int RHO>
+static hipError_t launch_fwd_med(int mode, int ydtype, const FwdArgs& a, int grid, hipStream_t st) {
+  if (mode != MODE_DIST) return hipErrorInvalidValue;
+  const dim3 g(sweep_groups(grid)), b(kWave * kSweepWaves);
+  if (ydtype == 0)
+    hipLaunchKernelGGL((dtw_fwd_kernel<float, float, D, RHO, MODE_DIST, false>), g, b, 0, st, a);
+  else
+    hipLaunchKernelGGL((dtw_fwd_kernel<double, double, D, RHO, MODE_DIST, false>), g, b, 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_fwd(int d, int rho, int mode, bool euc, bool x_is_cycle, int ydtype,
                       const FwdArgs& a, int grid, hipStream_t st) {
 #define CALLF(D, R) launch_fwd_d<D, R>(mode, euc, x_is_cycle, ydtype, a, grid, st)
 #define CALLB(D, R) launch_fwd_bary<D, R>(mode, euc, x_is_cycle, ydtype, a, grid, st)
+#define CALLM(D, R) launch_fwd_med<D, R>(mode, ydtype, a, grid, st)
   if (rho == 4) { WTS_D_SWITCH(d, 4, CALLF) }
   if (rho == 2) { WTS_D_SWITCH(d, 2, CALLF) }
+  if (rho == 5 && x_is_cycle) { WTS_D_SWITCH(d, 5, CALLM) }
   if (rho == 5) { WTS_D_SWITCH(d, 5, CALLB) }
+#undef CALLM
 #undef CALLB
 #undef CALLF
   return hipErrorInvalidValue;

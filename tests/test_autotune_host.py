@@ -34,7 +34,7 @@ def test_cache_round_trip(tmp_path):
 
 def test_candidates_cover_the_supported_shapes():
     assert sorted(r for r, _ in autotune.candidates("dba")) == [2, 4, 5]
-    assert sorted(r for r, _ in autotune.candidates("medoid")) == [2, 4]
+    assert sorted(r for r, _ in autotune.candidates("medoid")) == [2, 4, 5]
 
 
 def test_tune_rejects_op_plan_mismatch_before_any_gpu_call():

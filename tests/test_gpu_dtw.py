@@ -260,11 +260,13 @@ def test_init_kinds_bitwise(wts):
     np.testing.assert_array_equal(b.cpu().numpy(), oracle.resample(as64(w.cycles)[3], 120))
 
 
-def test_medoid_sampled_bitwise(wts):
+@pytest.mark.parametrize("rho", [0, 2, 5])
+def test_medoid_sampled_bitwise(wts, rho):
     w = synth.make(2, n=9, len_range=(200, 700))
     Y, off, dt = wts.pack_cycles(w.cycles)
-    plan = wts.Plan(off, 3, dt, 0)
-    say("case medoid")
+    plan = wts.Plan(off, 3, dt, 0, rho=rho)
+    assert plan.rho(wts.OP_MEDOID) == (rho or 4)
+    say("case medoid rho", rho)
     k, Dm, tot = wts.medoid(plan, Y)
     ko, Do = oracle.medoid(as64(w.cycles))
     np.testing.assert_array_equal(Dm.cpu().numpy(), Do)
