@@ -95,12 +95,6 @@ KERNELS = {   # sweep -> rocprofv3 kernel name, by rows per lane (rho) of the pl
 }
 
 
-def kernel_pattern(key: str):
-    import re
-    pre, post = KERNELS[key].split("{rho}")
-    return re.compile(re.escape(pre) + r"\d+" + re.escape(post))
-
-
 def ingest_traffic(root: str):
     """Reads rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes (CSV) found under
     `root` and writes profiles/traffic.json: HBM bytes per launch of every sweep
@@ -111,10 +105,14 @@ def ingest_traffic(root: str):
     import glob
     # every pass must have run the current kernel source (its --only line says which)
     hashes = set()
+    used = {}              # phase -> the sweep kernel instance its timed steps ran
     for f in glob.glob(os.path.join(root, "**", "*.out"), recursive=True):
         for line in open(f, errors="replace"):
             if line.startswith("{") and '"phase"' in line:
-                hashes.add(json.loads(line).get("source_hash"))
+                rec = json.loads(line)
+                hashes.add(rec.get("source_hash"))
+                if rec.get("kernel"):
+                    used[rec["phase"]] = rec["kernel"]
     if hashes != {kernel_source_hash()}:
         raise SystemExit("counter passes under %s ran kernel sources %s, not the current %s"
                          % (root, sorted(map(str, hashes)), kernel_source_hash()))
@@ -137,12 +135,14 @@ def ingest_traffic(root: str):
     out = {"_calibration": {"copy_bytes": int(gib), "fetch_kib": f_cal, "write_kib": w_cal,
                             "fetch_scale": f_scale, "write_scale": w_scale}}
     for key in KERNELS:
-        pat = kernel_pattern(key)
-        fk = [(k[0], avg[k]) for k in avg if pat.match(k[0]) and k[1] == "FETCH_SIZE"]
-        wk = [avg[k] for k in avg if pat.match(k[0]) and k[1] == "WRITE_SIZE"]
+        # the phase's own kernel instance (the sweep-shape tuner that runs
+        # first launches the other instances too)
+        name = used.get(key)
+        if name is None:
+            continue
+        fk = [avg[k] for k in avg if k[0].split("(wts::")[0] == name and k[1] == "FETCH_SIZE"]
+        wk = [avg[k] for k in avg if k[0].split("(wts::")[0] == name and k[1] == "WRITE_SIZE"]
         if fk and wk:
-            name = fk[0][0].split("(wts::")[0]
-            fk = [v for _, v in fk]
             out[key] = {"kernel": name, "source_hash": kernel_source_hash(),
                         "fetch_bytes": fk[0] * f_scale, "write_bytes": wk[0] * w_scale,
                         "bytes_per_launch": fk[0] * f_scale + wk[0] * w_scale}
@@ -527,7 +527,10 @@ def only_phase(args, wts, dev):
         else:
             wts.anomaly_score(plan, B, Y)
     torch.cuda.synchronize()
-    print(json.dumps({"phase": args.only, "L": L, "source_hash": kernel_source_hash()}))
+    used = {"medoid": mplan.rho(wts.OP_MEDOID), "dba": plan.rho(wts.OP_DBA),
+            "score": plan.rho(wts.OP_SCORE)}[args.only]
+    print(json.dumps({"phase": args.only, "L": L, "source_hash": kernel_source_hash(),
+                      "kernel": KERNELS[args.only].format(rho=used)}))
 
 
 def main():
