@@ -111,12 +111,18 @@ def test_config3_full_sampled(wts):
     assert int(counts.sum().item()) == int(plen.sum().item())
 
 
+@functools.lru_cache(maxsize=1)
+def _config4():
+    return synth.make(4)
+
+
 @pytest.mark.timeout(900)
-def test_config4_full_soft_sampled(wts):
-    """128 x 6 ch, 18000..22000, L = 20000, gamma = 0.1: values of sampled
-    cycles and the gradient weighted onto them, within 1e-4."""
+@pytest.mark.parametrize("gamma", [0.1, 1.0])
+def test_config4_full_soft_sampled(wts, gamma):
+    """128 x 6 ch, 18000..22000, L = 20000, gamma in {0.1, 1}: values of
+    sampled cycles and the gradient weighted onto them, within 1e-4."""
     import torch
-    w = synth.make(4)
+    w = _config4()
     Y, off, dt = wts.pack_cycles(w.cycles)
     plan = wts.Plan(off, 6, dt, w.L)
     cyc = f64(w.cycles)
@@ -127,14 +133,14 @@ def test_config4_full_soft_sampled(wts):
     np.testing.assert_array_equal(B.cpu().numpy(), Bo)
     wv = np.zeros(w.n)
     wv[pick] = [1.0 / lens for lens in w.lengths[pick]]
-    say("c4: Soft-DTW forward + backward on all 128 cycles")
-    val, ck = wts.softdtw_forward(plan, B, Y, 0.1)
-    g, h = wts.softdtw_backward(plan, B, Y, 0.1, ck, torch.from_numpy(wv).cuda(), with_mass=True)
+    say("c4: Soft-DTW forward + backward on all 128 cycles, gamma", gamma)
+    val, ck = wts.softdtw_forward(plan, B, Y, gamma)
+    g, h = wts.softdtw_backward(plan, B, Y, gamma, ck, torch.from_numpy(wv).cuda(), with_mass=True)
     torch.cuda.synchronize()
     assert wts.device_status(plan, wts.OP_SOFT_BWD) == 0
     del ck
     say("c4: oracle on cycles", pick)
-    ov, og, oh = oracle.softdtw_batch(Bo, [cyc[q] for q in pick], 0.1, wv[pick])
+    ov, og, oh = oracle.softdtw_batch(Bo, [cyc[q] for q in pick], gamma, wv[pick])
     check_vec(val.cpu().numpy()[pick], ov)
     check_vec(g.cpu().numpy(), og)
     check_vec(h.cpu().numpy(), oh)
