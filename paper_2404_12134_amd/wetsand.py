@@ -461,7 +461,15 @@ def segment(x: torch.Tensor, streams: Sequence[torch.Tensor], dtype: str,
     Plans are cached by window lengths, so rounds in which every window is
     2M long reuse one plan."""
     M, d = int(x.shape[0]), int(x.shape[1])
+    if x.dtype != torch.float64 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float64 [M][d] tensor")
+    want = torch.float32 if dtype == "f32" else torch.float64
+    for y in streams:
+        if y.dtype != want or y.dim() != 2 or int(y.shape[1]) != d:
+            raise ValueError("every stream must be a [N][%d] %s tensor" % (d, want))
     al = segment_alpha(M) if alpha is None else int(alpha)
+    if al < 0:
+        raise ValueError("alpha must be >= 0")
     ws = [0] * len(streams)
     out = [[] for _ in streams]
     plans = {}
