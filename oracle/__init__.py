@@ -51,6 +51,11 @@ def lib():
         L.wts_o_score_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P, P]
         L.wts_o_dba_iterate.argtypes = [P, I64, P, P, I32, I32, P, P, P, P, P]
         L.wts_o_softdtw.argtypes = [P, I64, P, I64, I32, D, P, P]
+        L.wts_o_softdtw_band.argtypes = [P, I64, P, I64, I32, D, D, P, P]
+        L.wts_o_softdtw_grad_band.argtypes = [P, I64, P, I64, I32, D, D, P, P, P, P]
+        L.wts_o_softdtw_batch_band.argtypes = [P, I64, P, P, I32, I32, D, D, P, P, P, P]
+        L.wts_o_band_cols.argtypes = [I64, I64, D, I64, P, P]
+        L.wts_o_band_cols.restype = None
         L.wts_o_softdtw_grad.argtypes = [P, I64, P, I64, I32, D, P, P, P, P]
         L.wts_o_softdtw_batch.argtypes = [P, I64, P, P, I32, I32, D, P, P, P, P]
         L.wts_o_medoid.argtypes = [P, P, I32, I32, P, P]
@@ -63,7 +68,8 @@ def lib():
         for f in ("wts_o_dtw", "wts_o_dtw_batch", "wts_o_score_batch", "wts_o_dba_iterate",
                   "wts_o_softdtw", "wts_o_softdtw_grad", "wts_o_softdtw_batch", "wts_o_medoid",
                   "wts_o_euclid_mean", "wts_o_nearest_init", "wts_o_num_threads",
-                  "wts_o_subdtw", "wts_o_subdtw_batch"):
+                  "wts_o_subdtw", "wts_o_subdtw_batch", "wts_o_softdtw_band",
+                  "wts_o_softdtw_grad_band", "wts_o_softdtw_batch_band"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -155,16 +161,26 @@ def dba_iterate(B, cycles, weights=None):
     return Bout, counts, dist, plen
 
 
-def softdtw(X, Y, gamma, with_R=False):
+def band_cols(M: int, N: int, band: float, i: int):
+    """Columns [jlo, jhi] of row i inside the Sakoe-Chiba band (Table I)."""
+    lo = np.zeros(1, dtype=np.int64)
+    hi = np.zeros(1, dtype=np.int64)
+    lib().wts_o_band_cols(int(M), int(N), float(band), int(i), _p(lo), _p(hi))
+    return int(lo[0]), int(hi[0])
+
+
+def softdtw(X, Y, gamma, with_R=False, band=0.0):
+    """Eq. 3-5 (band > 0: restricted to the Sakoe-Chiba band of Table I)."""
     X, Y = _series(X), _series(Y)
     M, N = X.shape[0], Y.shape[0]
     v = np.zeros(1)
     R = np.zeros((M, N)) if with_R else None
-    _check(lib().wts_o_softdtw(_p(X), M, _p(Y), N, X.shape[1], float(gamma), _p(v), _p(R)))
+    _check(lib().wts_o_softdtw_band(_p(X), M, _p(Y), N, X.shape[1], float(gamma), float(band),
+                                    _p(v), _p(R)))
     return (float(v[0]), R) if with_R else float(v[0])
 
 
-def softdtw_grad(X, Y, gamma, with_E=False):
+def softdtw_grad(X, Y, gamma, with_E=False, band=0.0):
     """Eq. 6: returns (value, grad [M][d], rowmass [M], E [M][N] or None)."""
     X, Y = _series(X), _series(Y)
     M, N, d = X.shape[0], Y.shape[0], X.shape[1]
@@ -172,12 +188,12 @@ def softdtw_grad(X, Y, gamma, with_E=False):
     g = np.zeros((M, d))
     h = np.zeros(M)
     E = np.zeros((M, N)) if with_E else None
-    _check(lib().wts_o_softdtw_grad(_p(X), M, _p(Y), N, d, float(gamma), _p(v), _p(g), _p(h),
-                                    _p(E)))
+    _check(lib().wts_o_softdtw_grad_band(_p(X), M, _p(Y), N, d, float(gamma), float(band),
+                                         _p(v), _p(g), _p(h), _p(E)))
     return float(v[0]), g, h, E
 
 
-def softdtw_batch(X, cycles, gamma, weights=None, grad=True):
+def softdtw_batch(X, cycles, gamma, weights=None, grad=True, band=0.0):
     """Values [n] and, if grad, (sum_i w_i dSDTW_i/dX [M][d], sum_i w_i rowmass_i [M])."""
     X = _series(X)
     Y, off = _packed(cycles)
@@ -186,8 +202,8 @@ def softdtw_batch(X, cycles, gamma, weights=None, grad=True):
     vals = np.zeros(n)
     g = np.zeros((M, d)) if grad else None
     h = np.zeros(M) if grad else None
-    _check(lib().wts_o_softdtw_batch(_p(X), M, _p(Y), _p(off), n, d, float(gamma), _p(w),
-                                     _p(vals), _p(g), _p(h)))
+    _check(lib().wts_o_softdtw_batch_band(_p(X), M, _p(Y), _p(off), n, d, float(gamma),
+                                          float(band), _p(w), _p(vals), _p(g), _p(h)))
     return (vals, g, h) if grad else vals
 
 

@@ -123,18 +123,34 @@ def subdtw(X, Y, kind="sq"):
     return best, chosen[0][1], b_star
 
 
-def softdtw(X, Y, gamma):
+def in_band(i: int, j: int, M: int, N: int, w: float) -> bool:
+    """Sakoe-Chiba band of Table I, as this build reads it: a band of radius
+    R = ceil(w max(M, N)) around the diagonal from (0, 0) to (M-1, N-1),
+    measured along the longer side (R at least ceil(max(M-1, N-1) /
+    min(M-1, N-1))); w <= 0 is no band."""
+    if w <= 0 or M == 1 or N == 1:
+        return True
+    a, b = M - 1, N - 1
+    R = max(math.ceil(w * max(M, N)), -(-max(a, b) // min(a, b)))
+    return abs(i * b - j * a) <= R * min(a, b)
+
+
+def band_paths(M: int, N: int, w: float):
+    return [p for p in all_paths(M, N) if all(in_band(i, j, M, N, w) for i, j in p)]
+
+
+def softdtw(X, Y, gamma, band=0.0):
     X, Y = _series(X), _series(Y)
-    costs = np.array([path_cost(X, Y, p) for p in all_paths(X.shape[0], Y.shape[0])])
+    costs = np.array([path_cost(X, Y, p) for p in band_paths(X.shape[0], Y.shape[0], band)])
     m = costs.min()
     return float(m - gamma * math.log(math.fsum(np.exp(-(costs - m) / gamma))))
 
 
-def gibbs_E(X, Y, gamma):
-    """E = sum over paths of A(path) * p(path)."""
+def gibbs_E(X, Y, gamma, band=0.0):
+    """E = sum over paths (inside the band) of A(path) * p(path)."""
     X, Y = _series(X), _series(Y)
     M, N = X.shape[0], Y.shape[0]
-    paths = all_paths(M, N)
+    paths = band_paths(M, N, band)
     costs = np.array([path_cost(X, Y, p) for p in paths])
     wts = np.exp(-(costs - costs.min()) / gamma)
     wts = wts / math.fsum(wts)

@@ -238,8 +238,39 @@ static double softmin3(double a, double b, double c, double gamma) {
 /* Eq. 4-5: Soft-DTW^gamma(X, Y) = r_{M,N} with the soft-min recursion (squared
  * Euclidean delta).  R (M*N, row-major, r(i, j) of the 0-based grid) is
  * filled when non-NULL. */
-int wts_o_softdtw(const double* X, int64_t M, const double* Y, int64_t N, int d, double gamma,
-                  double* value, double* R) {
+/* Sakoe-Chiba band (Table I: the bandwidth as a fraction w of the longest
+ * signal length), read as a band around the diagonal from (0, 0) to
+ * (M-1, N-1): with R = ceil(w * max(M, N)), raised where needed to
+ * ceil(max(M-1, N-1) / min(M-1, N-1)) so that every cell of the band other
+ * than (0, 0) keeps a predecessor in the band, cell (i, j) belongs to the
+ * band iff |i (N-1) - j (M-1)| <= R * min(M-1, N-1).  Row i of the band is
+ * the column range [jlo, jhi].  w <= 0 means no band. */
+static int64_t floor_div(int64_t a, int64_t b) {   /* b > 0 */
+  int64_t q = a / b;
+  if ((a % b != 0) && (a < 0)) --q;
+  return q;
+}
+
+static void band_cols(int64_t M, int64_t N, double w, int64_t i, int64_t* jlo, int64_t* jhi) {
+  *jlo = 0;
+  *jhi = N - 1;
+  if (!(w > 0) || M == 1 || N == 1) return;
+  const int64_t a = M - 1, b = N - 1;
+  const int64_t mn = a < b ? a : b, mx = a < b ? b : a;
+  int64_t R = (int64_t)ceil(w * (double)(M > N ? M : N));
+  const int64_t Rmin = (mx + mn - 1) / mn;
+  if (R < Rmin) R = Rmin;
+  const int64_t B = R * mn;
+  /* |i b - j a| <= B  <=>  (i b - B) / a <= j <= (i b + B) / a */
+  int64_t lo = -floor_div(-(i * b - B), a);
+  int64_t hi = floor_div(i * b + B, a);
+  if (lo > *jlo) *jlo = lo;
+  if (hi < *jhi) *jhi = hi;
+}
+
+/* Eq. 5 with gamma > 0, restricted to the band (cells outside: +inf). */
+int wts_o_softdtw_band(const double* X, int64_t M, const double* Y, int64_t N, int d,
+                       double gamma, double band, double* value, double* R) {
   double* prev = (double*)malloc(sizeof(double) * (size_t)(N + 1));
   double* cur = (double*)malloc(sizeof(double) * (size_t)(N + 1));
   if (!prev || !cur) { free(prev); free(cur); return -1; }
@@ -247,9 +278,13 @@ int wts_o_softdtw(const double* X, int64_t M, const double* Y, int64_t N, int d,
   for (int64_t j = 0; j < N; ++j) prev[j + 1] = INFINITY;
   for (int64_t i = 0; i < M; ++i) {
     cur[0] = INFINITY;
+    int64_t jlo, jhi;
+    band_cols(M, N, band, i, &jlo, &jhi);
     for (int64_t j = 0; j < N; ++j) {
-      double r = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID) +
-                 softmin3(prev[j], prev[j + 1], cur[j], gamma);
+      double r = INFINITY;
+      if (j >= jlo && j <= jhi)
+        r = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID) +
+            softmin3(prev[j], prev[j + 1], cur[j], gamma);
       cur[j + 1] = r;
       if (R) R[i * N + j] = r;
     }
@@ -272,8 +307,16 @@ int wts_o_softdtw(const double* X, int64_t M, const double* Y, int64_t N, int d,
  *   grad_i = sum_j e(i, j) * 2 (x_i - y_j)   (j ascending).
  * Outputs: value, grad (M*d), rowmass (M, sum_j e(i,j); may be NULL),
  * E (M*N; may be NULL).  Needs M*N doubles for R. */
-int wts_o_softdtw_grad(const double* X, int64_t M, const double* Y, int64_t N, int d,
-                       double gamma, double* value, double* grad, double* rowmass, double* E) {
+int wts_o_softdtw(const double* X, int64_t M, const double* Y, int64_t N, int d, double gamma,
+                  double* value, double* R) {
+  return wts_o_softdtw_band(X, M, Y, N, d, gamma, 0.0, value, R);
+}
+
+/* Eq. 6 restricted to the band: cells outside it have e = 0, and a
+ * successor with e = 0 passes nothing on. */
+int wts_o_softdtw_grad_band(const double* X, int64_t M, const double* Y, int64_t N, int d,
+                            double gamma, double band, double* value, double* grad,
+                            double* rowmass, double* E) {
   double* R = (double*)malloc(sizeof(double) * (size_t)(M * N));
   double* enext = (double*)malloc(sizeof(double) * (size_t)(N + 1));
   double* ecur = (double*)malloc(sizeof(double) * (size_t)(N + 1));
@@ -283,7 +326,7 @@ int wts_o_softdtw_grad(const double* X, int64_t M, const double* Y, int64_t N, i
     free(R); free(enext); free(ecur); free(rnext); free(dnext);
     return -1;
   }
-  wts_o_softdtw(X, M, Y, N, d, gamma, value, R);
+  wts_o_softdtw_band(X, M, Y, N, d, gamma, band, value, R);
   /* row M (outside): r = -inf except r(M, N) = r(M-1, N-1); e = 0 except e(M, N) = 1 */
   for (int64_t j = 0; j <= N; ++j) { enext[j] = 0.0; rnext[j] = -INFINITY; dnext[j] = 0.0; }
   enext[N] = 1.0;
@@ -291,12 +334,19 @@ int wts_o_softdtw_grad(const double* X, int64_t M, const double* Y, int64_t N, i
   for (int64_t i = M - 1; i >= 0; --i) {
     /* column N (outside) of row i: r = -inf, e = 0, delta = 0 */
     double e_right = 0.0, r_right = -INFINITY, d_right = 0.0;
+    int64_t jlo, jhi;
+    band_cols(M, N, band, i, &jlo, &jhi);
     for (int64_t j = N - 1; j >= 0; --j) {
       double rij = R[i * N + j];
       double e = 0.0;
-      e = e + enext[j] * exp((rnext[j] - dnext[j] - rij) / gamma);              /* (i+1, j)   */
-      e = e + e_right * exp((r_right - d_right - rij) / gamma);                 /* (i, j+1)   */
-      e = e + enext[j + 1] * exp((rnext[j + 1] - dnext[j + 1] - rij) / gamma);  /* (i+1, j+1) */
+      if (j >= jlo && j <= jhi) {
+        if (enext[j] != 0.0)                                                  /* (i+1, j)   */
+          e = e + enext[j] * exp((rnext[j] - dnext[j] - rij) / gamma);
+        if (e_right != 0.0)                                                   /* (i, j+1)   */
+          e = e + e_right * exp((r_right - d_right - rij) / gamma);
+        if (enext[j + 1] != 0.0)                                              /* (i+1, j+1) */
+          e = e + enext[j + 1] * exp((rnext[j + 1] - dnext[j + 1] - rij) / gamma);
+      }
       ecur[j] = e;
       e_right = e;
       r_right = rij;
@@ -390,9 +440,14 @@ int wts_o_subdtw_batch(const double* X, int64_t M, const double* Yall, const int
  * (Eq. 7 with w_i = lambda_i / m_i supplied by the caller).  grad (M*d) and
  * rowmass (M, may be NULL) receive sum_i w_i * (per-pair quantity), summed in
  * ascending i.  values: n. */
-int wts_o_softdtw_batch(const double* X, int64_t M, const double* Yall, const int64_t* off, int n,
-                        int d, double gamma, const double* w, double* values, double* grad,
-                        double* rowmass) {
+int wts_o_softdtw_grad(const double* X, int64_t M, const double* Y, int64_t N, int d,
+                       double gamma, double* value, double* grad, double* rowmass, double* E) {
+  return wts_o_softdtw_grad_band(X, M, Y, N, d, gamma, 0.0, value, grad, rowmass, E);
+}
+
+int wts_o_softdtw_batch_band(const double* X, int64_t M, const double* Yall, const int64_t* off,
+                             int n, int d, double gamma, double band, const double* w,
+                             double* values, double* grad, double* rowmass) {
   double* pg = grad ? (double*)malloc(sizeof(double) * (size_t)(n * M * d)) : NULL;
   double* ph = rowmass ? (double*)malloc(sizeof(double) * (size_t)(n * M)) : NULL;
   if ((grad && !pg) || (rowmass && !ph)) { free(pg); free(ph); return -1; }
@@ -403,11 +458,11 @@ int wts_o_softdtw_batch(const double* X, int64_t M, const double* Yall, const in
     int64_t N = off[p + 1] - off[p];
     if (grad || rowmass) {
       double* g = pg ? pg + (int64_t)p * M * d : (double*)malloc(sizeof(double) * (size_t)(M * d));
-      err |= wts_o_softdtw_grad(X, M, Y, N, d, gamma, &values[p], g,
+      err |= wts_o_softdtw_grad_band(X, M, Y, N, d, gamma, band, &values[p], g,
                                 ph ? ph + (int64_t)p * M : NULL, NULL);
       if (!pg) free(g);
     } else {
-      err |= wts_o_softdtw(X, M, Y, N, d, gamma, &values[p], NULL);
+      err |= wts_o_softdtw_band(X, M, Y, N, d, gamma, band, &values[p], NULL);
     }
   }
   if (!err && grad) {
@@ -426,6 +481,17 @@ int wts_o_softdtw_batch(const double* X, int64_t M, const double* Yall, const in
   }
   free(pg); free(ph);
   return err ? -1 : 0;
+}
+
+int wts_o_softdtw_batch(const double* X, int64_t M, const double* Yall, const int64_t* off, int n,
+                        int d, double gamma, const double* w, double* values, double* grad,
+                        double* rowmass) {
+  return wts_o_softdtw_batch_band(X, M, Yall, off, n, d, gamma, 0.0, w, values, grad, rowmass);
+}
+
+/* Row i's band columns, exposed for the tests. */
+void wts_o_band_cols(int64_t M, int64_t N, double w, int64_t i, int64_t* jlo, int64_t* jhi) {
+  band_cols(M, N, w, i, jlo, jhi);
 }
 
 /* Medoid initialisation: D[k][i] = DTW(Y_k, Y_i) for all k != i (D[k][k] = 0),

@@ -443,3 +443,60 @@ def test_segmentation_of_exact_copies():
     segs = oracle.segment(X, Y)
     assert [(a, b, v) for a, b, v in segs[:6]] == [(s, s + M - 1, 0.0) for s in starts]
     assert oracle.segment_alpha(M) == 4
+
+
+# ------------------------------------------------- Sakoe-Chiba band (Table I)
+
+@pytest.mark.parametrize("w", [0.1, 0.3, 0.6])
+def test_softdtw_band_brute(w):
+    """Soft-DTW and E restricted to the band equal the log-sum-exp and the
+    Gibbs expectation over the paths that stay inside it."""
+    r = rng(60)
+    for M, N in ((5, 5), (3, 6), (6, 4), (1, 5), (4, 1), (6, 6)):
+        X, Y = r.standard_normal((M, 2)), r.standard_normal((N, 2))
+        for gamma in (0.1, 1.0):
+            v = oracle.softdtw(X, Y, gamma, band=w)
+            assert abs(v - brute.softdtw(X, Y, gamma, band=w)) <= 1e-9 * max(1.0, abs(v))
+            _, _, _, E = oracle.softdtw_grad(X, Y, gamma, with_E=True, band=w)
+            np.testing.assert_allclose(E, brute.gibbs_E(X, Y, gamma, band=w), rtol=1e-7, atol=1e-12)
+
+
+def test_band_cells_match_the_definition_and_keep_a_predecessor():
+    """The oracle's per-row column ranges are exactly the cells of the band;
+    the corners are inside; every other cell inside has a predecessor
+    inside (so no cell of the band is cut off)."""
+    for M, N in ((7, 7), (9, 4), (4, 9), (2, 13), (13, 2), (1, 6), (6, 1), (30, 17)):
+        for w in (0.01, 0.1, 0.25, 0.6, 2.0):
+            inside = set()
+            for i in range(M):
+                lo, hi = oracle.band_cols(M, N, w, i)
+                assert lo <= hi
+                row = {j for j in range(N) if brute.in_band(i, j, M, N, w)}
+                assert row == set(range(lo, hi + 1)), (M, N, w, i)
+                inside |= {(i, j) for j in row}
+            assert (0, 0) in inside and (M - 1, N - 1) in inside
+            for i, j in inside - {(0, 0)}:
+                assert {(i - 1, j), (i, j - 1), (i - 1, j - 1)} & inside
+
+
+def test_softdtw_wide_band_is_no_band_bitwise():
+    r = rng(61)
+    X, Y = r.standard_normal((40, 3)), r.standard_normal((33, 3))
+    a = oracle.softdtw_grad(X, Y, 0.5)
+    b = oracle.softdtw_grad(X, Y, 0.5, band=5.0)
+    assert a[0] == b[0]
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_softdtw_band_gradient_finite_differences():
+    r = rng(62)
+    X, Y = r.standard_normal((9, 2)), r.standard_normal((12, 2))
+    _, g, _, _ = oracle.softdtw_grad(X, Y, 0.7, band=0.3)
+    h = 1e-6
+    for (i, c) in ((0, 0), (4, 1), (8, 0)):
+        Xp, Xm = X.copy(), X.copy()
+        Xp[i, c] += h
+        Xm[i, c] -= h
+        fd = (oracle.softdtw(Xp, Y, 0.7, band=0.3) - oracle.softdtw(Xm, Y, 0.7, band=0.3)) / (2 * h)
+        assert abs(fd - g[i, c]) <= 1e-6 * max(1.0, abs(g[i, c]))
