@@ -94,6 +94,14 @@ typedef struct {
                          values return WTS_E_UNSUPPORTED                                     */
   int32_t grid;       /* workgroups of the persistent sweep (0 = tuned default)              */
   int32_t reserved;   /* must be 0                                                           */
+  double band;        /* Soft-DTW only: Sakoe-Chiba bandwidth as a fraction w of the longer
+                         length (Table I: 0.6); 0 = no band.  Cell (i, j) of an M x N pair
+                         is kept iff |i (N-1) - j (M-1)| <= R min(M-1, N-1) with
+                         R = max(ceil(w max(M, N)), ceil(max(M-1,N-1) / min(M-1,N-1)))
+                         (computed in float64 from this value); the Soft-DTW values and
+                         gradients are those over the paths inside the band.  Must be
+                         finite and >= 0; a band needs L and every cycle length below
+                         2^26                                                            */
 } wts_opts;
 
 /* Create a plan for a batch of n cycles of d channels (1 <= d <= 8) stored as

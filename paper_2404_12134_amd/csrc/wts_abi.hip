@@ -359,6 +359,7 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   if (o.rho != 0 && o.rho != 2 && o.rho != 4 && o.rho != 5)
     return fail(WTS_E_UNSUPPORTED, "opts.rho = %d: 2, 4 or 5 supported", o.rho);
   if (o.grid < 0 || o.reserved != 0) return fail(WTS_E_ARG, "opts.grid / opts.reserved");
+  if (!(o.band >= 0.0) || !std::isfinite(o.band)) return fail(WTS_E_ARG, "opts.band must be finite and >= 0");
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(WTS_E_ARG, "device %d of %d", device, ndev);
@@ -373,6 +374,10 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   p->rho = o.rho ? o.rho : 4;   // medoid sweeps: 2, 4 or 5 (4 when automatic)
   p->off.assign(offsets_host, offsets_host + n + 1);
   for (int k = 0; k < n; ++k) p->nmax = std::max(p->nmax, p->off[k + 1] - p->off[k]);
+  if (o.band > 0.0 && (L >= (int64_t(1) << 26) || p->nmax >= (int64_t(1) << 26))) {
+    delete p;
+    return fail(WTS_E_SHAPE, "a Sakoe-Chiba band needs L and every cycle length below 2^26");
+  }
 
   DeviceGuard g(device);
   auto cleanup_fail = [&](hipError_t e, const char* what) {
@@ -653,6 +658,7 @@ wts_status wts_softdtw_forward(const wts_plan* p, const double* bary, const void
   a.rows = at<double>(ckpt, l.rows);
   a.states = at<double>(ckpt, l.states);
   a.kscale = 1.0 / (gamma * 0.69314718055994530942);
+  a.band = p->opts.band;
   a.value = value;
   a.L = p->L;
   const int tk = timing_begin(p, WTS_OP_SOFT_FWD, st);
@@ -692,6 +698,7 @@ wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const voi
   a.rows = at<double>(ck, lc.rows);
   a.states = at<double>(ck, lc.states);
   a.kscale = 1.0 / (gamma * 0.69314718055994530942);
+  a.band = p->opts.band;
   a.push_up = at<double>(ws, l.push_up);
   a.push_dg = at<double>(ws, l.push_dg);
   a.gsum = at<double>(ws, l.gsum);

@@ -121,6 +121,7 @@ struct SoftArgs {
   double* hsum;          // [n][L] per-cycle row mass
   int64_t L;
   int relaxed_wait;      // 1: far more items than resident wavefronts; wait with long sleeps
+  double band;           // Sakoe-Chiba bandwidth as a fraction of the longer length (0: none)
 };
 
 __device__ __forceinline__ double inf_d() { return __builtin_huge_val(); }

@@ -76,9 +76,43 @@ __device__ __forceinline__ SoftMin softmin3(double dg, double up, double lf) {
   return o;
 }
 
+// Sakoe-Chiba band (the bandwidth of Table I, a fraction w of the longer
+// length): cell (i, j) of an M x N pair lies in the band iff
+//   |i (N-1) - j (M-1)| <= B,   B = R min(M-1, N-1),
+//   R = max(ceil(w max(M, N)), ceil(max(M-1, N-1) / min(M-1, N-1))),
+// a band of radius R around the diagonal from (0, 0) to (M-1, N-1) along
+// the longer side; the lower bound on R keeps a predecessor in the band for
+// every cell of the band but (0, 0).  Returns B, or +inf (every cell) when
+// w = 0 or a side has length 1.  The test is done in float64, exact for
+// M, N < 2^26 (checked at plan time).
+__device__ __forceinline__ double band_halfwidth(int M, int N, double w) {
+  if (!(w > 0.0) || M == 1 || N == 1) return __builtin_huge_val();
+  const int64_t am = M - 1, bn = N - 1;
+  const int64_t mn = am < bn ? am : bn, mx = am < bn ? bn : am;
+  int64_t R = (int64_t)__builtin_ceil(w * (double)(M > N ? M : N));
+  const int64_t Rmin = (mx + mn - 1) / mn;
+  if (R < Rmin) R = Rmin;
+  return (double)(R * mn);
+}
+
+// softmin3 for a cell that may lie outside the band: there every input may
+// be +inf, so the shift m is replaced by 0 to keep the arithmetic free of
+// inf - inf (the caller discards the result of such a cell).
+__device__ __forceinline__ SoftMin softmin3_band(double dg, double up, double lf, bool inb) {
+  double m = __builtin_fmin(__builtin_fmin(dg, up), lf);
+  m = inb ? m : 0.0;
+  SoftMin o;
+  o.ed = __builtin_amdgcn_exp2f((float)(m - dg));
+  o.eu = __builtin_amdgcn_exp2f((float)(m - up));
+  o.el = __builtin_amdgcn_exp2f((float)(m - lf));
+  o.s = (o.ed + o.eu) + o.el;
+  o.v = m - (double)__builtin_amdgcn_logf(o.s);
+  return o;
+}
+
 // --------------------------------------------------------------- forward
 
-template <typename TY, int D, int RHO>
+template <typename TY, int D, int RHO, bool BAND>
 __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
   constexpr int H = kWave * RHO;
   constexpr int kChunk = 64;
@@ -103,6 +137,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     const int M = pd.M, N = pd.N;
     const int i0 = s * H;
     const int ib = i0 + lane * RHO;
+    const double band_b = BAND ? band_halfwidth(M, N, a.band) : 0.0;
     const bool has_prev = s > 0;
     const bool has_next = s + 1 < pd.S;
     const int Tend = pd.WT * 16;
@@ -210,11 +245,20 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
 #pragma unroll
             for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
             double dg = dg0, up = upin;
+            // band coordinate of row ib at column j (exact in float64)
+            const double bd0 = (double)ib * (double)(N - 1) - (double)j * (double)(M - 1);
 #pragma unroll
             for (int r = 0; r < RHO; ++r) {
               const double lf = left[r];
-              const SoftMin sm = softmin3(dg, up, lf);
-              const double rv = sq_cost<D>(xr[r], y) * k + sm.v;
+              double rv;
+              if constexpr (BAND) {
+                const bool inb = __builtin_fabs(bd0 + (double)r * (double)(N - 1)) <= band_b;
+                const SoftMin sm = softmin3_band(dg, up, lf, inb);
+                rv = inb ? sq_cost<D>(xr[r], y) * k + sm.v : INF;
+              } else {
+                const SoftMin sm = softmin3(dg, up, lf);
+                rv = sq_cost<D>(xr[r], y) * k + sm.v;
+              }
               dg = lf;
               up = rv;
               left[r] = rv;
@@ -266,8 +310,10 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
 
 // -------------------------------------------------------------- backward
 
-template <typename TY, int D, int RHO>
-__global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
+// The band test needs a few more registers: the banded instance is held to
+// two resident waves per SIMD (the unbanded one fits them by itself).
+template <typename TY, int D, int RHO, bool BAND>
+__global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs a) {
   constexpr int H = kWave * RHO;
   __shared__ double ys[D][kRing];
   __shared__ double bin_fwd[kTile];        // lane 0's upper input for the replay
@@ -293,6 +339,7 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
     const int M = pd.M, N = pd.N;
     const int i0 = s * H;
     const int ib = i0 + lane * RHO;
+    const double band_b = BAND ? band_halfwidth(M, N, a.band) : 0.0;
     const bool has_above = s > 0;            // a strip above consumes our top-row pushes
     const bool has_below = s + 1 < pd.S;     // the strip below feeds our bottom row
     const int G = pd.WT;                     // 16-step tiles
@@ -434,17 +481,32 @@ __global__ __launch_bounds__(kWave) void soft_bwd_kernel(SoftArgs a) {
 #pragma unroll
           for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
           double dg = dgi, up = upin;
+          const double bd0 = (double)ib * (double)(N - 1) - (double)j * (double)(M - 1);
 #pragma unroll
           for (int r = 0; r < RHO; ++r) {
             const double lf = left[r];
-            const SoftMin sm = softmin3(dg, up, lf);
-            const double rv = sq_cost<D>(xr[r], y) * k + sm.v;
-            wd[u][r] = sm.ed;   // unnormalised; normalised in float64 below
-            wu[u][r] = sm.eu;
-            wl[u][r] = sm.el;
-            dg = lf;
-            up = rv;
-            left[r] = rv;
+            if constexpr (BAND) {
+              // outside the band: cost +inf and weights (1, 0, 0), so the cell
+              // receives and passes on exactly nothing
+              const bool inb = __builtin_fabs(bd0 + (double)r * (double)(N - 1)) <= band_b;
+              const SoftMin sm = softmin3_band(dg, up, lf, inb);
+              const double rv = inb ? sq_cost<D>(xr[r], y) * k + sm.v : INF;
+              wd[u][r] = inb ? sm.ed : 1.0f;
+              wu[u][r] = inb ? sm.eu : 0.0f;
+              wl[u][r] = inb ? sm.el : 0.0f;
+              dg = lf;
+              up = rv;
+              left[r] = rv;
+            } else {
+              const SoftMin sm = softmin3(dg, up, lf);
+              const double rv = sq_cost<D>(xr[r], y) * k + sm.v;
+              wd[u][r] = sm.ed;   // unnormalised; normalised in float64 below
+              wu[u][r] = sm.eu;
+              wl[u][r] = sm.el;
+              dg = lf;
+              up = rv;
+              left[r] = rv;
+            }
           }
           bot = left[RHO - 1];
         }
@@ -604,10 +666,18 @@ hipError_t launch_precond_step(double* bary, const double* grad, const double* m
 
 template <typename TY, int D>
 static hipError_t launch_soft_t(bool bwd, const SoftArgs& a, int grid, hipStream_t st) {
-  if (bwd)
-    hipLaunchKernelGGL((soft_bwd_kernel<TY, D, kSoftRho>), dim3(grid), dim3(kWave), 0, st, a);
-  else
-    hipLaunchKernelGGL((soft_fwd_kernel<TY, D, kSoftRho>), dim3(grid), dim3(kWave), 0, st, a);
+  const bool band = a.band > 0.0;
+  if (bwd) {
+    if (band)
+      hipLaunchKernelGGL((soft_bwd_kernel<TY, D, kSoftRho, true>), dim3(grid), dim3(kWave), 0, st, a);
+    else
+      hipLaunchKernelGGL((soft_bwd_kernel<TY, D, kSoftRho, false>), dim3(grid), dim3(kWave), 0, st, a);
+  } else {
+    if (band)
+      hipLaunchKernelGGL((soft_fwd_kernel<TY, D, kSoftRho, true>), dim3(grid), dim3(kWave), 0, st, a);
+    else
+      hipLaunchKernelGGL((soft_fwd_kernel<TY, D, kSoftRho, false>), dim3(grid), dim3(kWave), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -34,7 +34,7 @@ class WtsError(RuntimeError):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("cost", ctypes.c_int32), ("rho", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("band", ctypes.c_double)]
 
 
 def load():
@@ -100,10 +100,12 @@ def _stream():
 
 class Plan:
     """A plan binds the cycle lengths, the channel count, the storage dtype and
-    the barycenter length L (L = 0: a plan for the medoid only)."""
+    the barycenter length L (L = 0: a plan for the medoid only).  band > 0
+    restricts the Soft-DTW calls to a Sakoe-Chiba band of that fraction of
+    the longer length (Table I)."""
 
     def __init__(self, offsets, d: int, dtype: str, L: int, device: int = 0, cost: str = "sq",
-                 rho: int = 0, grid: int = 0):
+                 rho: int = 0, grid: int = 0, band: float = 0.0):
         lib = load()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         self.offsets = off
@@ -112,7 +114,8 @@ class Plan:
         self.dtype = dtype
         self.L = int(L)
         self.device = int(device)
-        opts = _Opts(COST_EUCLID if cost == "euclid" else COST_SQ, int(rho), int(grid), 0)
+        opts = _Opts(COST_EUCLID if cost == "euclid" else COST_SQ, int(rho), int(grid), 0,
+                     float(band))
         h = ctypes.c_void_p()
         _check(lib.wts_plan_create(ctypes.byref(h), self.device, self.n, self.d,
                                    F32 if dtype == "f32" else F64,

@@ -73,6 +73,9 @@ def test_plan_create_rejects_bad_shapes_before_any_gpu_call(lib):
     for rho in (1, 3, 6, 8):   # rows per lane: 2, 4 or 5 only
         assert _create(lib, opts=ctypes.byref(_Opts(0, rho, 0, 0)))[0] == WTS_E_UNSUPPORTED
     assert _create(lib, opts=ctypes.byref(_Opts(0, 4, -1, 0)))[0] == WTS_E_ARG
+    for band in (-0.5, float("nan"), float("inf")):   # Sakoe-Chiba bandwidth
+        assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 0, band)))[0] == WTS_E_ARG
+    assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 7)))[0] == WTS_E_ARG
 
 
 def test_null_plan_is_rejected(lib):

@@ -34,10 +34,10 @@ def check_vec(a, b, rtol=RTOL):
     assert np.linalg.norm(a - b) <= rtol * np.linalg.norm(b)
 
 
-def setup(wts, B, cycles, dtype=None):
+def setup(wts, B, cycles, dtype=None, band=0.0):
     import torch
     Y, off, dt = wts.pack_cycles(cycles, dtype=dtype)
-    plan = wts.Plan(off, B.shape[1], dt, B.shape[0])
+    plan = wts.Plan(off, B.shape[1], dt, B.shape[0], band=band)
     return plan, torch.from_numpy(np.ascontiguousarray(B, dtype=np.float64)).cuda(), Y
 
 
@@ -182,3 +182,55 @@ def test_lbfgs_barycenter_converges_on_the_oracle_objective(wts):
     # max-norm about 56-fold on this problem)
     assert np.abs(g1).max() <= 5e-2 * np.abs(g0).max()
     assert len(hist) <= 200 + 25
+
+
+
+BAND_SHAPES = [  # (L, lengths): one and several strips, L above and below N
+    (40, [40, 25, 90]),
+    (300, [260, 420, 7]),
+    (700, [500, 900]),
+]
+
+
+@pytest.mark.parametrize("w", [0.6, 0.2, 0.03])
+@pytest.mark.parametrize("L,lens", BAND_SHAPES)
+def test_soft_band_matches_oracle(wts, w, L, lens):
+    """Sakoe-Chiba band (Table I): values, gradient and row mass of the paths
+    inside the band, within 1e-4 of the oracle."""
+    import torch
+    r = rng(int(1000 * w) + L)
+    B = r.standard_normal((L, 3))
+    cyc = [r.standard_normal((N, 3)) for N in lens]
+    wv = r.uniform(0.5, 1.5, len(lens))
+    for gamma, dtype in ((0.1, "f32"), (1.0, "f64")):
+        say("soft band w=%g L=%d lens=%s gamma=%g %s" % (w, L, lens, gamma, dtype))
+        cs = [np.asarray(c, dtype=np.float32 if dtype == "f32" else np.float64) for c in cyc]
+        plan, Bt, Y = setup(wts, B, cs, dtype=dtype, band=w)
+        val, ck = wts.softdtw_forward(plan, Bt, Y, gamma)
+        g, h = wts.softdtw_backward(plan, Bt, Y, gamma, ck, torch.from_numpy(wv).cuda(),
+                                    with_mass=True)
+        torch.cuda.synchronize()
+        assert wts.device_status(plan, wts.OP_SOFT_BWD) == 0
+        c64 = [np.asarray(c, dtype=np.float64) for c in cs]
+        ov, og, oh = oracle.softdtw_batch(B, c64, gamma, wv, band=w)
+        check_vec(val.cpu().numpy(), ov)
+        check_vec(g.cpu().numpy(), og)
+        check_vec(h.cpu().numpy(), oh)
+
+
+def test_soft_wide_band_is_bitwise_unbanded(wts):
+    """A band wider than every pair keeps every cell: the banded kernels then
+    compute exactly the unbanded bits."""
+    import torch
+    r = rng(71)
+    B = r.standard_normal((300, 2))
+    cyc = [r.standard_normal((N, 2)).astype(np.float32) for N in (280, 333)]
+    outs = []
+    for band in (0.0, 10.0):
+        plan, Bt, Y = setup(wts, B, cyc, band=band)
+        v, ck = wts.softdtw_forward(plan, Bt, Y, 0.5)
+        g, h = wts.softdtw_backward(plan, Bt, Y, 0.5, ck, with_mass=True)
+        torch.cuda.synchronize()
+        outs.append((v.cpu().numpy(), g.cpu().numpy(), h.cpu().numpy()))
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
