@@ -117,14 +117,15 @@ def _config4():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("gamma", [0.1, 1.0])
-def test_config4_full_soft_sampled(wts, gamma):
-    """128 x 6 ch, 18000..22000, L = 20000, gamma in {0.1, 1}: values of
-    sampled cycles and the gradient weighted onto them, within 1e-4."""
+@pytest.mark.parametrize("gamma,band", [(0.1, 0.0), (1.0, 0.0), (0.1, 0.6)])
+def test_config4_full_soft_sampled(wts, gamma, band):
+    """128 x 6 ch, 18000..22000, L = 20000, gamma in {0.1, 1}, and the Table I
+    band of 0.6: values of sampled cycles and the gradient weighted onto
+    them, within 1e-4."""
     import torch
     w = _config4()
     Y, off, dt = wts.pack_cycles(w.cycles)
-    plan = wts.Plan(off, 6, dt, w.L)
+    plan = wts.Plan(off, 6, dt, w.L, band=band)
     cyc = f64(w.cycles)
     pick = [5, 77]
     say("c4: Euclidean-mean init")
@@ -140,7 +141,7 @@ def test_config4_full_soft_sampled(wts, gamma):
     assert wts.device_status(plan, wts.OP_SOFT_BWD) == 0
     del ck
     say("c4: oracle on cycles", pick)
-    ov, og, oh = oracle.softdtw_batch(Bo, [cyc[q] for q in pick], gamma, wv[pick])
+    ov, og, oh = oracle.softdtw_batch(Bo, [cyc[q] for q in pick], gamma, wv[pick], band=band)
     check_vec(val.cpu().numpy()[pick], ov)
     check_vec(g.cpu().numpy(), og)
     check_vec(h.cpu().numpy(), oh)
