@@ -83,9 +83,11 @@ def traffic_from_profiles(kernel: str, name: str = None):
         return None
     if not rec or rec.get("source_hash") != kernel_source_hash():
         return None
-    if name is not None and rec.get("kernel", "").replace("void ", "") != name:
-        return None
-    return rec.get("bytes_per_launch")
+    inst = rec.get("instances", {})
+    if name is None:
+        name = rec.get("kernel", "").replace("void ", "")
+    hit = inst.get("void " + name) or inst.get(name)
+    return None if hit is None else hit.get("bytes_per_launch")
 
 
 KERNELS = {   # sweep -> rocprofv3 kernel name, by rows per lane (rho) of the plan
@@ -135,17 +137,22 @@ def ingest_traffic(root: str):
     out = {"_calibration": {"copy_bytes": int(gib), "fetch_kib": f_cal, "write_kib": w_cal,
                             "fetch_scale": f_scale, "write_scale": w_scale}}
     for key in KERNELS:
-        # the phase's own kernel instance (the sweep-shape tuner that runs
-        # first launches the other instances too)
-        name = used.get(key)
-        if name is None:
-            continue
-        fk = [avg[k] for k in avg if k[0].split("(wts::")[0] == name and k[1] == "FETCH_SIZE"]
-        wk = [avg[k] for k in avg if k[0].split("(wts::")[0] == name and k[1] == "WRITE_SIZE"]
-        if fk and wk:
-            out[key] = {"kernel": name, "source_hash": kernel_source_hash(),
-                        "fetch_bytes": fk[0] * f_scale, "write_bytes": wk[0] * w_scale,
-                        "bytes_per_launch": fk[0] * f_scale + wk[0] * w_scale}
+        # every instance of this sweep that ran a complete launch in the
+        # passes (the sweep-shape tuner at the start of each phase launches
+        # all candidates); `kernel` is the one the phase itself chose
+        pre, post = KERNELS[key].split("{rho}")
+        names = sorted({k[0].split("(wts::")[0] for k in avg
+                        if k[0].startswith(pre) and k[0].split("(wts::")[0].endswith(post)})
+        inst = {}
+        for name in names:
+            fk = [avg[k] for k in avg if k[0].split("(wts::")[0] == name and k[1] == "FETCH_SIZE"]
+            wk = [avg[k] for k in avg if k[0].split("(wts::")[0] == name and k[1] == "WRITE_SIZE"]
+            if fk and wk:
+                inst[name] = {"fetch_bytes": fk[0] * f_scale, "write_bytes": wk[0] * w_scale,
+                              "bytes_per_launch": fk[0] * f_scale + wk[0] * w_scale}
+        if inst:
+            out[key] = {"kernel": used.get(key, names[0]), "source_hash": kernel_source_hash(),
+                        "instances": inst}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
