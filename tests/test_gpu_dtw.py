@@ -3,8 +3,8 @@ init) against the FP64 oracle, through the C ABI.
 
 The decision arithmetic on both sides is float64 with the same operation
 order, so distances, path lengths, paths, alignment counts, DBA barycenters,
-scores and medoid matrices must match BIT FOR BIT (spec bar: paths and
-integer counts exact; values within 1e-4 relative -- we hold them to 0 ulp).
+scores and medoid matrices must match BIT FOR BIT (paths and integer counts
+must be exact and values within 1e-4 relative; these are held to 0 ulp).
 """
 
 import sys

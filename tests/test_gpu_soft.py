@@ -3,7 +3,7 @@
 Soft-DTW uses float32 base-2 exponentials/logarithms on float64 differences,
 so it is not bit-exact: scalars must satisfy |a - b| <= 1e-4 |b| and vectors
 both |a_k - b_k| <= 1e-4 max(|b_k|, 1e-2 ||b||_inf) per element and
-||a - b||_2 <= 1e-4 ||b||_2 (the benchmark spec's 1e-4 relative bar).
+||a - b||_2 <= 1e-4 ||b||_2 (a 1e-4 relative bar).
 """
 
 import sys
