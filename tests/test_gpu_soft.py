@@ -185,7 +185,9 @@ def test_lbfgs_barycenter_converges_on_the_oracle_objective(wts):
 
 
 
-BAND_SHAPES = [  # (L, lengths): one and several strips, L above and below N
+BAND_SHAPES = [  # (L, lengths): one and several strips, L above and below N, one-row /
+    (1, [1, 9]),    # one-column pairs (the band keeps every cell)
+    (37, [1, 64]),
     (40, [40, 25, 90]),
     (300, [260, 420, 7]),
     (700, [500, 900]),
