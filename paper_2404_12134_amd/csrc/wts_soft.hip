@@ -95,6 +95,25 @@ __device__ __forceinline__ double band_halfwidth(int M, int N, double w) {
   return (double)(R * mn);
 }
 
+// Columns of the band over rows i_first .. i_last (the band's left edge is
+// non-decreasing in i, so the range runs from row i_first's left edge to row
+// i_last's right edge), in exact integer arithmetic: a 16-step group whose
+// cells all lie outside it can skip its cell arithmetic.
+__device__ __forceinline__ void band_strip_cols(int M, int N, double w, int i_first, int i_last,
+                                                int* jlo, int* jhi) {
+  *jlo = 0;
+  *jhi = N - 1;
+  if (!(w > 0.0) || M == 1 || N == 1) return;
+  const int64_t am = M - 1, bn = N - 1;
+  const int64_t B = (int64_t)band_halfwidth(M, N, w);
+  // left edge of row i: ceil((i bn - B) / am); right edge: floor((i bn + B) / am)
+  auto floor_div = [](int64_t x, int64_t y) { return x / y - ((x % y != 0) && (x < 0)); };
+  const int64_t lo = -floor_div(B - (int64_t)i_first * bn, am);
+  const int64_t hi = floor_div((int64_t)i_last * bn + B, am);
+  if (lo > 0) *jlo = (int)(lo < bn ? lo : bn);
+  if (hi < bn) *jhi = (int)(hi > 0 ? hi : 0);
+}
+
 // softmin3 for a cell that may lie outside the band: there every input may
 // be +inf, so the shift m is replaced by 0 to keep the arithmetic free of
 // inf - inf (the caller discards the result of such a cell).
@@ -138,6 +157,8 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     const int i0 = s * H;
     const int ib = i0 + lane * RHO;
     const double band_b = BAND ? band_halfwidth(M, N, a.band) : 0.0;
+    int band_jlo = 0, band_jhi = N - 1;
+    if (BAND) band_strip_cols(M, N, a.band, i0, min(i0 + H, M) - 1, &band_jlo, &band_jhi);
     const bool has_prev = s > 0;
     const bool has_next = s + 1 < pd.S;
     const int Tend = pd.WT * 16;
@@ -268,9 +289,32 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
           }
         }
       };
+      // a group whose columns (tg - 63 .. tg + 15 over the lanes) all lie
+      // outside the strip's band keeps only its bookkeeping: checkpoint,
+      // +inf state and bottom row, and lane 0's diagonal input of the next step
+      auto skip16 = [&](int tb) {
+        const int tg = t0 + tb;
+        double* p = st + (int64_t)(tg >> 4) * (RHO + 1) * kWave + lane;
+#pragma unroll
+        for (int r = 0; r < RHO; ++r) p[r * kWave] = left[r];
+        p[RHO * kWave] = upprev;
+        // lanes with cells in the grid during the group end it at +inf; a lane
+        // already past column N-1 keeps its values (as the sweep would)
+        if (tg + 15 - lane >= 0 && tg - lane <= N - 1) {
+#pragma unroll
+          for (int r = 0; r < RHO; ++r) left[r] = INF;
+          bot = INF;
+        }
+        upprev = (lane == 0 && has_prev) ? binr[tb + 15] : INF;
+        if (has_next && lane < 16) {
+          const int j = tg - (kWave - 1) + lane;
+          if (j >= 0 && j < N) bor[j & (kRing - 1)] = INF;
+        }
+      };
       for (int tb = 0; tb < tcnt; tb += 16) {
         const int tg = t0 + tb;
-        if (tg >= kWave - 1 && tg + 16 <= N) group16(std::true_type{}, tb);
+        if (BAND && (tg + 15 < band_jlo || tg - (kWave - 1) > band_jhi)) skip16(tb);
+        else if (tg >= kWave - 1 && tg + 16 <= N) group16(std::true_type{}, tb);
         else group16(std::false_type{}, tb);
       }
       __syncthreads();
