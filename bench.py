@@ -366,7 +366,7 @@ def dba_large_section(wts, dev, iters: int = 10, speedup: bool = True):
 
 
 def irregular_section(wts, dev, dba_iters: int = 10, soft_steps: int = 10, gamma: float = 0.1,
-                      max_ckpt_gib: float = 48.0, speedup: bool = True):
+                      max_ckpt_gib: float = 96.0, speedup: bool = True):
     """The 256-cycle workload (6 channels, lengths 40000..50000 with 1 % of the
     samples dropped in gaps, L = max N): nearest-length init, `dba_iters` DBA
     iterations replayed from a hipGraph, then `soft_steps` preconditioned
