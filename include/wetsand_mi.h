@@ -80,7 +80,8 @@ enum {
   WTS_OP_SOFT_FWD = 4,     /* checkpoint buffer of the Soft-DTW pair */
   WTS_OP_SOFT_BWD = 5,     /* workspace of wts_softdtw_backward      */
   WTS_OP_MEDOID = 6,       /* wts_medoid                            */
-  WTS_OP_SUBDTW = 7        /* wts_subdtw                            */
+  WTS_OP_SUBDTW = 7,       /* wts_subdtw                            */
+  WTS_OP_SOFT_GRAD_C = 8   /* wts_softdtw_grad_cycles               */
 };
 
 enum { WTS_INIT_EUCLID_MEAN = 0, WTS_INIT_NEAREST = 1, WTS_INIT_COPY = 2 };
@@ -206,6 +207,19 @@ wts_status wts_softdtw_backward(const wts_plan* plan, const double* bary, const 
                                 double gamma, const void* ckpt, size_t ckpt_bytes,
                                 const double* grad_value, double* grad_bary, double* row_mass,
                                 void* ws, size_t ws_bytes, void* stream);
+
+/* Eq. 6 for the other argument: the gradient of sum_k w_k Soft-DTW^gamma(B, C_k)
+ * with respect to the cycle values,
+ *   d/dc_kj = w_k sum_i e_ij 2 (c_kj - b_i),
+ * computed as the row gradient of Soft-DTW(C_k, B) (the measure is symmetric in
+ * its two series, and so is the plan's band): one forward and one backward
+ * sweep with the cycles on the rows.  cycles64: the cycle values as float64
+ * [sum N][d]; grad_value [n] float64 or NULL (all 1); grad_cycles [sum N][d]
+ * float64, overwritten.  ws: workspace of wts_workspace_bytes(WTS_OP_SOFT_GRAD_C)
+ * bytes (it holds this call's own checkpoints). */
+wts_status wts_softdtw_grad_cycles(const wts_plan* plan, const double* bary, const double* cycles64,
+                                   double gamma, const double* grad_value, double* grad_cycles,
+                                   void* ws, size_t ws_bytes, void* stream);
 
 /* One step of the gradient descent that approximates the Soft-DTW barycenter
  * of Eq. 7 (Sec. III-C computes it by gradient descent):

@@ -193,6 +193,17 @@ def softdtw_grad(X, Y, gamma, with_E=False, band=0.0):
     return float(v[0]), g, h, E
 
 
+def softdtw_grad_y(X, Y, gamma, band=0.0):
+    """Eq. 6 taken with respect to the second series: the cost of cell (i, j)
+    depends on y_j through ||x_i - y_j||^2, whose derivative is 2 (y_j - x_i),
+    so d Soft-DTW / d y_j = sum_i e_ij 2 (y_j - x_i).  E comes from the
+    oracle's own backward recursion; returns (value, grad [N][d])."""
+    X, Y = _series(X), _series(Y)
+    v, _, _, E = softdtw_grad(X, Y, gamma, with_E=True, band=band)
+    colmass = E.sum(axis=0)
+    return v, 2.0 * (colmass[:, None] * Y - E.T @ X)
+
+
 def softdtw_batch(X, cycles, gamma, weights=None, grad=True, band=0.0):
     """Values [n] and, if grad, (sum_i w_i dSDTW_i/dX [M][d], sum_i w_i rowmass_i [M])."""
     X = _series(X)

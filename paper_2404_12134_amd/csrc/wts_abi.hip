@@ -165,6 +165,7 @@ struct wts_plan {
   int64_t* d_path_base = nullptr;
   int2* d_med_ab = nullptr;
   PairSet bary, med, soft;
+  PairSet softT;   // Soft-DTW with the roles swapped: the cycles on the rows, B on the columns
   int64_t nmax = 0;
   // optional sweep timing: pool of (start, stop) event pairs, one per sweep launch
   std::vector<hipEvent_t> ev;
@@ -179,7 +180,22 @@ Layout layout(const wts_plan* p, int op) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + std::max<size_t>(bytes, 1)); return at; };
   const PairSet& ps = op == WTS_OP_MEDOID ? p->med
-                      : (op == WTS_OP_SOFT_FWD || op == WTS_OP_SOFT_BWD) ? p->soft : p->bary;
+                      : (op == WTS_OP_SOFT_FWD || op == WTS_OP_SOFT_BWD) ? p->soft
+                      : op == WTS_OP_SOFT_GRAD_C ? p->softT : p->bary;
+  if (op == WTS_OP_SOFT_GRAD_C) {   // the transposed forward and backward in one buffer
+    const int64_t rows = p->off[p->n];
+    l.queue = take(2 * sizeof(int));
+    l.progress = take(sizeof(int) * (size_t)ps.n_flags);
+    l.rows = take(sizeof(double) * (size_t)ps.aux_strip_elems);
+    l.states = take(sizeof(double) * (size_t)ps.state_elems);
+    l.push_up = take(sizeof(double) * (size_t)ps.bnd_elems);
+    l.push_dg = take(sizeof(double) * (size_t)ps.bnd_elems);
+    l.gsum = take(sizeof(double) * (size_t)rows * (size_t)p->d);
+    l.hsum = take(sizeof(double) * (size_t)rows);
+    l.out_dist = take(sizeof(double) * (size_t)p->n);
+    l.total = o;
+    return l;
+  }
   if (op == WTS_OP_SOFT_FWD || op == WTS_OP_SOFT_BWD) {
     l.queue = take(2 * sizeof(int));
     l.progress = take(sizeof(int) * (size_t)ps.n_flags);
@@ -394,6 +410,10 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
       jobs.push_back(Job{0, p->off[k], (int32_t)L, (int32_t)(p->off[k + 1] - p->off[k]), k});
     build_set(p->bary, jobs, o.rho ? o.rho : bary_rho(L, n, p->cus));
     build_set(p->soft, jobs, wts::kSoftRho);
+    std::vector<Job> tjobs;
+    for (int k = 0; k < n; ++k)
+      tjobs.push_back(Job{p->off[k], 0, (int32_t)(p->off[k + 1] - p->off[k]), (int32_t)L, k});
+    build_set(p->softT, tjobs, wts::kSoftRho);
     std::vector<int64_t> base(n);
     for (int k = 0; k < n; ++k) base[k] = (int64_t)k * (L - 1) + p->off[k];
     hipError_t e;
@@ -419,7 +439,7 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
         return cleanup_fail(e, "hipMemcpy");
     }
   }
-  for (PairSet* ps : {&p->bary, &p->med, &p->soft}) {
+  for (PairSet* ps : {&p->bary, &p->med, &p->soft, &p->softT}) {
     if (ps->pairs.empty()) continue;
     hipError_t e;
     if ((e = hipMalloc(&ps->d_pairs, sizeof(PairDesc) * ps->pairs.size())) != hipSuccess) return cleanup_fail(e, "hipMalloc");
@@ -505,7 +525,7 @@ void wts_plan_destroy(wts_plan* p) {
   if (!p) return;
   DeviceGuard g(p->device);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
-  for (PairSet* ps : {&p->bary, &p->med, &p->soft}) {
+  for (PairSet* ps : {&p->bary, &p->med, &p->soft, &p->softT}) {
     if (ps->d_pairs) (void)hipFree(ps->d_pairs);
     if (ps->d_items) (void)hipFree(ps->d_items);
     if (ps->d_items_rev) (void)hipFree(ps->d_items_rev);
@@ -527,6 +547,7 @@ size_t wts_workspace_bytes(const wts_plan* p, int op) {
     case WTS_OP_SOFT_FWD:
     case WTS_OP_SOFT_BWD:
     case WTS_OP_SUBDTW:
+    case WTS_OP_SOFT_GRAD_C:
       return p->L > 0 ? layout(p, op).total : 0;
     case WTS_OP_MEDOID:
       return p->L == 0 ? layout(p, op).total : 0;
@@ -709,6 +730,51 @@ wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const voi
   timing_end(p, tk, st);
   HIP_TRY(wts::launch_soft_reduce(a.gsum, a.hsum, grad_value, p->n, p->L, p->d, grad_bary,
                                   row_mass, st));
+  return WTS_OK;
+}
+
+wts_status wts_softdtw_grad_cycles(const wts_plan* p, const double* bary, const double* cycles64,
+                                   double gamma, const double* grad_value, double* grad_cycles,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  wts_status rc = check_bary_plan(p);
+  if (rc != WTS_OK) return rc;
+  if (!bary || !cycles64 || !grad_cycles) return fail(WTS_E_ARG, "null bary/cycles64/grad_cycles");
+  if (!(gamma > 0) || !(gamma < INFINITY)) return fail(WTS_E_ARG, "gamma must be finite and > 0");
+  if ((rc = check_ws(p, WTS_OP_SOFT_GRAD_C, ws, ws_bytes)) != WTS_OK) return rc;
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout l = layout(p, WTS_OP_SOFT_GRAD_C);
+  const PairSet& ps = p->softT;
+  wts::SoftArgs a{};
+  a.pairs = ps.d_pairs;
+  a.n_items = ps.n_items;
+  a.queue = at<int>(ws, l.queue);
+  a.status = at<int>(ws, l.queue) + 1;
+  a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
+  a.progress = at<int>(ws, l.progress);
+  a.x = cycles64;          // rows: every cycle, at its own offset (PairDesc.x_off)
+  a.y = bary;              // columns: the barycenter, shared by all pairs
+  a.rows = at<double>(ws, l.rows);
+  a.states = at<double>(ws, l.states);
+  a.kscale = 1.0 / (gamma * 0.69314718055994530942);
+  a.band = p->opts.band;   // the band is symmetric in the two series
+  a.value = at<double>(ws, l.out_dist);
+  a.push_up = at<double>(ws, l.push_up);
+  a.push_dg = at<double>(ws, l.push_dg);
+  a.gsum = at<double>(ws, l.gsum);
+  a.hsum = at<double>(ws, l.hsum);
+  a.L = p->L;
+  a.rows_packed = 1;
+  HIP_TRY(wts::launch_zero(a.queue, 2, st));
+  HIP_TRY(wts::launch_zero(a.progress, ps.n_flags, st));
+  a.items = ps.d_sweep_items;
+  HIP_TRY(wts::launch_soft(p->d, WTS_F64, false, a, default_grid(p, ps), st));
+  HIP_TRY(wts::launch_zero(a.queue, 2, st));
+  HIP_TRY(wts::launch_zero(a.progress, ps.n_flags, st));
+  a.items = ps.d_items_rev;
+  HIP_TRY(wts::launch_soft(p->d, WTS_F64, true, a, default_grid(p, ps), st));
+  HIP_TRY(wts::launch_soft_rows_scale(a.gsum, p->d_off, p->n, p->off[p->n], p->d, grad_value,
+                                      grad_cycles, st));
   return WTS_OK;
 }
 

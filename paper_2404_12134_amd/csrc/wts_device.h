@@ -109,19 +109,20 @@ struct SoftArgs {
   int* queue;
   int* status;
   int* progress;
-  const double* x;       // barycenter [L][d]
-  const void* y;         // cycle values
+  const double* x;       // row series: the barycenter [L][d], or packed float64 cycles (x_off)
+  const void* y;         // column series: cycle values, or the barycenter
   double* rows;          // bottom row of every strip, scaled units (S * N per pair)
   double* states;        // sweep state every 16 steps (RHO + 1 values per lane)
   double kscale;         // log2(e) / gamma
   double* value;         // [n] Soft-DTW values (forward)
   double* push_up;       // rolling top-row pushes between strips (backward)
   double* push_dg;
-  double* gsum;          // [n][L][d] per-cycle gradient rows
-  double* hsum;          // [n][L] per-cycle row mass
+  double* gsum;          // per-pair gradient rows ([n][L][d], or packed [sum M][d])
+  double* hsum;          // per-pair row mass ([n][L], or packed [sum M])
   int64_t L;
   int relaxed_wait;      // 1: far more items than resident wavefronts; wait with long sleeps
   double band;           // Sakoe-Chiba bandwidth as a fraction of the longer length (0: none)
+  int rows_packed;       // 0: gsum/hsum rows at out * L + i; 1: at x_off + i (X rows packed)
 };
 
 __device__ __forceinline__ double inf_d() { return __builtin_huge_val(); }

@@ -42,6 +42,8 @@ hipError_t launch_sub_out(const int* start, const int* end, int n, int64_t* a_st
 hipError_t launch_medoid(const double* pair_dist, const int2* pair_ab, int n_pairs, int n,
                          double* Dm, double* totals, int32_t* medoid, hipStream_t st);
 hipError_t launch_soft(int d, int ydtype, bool bwd, const SoftArgs& a, int grid, hipStream_t st);
+hipError_t launch_soft_rows_scale(const double* g, const int64_t* off, int n, int64_t rows, int d,
+                                  const double* w, double* out, hipStream_t st);
 hipError_t launch_soft_reduce(const double* gsum, const double* hsum, const double* w, int n,
                               int64_t L, int d, double* grad, double* mass, hipStream_t st);
 hipError_t launch_precond_step(double* bary, const double* grad, const double* mass, int64_t L,

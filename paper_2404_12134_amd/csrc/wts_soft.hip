@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     for (int r = 0; r < RHO; ++r)
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        xr[r][c] = (ib + r < M) ? a.x[(int64_t)(ib + r) * D + c] : 0.0;
+        xr[r][c] = (ib + r < M) ? a.x[(pd.x_off + ib + r) * D + c] : 0.0;
     double left[RHO];
 #pragma unroll
     for (int r = 0; r < RHO; ++r) left[r] = INF;
@@ -379,6 +379,8 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
     if (item >= a.n_items) break;
     const int2 it = a.items[item];
     const PairDesc pd = uniform(a.pairs[uni(it.x)]);
+    // first gradient row of this pair (per-cycle blocks of L rows, or the packed X rows)
+    const int64_t grow = uni(a.rows_packed ? pd.x_off : (int64_t)pd.out * a.L);
     const int s = uni(it.y);
     const int M = pd.M, N = pd.N;
     const int i0 = s * H;
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
     for (int r = 0; r < RHO; ++r)
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        xr[r][c] = (ib + r < M) ? a.x[(int64_t)(ib + r) * D + c] : 0.0;
+        xr[r][c] = (ib + r < M) ? a.x[(pd.x_off + ib + r) * D + c] : 0.0;
 
     double acc_e[RHO], acc_ey[RHO][D];
     double pl[RHO], pdg[RHO];                 // pending left / diagonal pushes into each row
@@ -644,7 +646,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
     for (int r = 0; r < RHO; ++r) {
       const int i = ib + r;
       if (i < M) {
-        const int64_t o = (int64_t)pd.out * a.L + i;
+        const int64_t o = grow + i;
 #pragma unroll
         for (int c = 0; c < D; ++c)
           a.gsum[o * D + c] = 2.0 * (xr[r][c] * acc_e[r] - acc_ey[r][c]);
@@ -671,6 +673,24 @@ __global__ void soft_reduce_kernel(const double* __restrict__ gsum, const double
     for (int p = 0; p < n; ++p) h = h + (w ? w[p] : 1.0) * hsum[(int64_t)p * L + l];
     mass[l] = h;
   }
+}
+
+// Rows of a packed [sum N][d] gradient scaled by their cycle's weight:
+// out[row] = w[k] * g[row] for the cycle k holding the row (offsets off[n+1]).
+__global__ void soft_rows_scale_kernel(const double* __restrict__ g, const int64_t* __restrict__ off,
+                                       int n, int d, const double* __restrict__ w,
+                                       double* __restrict__ out) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t rows = off[n];
+  if (idx >= rows * d) return;
+  const int64_t row = idx / d;
+  int lo = 0, hi = n - 1;   // the cycle k with off[k] <= row < off[k + 1]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= row) lo = mid;
+    else hi = mid - 1;
+  }
+  out[idx] = w ? w[lo] * g[idx] : g[idx];
 }
 
 // One preconditioned gradient step on the barycenter:
@@ -730,6 +750,15 @@ hipError_t launch_soft(int d, int ydtype, bool bwd, const SoftArgs& a, int grid,
                               : launch_soft_t<double, D>(bwd, a, grid, st))
   WTS_SOFT_D_SWITCH(d, CALLS)
 #undef CALLS
+}
+
+hipError_t launch_soft_rows_scale(const double* g, const int64_t* off, int n, int64_t rows, int d,
+                                  const double* w, double* out, hipStream_t st) {
+  const int64_t tot = rows * d;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(soft_rows_scale_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     g, off, n, d, w, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_soft_reduce(const double* gsum, const double* hsum, const double* w, int n,

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libwetsand_mi.so")
 
 F32, F64 = 0, 1
 COST_SQ, COST_EUCLID = 0, 1
-OP_ALIGN, OP_ALIGN_PATHS, OP_DBA, OP_SCORE, OP_SOFT_FWD, OP_SOFT_BWD, OP_MEDOID, OP_SUBDTW = range(8)
+(OP_ALIGN, OP_ALIGN_PATHS, OP_DBA, OP_SCORE, OP_SOFT_FWD, OP_SOFT_BWD, OP_MEDOID, OP_SUBDTW,
+ OP_SOFT_GRAD_C) = range(9)
 INIT_EUCLID_MEAN, INIT_NEAREST, INIT_COPY = 0, 1, 2
 
 _lib = None
@@ -63,6 +64,7 @@ def load():
         "wts_plan_sweep_ms": [P, ctypes.c_int, P, P],
         "wts_plan_rho": [P, ctypes.c_int],
         "wts_subdtw": [P, P, P, P, P, P, P, SZ, P],
+        "wts_softdtw_grad_cycles": [P, P, P, D, P, P, P, SZ, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -82,7 +84,8 @@ def exported_symbols():
     return ["wts_plan_create", "wts_plan_destroy", "wts_workspace_bytes", "wts_last_error",
             "wts_dtw_align", "wts_dba_iterate", "wts_anomaly_score", "wts_softdtw_forward",
             "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step",
-            "wts_plan_timing", "wts_plan_sweep_ms", "wts_plan_rho", "wts_subdtw"]
+            "wts_plan_timing", "wts_plan_sweep_ms", "wts_plan_rho", "wts_subdtw",
+            "wts_softdtw_grad_cycles"]
 
 
 def _check(rc: int):
@@ -313,27 +316,49 @@ def softdtw_backward(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, gamma
     return (grad, mass) if with_mass else grad
 
 
+def softdtw_grad_cycles(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, gamma: float,
+                        grad_value: Optional[torch.Tensor] = None):
+    """Eq. 6 for the cycles: grad [sum N][d] f64, row j of cycle k holding
+    grad_value_k dSoft-DTW^gamma(B, C_k)/dc_kj (the sweeps run with the
+    cycles on the rows; float32 cycles are widened to float64 first)."""
+    c64 = cycles.to(torch.float64).contiguous()
+    grad = torch.empty_like(c64)
+    ws = plan.workspace(OP_SOFT_GRAD_C)
+    gv = None if grad_value is None else grad_value.to(torch.float64).contiguous()
+    _check(load().wts_softdtw_grad_cycles(plan.handle, _ptr(bary), _ptr(c64), float(gamma),
+                                          _ptr(gv), _ptr(grad), _ptr(ws), ws.numel(), _stream()))
+    return grad
+
+
 class SoftDTW(torch.autograd.Function):
     """values[k] = Soft-DTW^gamma(B, C_k) with the hand-written E-matrix backward.
 
     Usage: SoftDTW.apply(bary, plan, cycles, gamma) with bary a float64 [L][d]
-    tensor; the checkpoints of the forward are kept for the backward."""
+    tensor and cycles the packed [sum N][d] buffer of the plan; the
+    checkpoints of the forward are kept for the backward.  Gradients flow to
+    the barycenter and, when it requires them, to the cycle buffer."""
 
     @staticmethod
     def forward(ctx, bary, plan, cycles, gamma):
         bary_c = bary.detach().contiguous()
-        value, ckpt = softdtw_forward(plan, bary_c, cycles, gamma)
-        ctx.plan, ctx.cycles, ctx.gamma, ctx.ckpt = plan, cycles, gamma, ckpt
+        cyc = cycles.detach()
+        value, ckpt = softdtw_forward(plan, bary_c, cyc, gamma)
+        ctx.plan, ctx.cycles, ctx.gamma, ctx.ckpt = plan, cyc, gamma, ckpt
         ctx.save_for_backward(bary_c)
         return value
 
     @staticmethod
     def backward(ctx, grad_value):
         (bary_c,) = ctx.saved_tensors
-        grad = softdtw_backward(ctx.plan, bary_c, ctx.cycles, ctx.gamma, ctx.ckpt,
-                                grad_value.contiguous())
+        gv = grad_value.contiguous()
+        grad_b = grad_c = None
+        if ctx.needs_input_grad[0]:
+            grad_b = softdtw_backward(ctx.plan, bary_c, ctx.cycles, ctx.gamma, ctx.ckpt, gv)
         ctx.ckpt = None
-        return grad, None, None, None
+        if ctx.needs_input_grad[2]:
+            grad_c = softdtw_grad_cycles(ctx.plan, bary_c, ctx.cycles, ctx.gamma, gv)
+            grad_c = grad_c.to(ctx.cycles.dtype)
+        return grad_b, None, grad_c, None
 
 
 def precond_step(bary: torch.Tensor, grad: torch.Tensor, row_mass: torch.Tensor, eta: float):

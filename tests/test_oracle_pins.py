@@ -324,6 +324,40 @@ def test_gradient_finite_differences(gamma):
     np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-6 * np.abs(g).max())
 
 
+@pytest.mark.parametrize("gamma,band", [(0.1, 0.0), (1.0, 0.0), (0.7, 0.3)])
+def test_gradient_wrt_y_finite_differences(gamma, band):
+    """Eq. 6 for the second series, pinned to central differences of the value."""
+    r = rng(19)
+    X, Y = r.standard_normal((11, 2)), r.standard_normal((16, 2))
+    v, gy = oracle.softdtw_grad_y(X, Y, gamma, band=band)
+    assert v == oracle.softdtw(X, Y, gamma, band=band)
+    h = 1e-6
+    fd = np.zeros_like(Y)
+    for j in range(Y.shape[0]):
+        for c in range(Y.shape[1]):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[j, c] += h
+            Ym[j, c] -= h
+            fd[j, c] = (oracle.softdtw(X, Yp, gamma, band=band)
+                        - oracle.softdtw(X, Ym, gamma, band=band)) / (2 * h)
+    np.testing.assert_allclose(gy, fd, rtol=1e-6, atol=1e-6 * np.abs(gy).max())
+
+
+def test_gradient_wrt_y_symmetry_and_translation():
+    """Soft-DTW(X, Y) = Soft-DTW(Y, X), so the gradient for Y is the gradient
+    for the first argument of the swapped pair; and shifting both series by
+    one vector leaves the value unchanged, so the two gradients sum to zero."""
+    r = rng(20)
+    X, Y = r.standard_normal((13, 3)), r.standard_normal((9, 3))
+    for band in (0.0, 0.4):
+        v, gy = oracle.softdtw_grad_y(X, Y, 0.5, band=band)
+        vs, gx_swapped, _, _ = oracle.softdtw_grad(Y, X, 0.5, band=band)
+        assert abs(v - vs) <= 1e-12 * abs(v)
+        np.testing.assert_allclose(gy, gx_swapped, rtol=1e-10, atol=1e-12)
+        _, gx, _, _ = oracle.softdtw_grad(X, Y, 0.5, band=band)
+        np.testing.assert_allclose(gx.sum(axis=0) + gy.sum(axis=0), 0.0, atol=1e-11)
+
+
 def test_softdtw_batch_weighted_gradient():
     r = rng(18)
     X = r.standard_normal((10, 2))
