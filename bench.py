@@ -258,13 +258,31 @@ def soft_section(wts, dev, steps: int = 2, gamma: float = 0.1, band: float = 0.0
     gcups = counted / sec / 1e9
     cm = c_min_soft(w.d)
     frac = gcups * 1e9 * cm / VALU_LANE_OPS_PEAK
-    return {"workload": w.name + ": Soft-DTW gamma=%g, forward + backward + preconditioned "
-                                 "step (eta 0.5), weights 1/m_k%s"
-                                 % (gamma, ", Sakoe-Chiba band %g" % band if band else ""),
-            "gcups_fwd_bwd": round(gcups, 2), "s_per_gradient_step": round(sec, 4),
-            "forward_ms": round(1e3 * float(np.mean(tf)), 2),
-            "backward_ms": round(1e3 * float(np.mean(tb)), 2),
-            "cells_per_pass": cells, "ops_per_cell": cm, "alu_frac": round(frac, 4)}
+    rec = {"workload": w.name + ": Soft-DTW gamma=%g, forward + backward + preconditioned "
+                                "step (eta 0.5), weights 1/m_k%s"
+                                % (gamma, ", Sakoe-Chiba band %g" % band if band else ""),
+           "gcups_fwd_bwd": round(gcups, 2), "s_per_gradient_step": round(sec, 4),
+           "forward_ms": round(1e3 * float(np.mean(tf)), 2),
+           "backward_ms": round(1e3 * float(np.mean(tb)), 2),
+           "cells_per_pass": cells, "ops_per_cell": cm, "alu_frac": round(frac, 4)}
+    if band == 0.0:
+        # the gradient with respect to the cycles: one more forward and
+        # backward over the same cells, with the cycles on the rows
+        Y64 = Y.to(torch.float64)
+        wts.softdtw_grad_cycles(plan, B, Y64, gamma, gv)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(steps):
+            wts.softdtw_grad_cycles(plan, B, Y64, gamma, gv)
+        ev[1].record()
+        torch.cuda.synchronize()
+        if wts.device_status(plan, wts.OP_SOFT_GRAD_C) != 0:
+            raise RuntimeError("device status after the cycles gradient")
+        tg = ev[0].elapsed_time(ev[1]) / 1e3 / steps
+        gg = 2 * cells / tg / 1e9
+        rec["grad_cycles"] = {"ms": round(1e3 * tg, 2), "gcups_fwd_bwd": round(gg, 2),
+                              "alu_frac": round(gg * 1e9 * cm / VALU_LANE_OPS_PEAK, 4)}
+    return rec
 
 
 def dba_per_cycle_speedup(wts, plan, off, d, dt, L, Y, B, sequential=False):

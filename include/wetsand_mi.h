@@ -216,7 +216,9 @@ wts_status wts_softdtw_backward(const wts_plan* plan, const double* bary, const 
  * sweep with the cycles on the rows.  cycles64: the cycle values as float64
  * [sum N][d]; grad_value [n] float64 or NULL (all 1); grad_cycles [sum N][d]
  * float64, overwritten.  ws: workspace of wts_workspace_bytes(WTS_OP_SOFT_GRAD_C)
- * bytes (it holds this call's own checkpoints). */
+ * bytes (it holds this call's own checkpoints; no wts_softdtw_forward is
+ * needed first).  WTS_E_ARG for a null pointer, a ws not 256-byte aligned, gamma
+ * not finite and > 0, or a plan created with L = 0; WTS_E_WORKSPACE for a short ws. */
 wts_status wts_softdtw_grad_cycles(const wts_plan* plan, const double* bary, const double* cycles64,
                                    double gamma, const double* grad_value, double* grad_cycles,
                                    void* ws, size_t ws_bytes, void* stream);

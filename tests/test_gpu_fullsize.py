@@ -147,6 +147,30 @@ def test_config4_full_soft_sampled(wts, gamma, band):
     check_vec(h.cpu().numpy(), oh)
 
 
+@pytest.mark.timeout(900)
+def test_config4_full_grad_cycles_sampled(wts):
+    """The gradient with respect to the cycles on all 128 cycles of the
+    20000-sample workload (gamma 0.1, weights 1/m_k, the bench's call); the
+    rows of two cycles checked against the oracle within 1e-4."""
+    import torch
+    w = _config4()
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    plan = wts.Plan(off, 6, dt, w.L)
+    cyc = f64(w.cycles)
+    B, _ = wts.init_barycenter(plan, Y, wts.INIT_EUCLID_MEAN)
+    Bo = oracle.euclid_mean(cyc, w.L)
+    wv = 1.0 / w.lengths.astype(np.float64)
+    say("c4: gradient w.r.t. the cycles, all 128 cycles")
+    g = wts.softdtw_grad_cycles(plan, B, Y.to(torch.float64), 0.1, torch.from_numpy(wv).cuda())
+    torch.cuda.synchronize()
+    assert wts.device_status(plan, wts.OP_SOFT_GRAD_C) == 0
+    g = g.cpu().numpy()
+    for q in (5, 77):
+        say("c4: oracle gradient for cycle", q)
+        _, want = oracle.softdtw_grad_y(Bo, cyc[q], 0.1)
+        check_vec(g[off[q]:off[q + 1]], wv[q] * want)
+
+
 @functools.lru_cache(maxsize=1)
 def _config5():
     return synth.make(5)
