@@ -511,8 +511,9 @@ int32_t wts_plan_rho(const wts_plan* p, int op) {
       return p->bary.rho;
     case WTS_OP_SOFT_FWD:
     case WTS_OP_SOFT_BWD:
+    case WTS_OP_SOFT_GRAD_C:
       if (p->L <= 0) return fail(WTS_E_ARG, "plan was created with L = 0 (medoid/init only)");
-      return p->soft.rho;
+      return op == WTS_OP_SOFT_GRAD_C ? p->softT.rho : p->soft.rho;
     case WTS_OP_MEDOID:
       if (p->L != 0) return fail(WTS_E_ARG, "medoid needs a plan with L = 0");
       return p->med.rho;

@@ -178,3 +178,6 @@ def test_grad_cycles_rejects_bad_arguments(wts):
     with pytest.raises(wts.WtsError):
         wts.softdtw_grad_cycles(mplan, Bt, Y, 1.0)
     assert torch.isfinite(wts.softdtw_grad_cycles(plan, Bt, Y, 1.0)).all()
+    assert plan.rho(wts.OP_SOFT_GRAD_C) == plan.rho(wts.OP_SOFT_FWD) == 2
+    assert plan.workspace_bytes(wts.OP_SOFT_GRAD_C) > 0
+    assert mplan.workspace_bytes(wts.OP_SOFT_GRAD_C) == 0
