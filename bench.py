@@ -282,6 +282,16 @@ def soft_section(wts, dev, steps: int = 2, gamma: float = 0.1, band: float = 0.0
         gg = 2 * cells / tg / 1e9
         rec["grad_cycles"] = {"ms": round(1e3 * tg, 2), "gcups_fwd_bwd": round(gg, 2),
                               "alu_frac": round(gg * 1e9 * cm / VALU_LANE_OPS_PEAK, 4)}
+        # Table I's optimizer, bounded to 3 iterations / 8 evaluations: the
+        # host L-BFGS share is the wall time beyond the evaluations' sweeps
+        t0 = time.perf_counter()
+        _, hist = wts.lbfgs_barycenter(plan, Y, B, gamma, gv, max_iter=3, max_eval=8)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        rec["lbfgs"] = {"iterations_max": 3, "evaluations": len(hist),
+                        "s_per_evaluation": round(tl / len(hist), 4),
+                        "objective_first_last": [round(hist[0], 6), round(hist[-1], 6)],
+                        "sweep_share": round(len(hist) * sec / tl, 3)}
     return rec
 
 
