@@ -59,7 +59,7 @@ SHAPES = [(1, [1, 7]), (7, [1, 64, 130]), (128, [127, 129]), (300, [129, 1]),
 
 
 @pytest.mark.parametrize("gamma", [0.1, 1.0])
-@pytest.mark.parametrize("d", [1, 3, 6])
+@pytest.mark.parametrize("d", [1, 3, 6, 8])
 @pytest.mark.parametrize("L,lens", SHAPES)
 def test_grad_cycles_matches_oracle(wts, gamma, d, L, lens):
     import torch
