@@ -273,6 +273,42 @@ def test_medoid_sampled_bitwise(wts, rho):
     assert int(k.item()) == ko
 
 
+# ----------------------------------------------------------- channel counts
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_every_channel_count(wts, d):
+    """Every kernel instance a plan can select (d = 1..8): paths, one DBA
+    iteration, scores and the medoid bit for bit, on float32 cycles with a
+    ragged tail and a one-sample cycle."""
+    import torch
+    r = rng(900 + d)
+    L = 150
+    cyc = [r.standard_normal((N, d)).astype(np.float32) for N in (1, 90, 300)]
+    B = r.standard_normal((L, d))
+    say("case channels d=%d" % d)
+    dist, plen, paths = run_align(wts, B, cyc, paths=True)
+    for k, Y in enumerate(cyc):
+        od, ol, op, _ = oracle.dtw(B, np.asarray(Y, np.float64))
+        assert dist[k] == od and plen[k] == ol
+        np.testing.assert_array_equal(paths[k], op)
+    Y, off, dt = wts.pack_cycles(cyc)
+    plan = wts.Plan(off, d, dt, L)
+    Bt = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    Bg, counts, dist = wts.dba_iterate(plan, Bt, Y)
+    Bn, K, od, _ = oracle.dba_iterate(B, as64(cyc))
+    np.testing.assert_array_equal(Bg.cpu().numpy(), Bn)
+    np.testing.assert_array_equal(counts.cpu().numpy(), K)
+    score, _, plen = wts.anomaly_score(plan, Bt, Y)
+    os_, _, ol = oracle.score_batch(B, as64(cyc))
+    np.testing.assert_array_equal(score.cpu().numpy(), os_)
+    np.testing.assert_array_equal(plen.cpu().numpy(), ol)
+    mplan = wts.Plan(off, d, dt, 0)
+    k, Dm, _ = wts.medoid(mplan, Y)
+    ko, Do = oracle.medoid(as64(cyc))
+    np.testing.assert_array_equal(Dm.cpu().numpy(), Do)
+    assert int(k.item()) == ko
+
+
 # ------------------------------------------------------------------- graphs
 
 def test_graph_replay_matches_eager(wts):

@@ -46,7 +46,7 @@ SHAPES = [(1, [1, 7]), (5, [1, 64, 130]), (127, [128, 129]), (129, [300, 1]),
 
 
 @pytest.mark.parametrize("gamma", [0.1, 1.0])
-@pytest.mark.parametrize("d", [1, 3, 6])
+@pytest.mark.parametrize("d", [1, 3, 6, 8])
 @pytest.mark.parametrize("L,lens", SHAPES)
 def test_soft_forward_and_gradient(wts, gamma, d, L, lens):
     import torch

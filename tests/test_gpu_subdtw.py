@@ -54,7 +54,7 @@ SHAPES = [  # (M, window lengths): one and several strips, windows shorter than 
 ]
 
 
-@pytest.mark.parametrize("d", [1, 3, 6])
+@pytest.mark.parametrize("d", [1, 3, 6, 8])
 @pytest.mark.parametrize("M,lens", SHAPES)
 def test_subdtw_bitwise(wts, d, M, lens):
     r = rng(1000 * d + M)
