@@ -37,7 +37,8 @@ def test_header_declares_the_entry_points():
     names = declared()
     for n in ["wts_plan_create", "wts_plan_destroy", "wts_workspace_bytes", "wts_last_error",
               "wts_dtw_align", "wts_dba_iterate", "wts_softdtw_forward", "wts_softdtw_backward",
-              "wts_anomaly_score", "wts_medoid", "wts_init_barycenter"]:
+              "wts_anomaly_score", "wts_medoid", "wts_init_barycenter", "wts_subdtw",
+              "wts_softdtw_grad_cycles"]:
         assert n in names
 
 
@@ -84,6 +85,9 @@ def test_null_plan_is_rejected(lib):
     assert lib.wts_dba_iterate(None, P(1), P(1), None, P(2), P(1), None, P(256), ctypes.c_size_t(1), None) == WTS_E_ARG
     assert lib.wts_anomaly_score(None, P(1), P(1), P(1), None, None, P(256), ctypes.c_size_t(1), None) == WTS_E_ARG
     assert lib.wts_medoid(None, P(1), None, None, P(1), P(256), ctypes.c_size_t(1), None) == WTS_E_ARG
+    assert lib.wts_softdtw_grad_cycles(None, P(1), P(1), ctypes.c_double(1.0), None, P(1), P(256),
+                                       ctypes.c_size_t(1), None) == WTS_E_ARG
+    assert lib.wts_subdtw(None, P(1), P(1), P(1), P(1), P(1), P(256), ctypes.c_size_t(1), None) == WTS_E_ARG
     assert lib.wts_workspace_bytes(None, 0) == 0
     lib.wts_plan_destroy(None)   # no-op
 
