@@ -181,3 +181,42 @@ def test_grad_cycles_rejects_bad_arguments(wts):
     assert plan.rho(wts.OP_SOFT_GRAD_C) == plan.rho(wts.OP_SOFT_FWD) == 2
     assert plan.workspace_bytes(wts.OP_SOFT_GRAD_C) > 0
     assert mplan.workspace_bytes(wts.OP_SOFT_GRAD_C) == 0
+
+
+def test_soft_calls_replay_from_a_captured_graph(wts):
+    """Forward, backward and the cycles gradient captured in one HIP graph:
+    every replay, with eager work on the same buffers in between, gives the
+    eager results bit for bit (the sweeps are deterministic)."""
+    import torch
+    r = rng(8)
+    B = r.standard_normal((300, 3))
+    cyc = [r.standard_normal((N, 3)) for N in (257, 129, 400)]
+    plan, Bt, Y = setup(wts, B, cyc, dtype="f64")
+    wv = torch.tensor([0.5, 1.0, 2.0], dtype=torch.float64, device="cuda")
+
+    def calls():
+        v, ck = wts.softdtw_forward(plan, Bt, Y, 0.5)
+        gb = wts.softdtw_backward(plan, Bt, Y, 0.5, ck, wv)
+        gc = wts.softdtw_grad_cycles(plan, Bt, Y, 0.5, wv)
+        return v, gb, gc
+
+    say("case graph: eager")
+    ref = [t.clone() for t in calls()]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    say("case graph: capture")
+    with torch.cuda.graph(g, stream=s):
+        out = calls()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        say("case graph: replay", rep)
+        for t in out:
+            t.fill_(-1.0)
+        eager = calls()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b, e in zip(out, ref, eager):
+            assert torch.equal(a, b) and torch.equal(e, b)
