@@ -136,3 +136,39 @@ def test_segmentation_matches_oracle(wts):
         want = oracle.segment(Xd, Y.astype(np.float64))
         assert g == want
         assert len(g) >= 3
+
+
+def test_subdtw_replays_from_a_captured_graph(wts):
+    """One Sub-DTW launch over a batch of windows captured in a HIP graph:
+    every replay, with eager calls on the same workspace in between, gives
+    the oracle's values and columns."""
+    import torch
+    r = rng(31)
+    X = r.standard_normal((150, 3))
+    wins = [r.standard_normal((N, 3)) for N in (300, 151, 1, 700)]
+    Y, off, dt = wts.pack_cycles(wins, dtype="f64")
+    plan = wts.Plan(off, 3, dt, 150)
+    Xt = torch.from_numpy(X).cuda()
+    ov, oa, ob = oracle.subdtw_batch(X, wins)
+    wts.subdtw(plan, Xt, Y)   # allocates the plan's workspace before the capture
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    say("case subdtw graph: capture")
+    with torch.cuda.graph(g, stream=s):
+        v, a, b = wts.subdtw(plan, Xt, Y)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        say("case subdtw graph: replay", rep)
+        v.fill_(-1.0)
+        a.fill_(-1)
+        b.fill_(-1)
+        ev, ea, eb = wts.subdtw(plan, Xt, Y)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for got in ((v, a, b), (ev, ea, eb)):
+            np.testing.assert_array_equal(got[0].cpu().numpy(), ov)
+            np.testing.assert_array_equal(got[1].cpu().numpy(), oa)
+            np.testing.assert_array_equal(got[2].cpu().numpy(), ob)
