@@ -340,3 +340,58 @@ def test_graph_replay_matches_eager(wts):
         torch.cuda.synchronize()
         assert torch.equal(Bout, ref[0]) and torch.equal(counts, ref[1])
         assert torch.equal(dist, ref[2])
+
+
+def test_medoid_scores_and_paths_replay_from_a_captured_graph(wts):
+    """The medoid, the scores and the path alignment captured in one HIP
+    graph: every replay, with eager calls in between, matches the oracle bit
+    for bit."""
+    import torch
+    w = synth.make(2, n=7, len_range=(150, 400))
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    cyc = as64(w.cycles)
+    ko, Do = oracle.medoid(cyc)
+    L = int(w.lengths[ko])
+    mplan = wts.Plan(off, 3, dt, 0)
+    plan = wts.Plan(off, 3, dt, L)
+    B = torch.from_numpy(np.ascontiguousarray(cyc[ko])).cuda()
+    os_, od, ol = oracle.score_batch(cyc[ko], cyc)
+
+    def calls():
+        k, Dm, _ = wts.medoid(mplan, Y)
+        score, _, plen = wts.anomaly_score(plan, B, Y)
+        dist, plen2, pth = wts.dtw_align(plan, B, Y, paths=True)
+        return k, Dm, score, plen, dist, plen2, pth
+
+    def check(out):
+        k, Dm, score, plen, dist, plen2, pth = out
+        assert int(k.item()) == ko
+        np.testing.assert_array_equal(Dm.cpu().numpy(), Do)
+        np.testing.assert_array_equal(score.cpu().numpy(), os_)
+        np.testing.assert_array_equal(plen.cpu().numpy(), ol)
+        np.testing.assert_array_equal(dist.cpu().numpy(), od)
+        np.testing.assert_array_equal(plen2.cpu().numpy(), ol)
+        for q in (0, ko, w.n - 1):
+            _, _, op, _ = oracle.dtw(cyc[ko], cyc[q])
+            np.testing.assert_array_equal(wts.path_of(plan, pth, plen2, q), op)
+
+    say("case graph dtw: eager")
+    check(calls())
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    say("case graph dtw: capture")
+    with torch.cuda.graph(g, stream=s):
+        out = calls()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        say("case graph dtw: replay", rep)
+        for t in out:
+            t.fill_(-1)
+        eager = calls()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        check(out)
+        check(eager)
