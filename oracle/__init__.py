@@ -53,6 +53,7 @@ def lib():
         L.wts_o_softdtw.argtypes = [P, I64, P, I64, I32, D, P, P]
         L.wts_o_softdtw_band.argtypes = [P, I64, P, I64, I32, D, D, P, P]
         L.wts_o_softdtw_grad_band.argtypes = [P, I64, P, I64, I32, D, D, P, P, P, P]
+        L.wts_o_softdtw_grad_ckpt.argtypes = [P, I64, P, I64, I32, D, D, P, P, P]
         L.wts_o_softdtw_batch_band.argtypes = [P, I64, P, P, I32, I32, D, D, P, P, P, P]
         L.wts_o_band_cols.argtypes = [I64, I64, D, I64, P, P]
         L.wts_o_band_cols.restype = None
@@ -69,7 +70,8 @@ def lib():
                   "wts_o_softdtw", "wts_o_softdtw_grad", "wts_o_softdtw_batch", "wts_o_medoid",
                   "wts_o_euclid_mean", "wts_o_nearest_init", "wts_o_num_threads",
                   "wts_o_subdtw", "wts_o_subdtw_batch", "wts_o_softdtw_band",
-                  "wts_o_softdtw_grad_band", "wts_o_softdtw_batch_band"):
+                  "wts_o_softdtw_grad_band", "wts_o_softdtw_batch_band",
+                  "wts_o_softdtw_grad_ckpt"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -191,6 +193,20 @@ def softdtw_grad(X, Y, gamma, with_E=False, band=0.0):
     _check(lib().wts_o_softdtw_grad_band(_p(X), M, _p(Y), N, d, float(gamma), float(band),
                                          _p(v), _p(g), _p(h), _p(E)))
     return float(v[0]), g, h, E
+
+
+def softdtw_grad_ckpt(X, Y, gamma, band=0.0):
+    """Eq. 6 with square-root checkpointing of R (memory ~2 sqrt(M) N doubles,
+    for pairs of 50k samples): returns (value, grad [M][d], rowmass [M]),
+    bitwise those of softdtw_grad."""
+    X, Y = _series(X), _series(Y)
+    M, N, d = X.shape[0], Y.shape[0], X.shape[1]
+    v = np.zeros(1)
+    g = np.zeros((M, d))
+    h = np.zeros(M)
+    _check(lib().wts_o_softdtw_grad_ckpt(_p(X), M, _p(Y), N, d, float(gamma), float(band),
+                                         _p(v), _p(g), _p(h)))
+    return float(v[0]), g, h
 
 
 def softdtw_grad_y(X, Y, gamma, band=0.0):

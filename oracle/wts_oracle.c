@@ -268,6 +268,23 @@ static void band_cols(int64_t M, int64_t N, double w, int64_t i, int64_t* jlo, i
   if (hi < *jhi) *jhi = hi;
 }
 
+/* Eq. 5 with gamma > 0, restricted to the band (cells outside: +inf), for
+ * one row i: prev[j+1] = r(i-1, j) and prev[0] = r(i-1, -1) on entry; cur
+ * receives r(i, -1) = +inf in cur[0] and r(i, j) in cur[j+1]. */
+static void soft_row(const double* X, int64_t M, const double* Y, int64_t N, int d,
+                     double gamma, double band, int64_t i, const double* prev, double* cur) {
+  int64_t jlo, jhi;
+  band_cols(M, N, band, i, &jlo, &jhi);
+  cur[0] = INFINITY;
+  for (int64_t j = 0; j < N; ++j) {
+    double r = INFINITY;
+    if (j >= jlo && j <= jhi)
+      r = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID) +
+          softmin3(prev[j], prev[j + 1], cur[j], gamma);
+    cur[j + 1] = r;
+  }
+}
+
 /* Eq. 5 with gamma > 0, restricted to the band (cells outside: +inf). */
 int wts_o_softdtw_band(const double* X, int64_t M, const double* Y, int64_t N, int d,
                        double gamma, double band, double* value, double* R) {
@@ -277,17 +294,8 @@ int wts_o_softdtw_band(const double* X, int64_t M, const double* Y, int64_t N, i
   prev[0] = 0.0;
   for (int64_t j = 0; j < N; ++j) prev[j + 1] = INFINITY;
   for (int64_t i = 0; i < M; ++i) {
-    cur[0] = INFINITY;
-    int64_t jlo, jhi;
-    band_cols(M, N, band, i, &jlo, &jhi);
-    for (int64_t j = 0; j < N; ++j) {
-      double r = INFINITY;
-      if (j >= jlo && j <= jhi)
-        r = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID) +
-            softmin3(prev[j], prev[j + 1], cur[j], gamma);
-      cur[j + 1] = r;
-      if (R) R[i * N + j] = r;
-    }
+    soft_row(X, M, Y, N, d, gamma, band, i, prev, cur);
+    if (R) memcpy(R + i * N, cur + 1, sizeof(double) * (size_t)N);
     double* t = prev; prev = cur; cur = t;
     prev[0] = INFINITY;
   }
@@ -296,24 +304,69 @@ int wts_o_softdtw_band(const double* X, int64_t M, const double* Y, int64_t N, i
   return 0;
 }
 
-/* Eq. 6: gradient of Soft-DTW^gamma(X, Y) with respect to X.
- * E is obtained from Eq. 5 by the chain rule.  On the grid extended by one
- * row and one column:
- *   r(M, j) = r(i, N) = -inf except r(M, N) = r(M-1, N-1); delta = 0 outside;
- *   e(M, N) = 1; every other e outside the grid = 0;
- *   e(i, j) = sum over the successors (i+1, j), (i, j+1), (i+1, j+1) of
- *             e(p, q) * exp((r(p, q) - delta(p, q) - r(i, j)) / gamma).
- * With the squared Euclidean delta, d delta_{ij} / d x_i = 2 (x_i - y_j), so
- *   grad_i = sum_j e(i, j) * 2 (x_i - y_j)   (j ascending).
- * Outputs: value, grad (M*d), rowmass (M, sum_j e(i,j); may be NULL),
- * E (M*N; may be NULL).  Needs M*N doubles for R. */
 int wts_o_softdtw(const double* X, int64_t M, const double* Y, int64_t N, int d, double gamma,
                   double* value, double* R) {
   return wts_o_softdtw_band(X, M, Y, N, d, gamma, 0.0, value, R);
 }
 
-/* Eq. 6 restricted to the band: cells outside it have e = 0, and a
- * successor with e = 0 passes nothing on. */
+/* One row i of the E recursion of Eq. 6 (restricted to the band: cells
+ * outside it have e = 0, and a successor with e = 0 passes nothing on).
+ * Ri[j] = r(i, j); on entry enext, rnext, dnext hold e, r and delta of row
+ * i+1 (indices 0..N, index N the column outside the grid); ecur receives
+ * e(i, .).  Writes grad row i (sum_j e(i, j) 2 (x_i - y_j), j ascending),
+ * rowmass[i] (if non-NULL) and E row i (if non-NULL), then shifts row i into
+ * the "next" buffers for row i-1. */
+static void soft_e_row(const double* X, int64_t M, const double* Y, int64_t N, int d,
+                       double gamma, double band, int64_t i, const double* Ri, double* enext,
+                       double* ecur, double* rnext, double* dnext, double* grad,
+                       double* rowmass, double* E) {
+  /* column N (outside) of row i: r = -inf, e = 0, delta = 0 */
+  double e_right = 0.0, r_right = -INFINITY, d_right = 0.0;
+  int64_t jlo, jhi;
+  band_cols(M, N, band, i, &jlo, &jhi);
+  for (int64_t j = N - 1; j >= 0; --j) {
+    double rij = Ri[j];
+    double e = 0.0;
+    if (j >= jlo && j <= jhi) {
+      if (enext[j] != 0.0)                                                  /* (i+1, j)   */
+        e = e + enext[j] * exp((rnext[j] - dnext[j] - rij) / gamma);
+      if (e_right != 0.0)                                                   /* (i, j+1)   */
+        e = e + e_right * exp((r_right - d_right - rij) / gamma);
+      if (enext[j + 1] != 0.0)                                              /* (i+1, j+1) */
+        e = e + enext[j + 1] * exp((rnext[j + 1] - dnext[j + 1] - rij) / gamma);
+    }
+    ecur[j] = e;
+    e_right = e;
+    r_right = rij;
+    d_right = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID);
+    if (E) E[i * N + j] = e;
+  }
+  /* gradient row i, then shift row i into the "next" buffers */
+  double mass = 0.0;
+  for (int c = 0; c < d; ++c) {
+    double g = 0.0;
+    for (int64_t j = 0; j < N; ++j) g = g + ecur[j] * (2.0 * (X[i * d + c] - Y[j * d + c]));
+    grad[i * d + c] = g;
+  }
+  for (int64_t j = 0; j < N; ++j) mass = mass + ecur[j];
+  if (rowmass) rowmass[i] = mass;
+  for (int64_t j = 0; j < N; ++j) {
+    enext[j] = ecur[j];
+    rnext[j] = Ri[j];
+    dnext[j] = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID);
+  }
+  enext[N] = 0.0; rnext[N] = -INFINITY; dnext[N] = 0.0;
+}
+
+/* The row M outside the grid: r = -inf except r(M, N) = r(M-1, N-1); e = 0
+ * except e(M, N) = 1; delta = 0. */
+static void soft_e_init(int64_t N, double rlast, double* enext, double* rnext, double* dnext) {
+  for (int64_t j = 0; j <= N; ++j) { enext[j] = 0.0; rnext[j] = -INFINITY; dnext[j] = 0.0; }
+  enext[N] = 1.0;
+  rnext[N] = rlast;
+}
+
+/* Eq. 6 restricted to the band, keeping the whole R (M*N doubles). */
 int wts_o_softdtw_grad_band(const double* X, int64_t M, const double* Y, int64_t N, int d,
                             double gamma, double band, double* value, double* grad,
                             double* rowmass, double* E) {
@@ -327,49 +380,65 @@ int wts_o_softdtw_grad_band(const double* X, int64_t M, const double* Y, int64_t
     return -1;
   }
   wts_o_softdtw_band(X, M, Y, N, d, gamma, band, value, R);
-  /* row M (outside): r = -inf except r(M, N) = r(M-1, N-1); e = 0 except e(M, N) = 1 */
-  for (int64_t j = 0; j <= N; ++j) { enext[j] = 0.0; rnext[j] = -INFINITY; dnext[j] = 0.0; }
-  enext[N] = 1.0;
-  rnext[N] = R[(M - 1) * N + (N - 1)];
-  for (int64_t i = M - 1; i >= 0; --i) {
-    /* column N (outside) of row i: r = -inf, e = 0, delta = 0 */
-    double e_right = 0.0, r_right = -INFINITY, d_right = 0.0;
-    int64_t jlo, jhi;
-    band_cols(M, N, band, i, &jlo, &jhi);
-    for (int64_t j = N - 1; j >= 0; --j) {
-      double rij = R[i * N + j];
-      double e = 0.0;
-      if (j >= jlo && j <= jhi) {
-        if (enext[j] != 0.0)                                                  /* (i+1, j)   */
-          e = e + enext[j] * exp((rnext[j] - dnext[j] - rij) / gamma);
-        if (e_right != 0.0)                                                   /* (i, j+1)   */
-          e = e + e_right * exp((r_right - d_right - rij) / gamma);
-        if (enext[j + 1] != 0.0)                                              /* (i+1, j+1) */
-          e = e + enext[j + 1] * exp((rnext[j + 1] - dnext[j + 1] - rij) / gamma);
-      }
-      ecur[j] = e;
-      e_right = e;
-      r_right = rij;
-      d_right = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID);
-      if (E) E[i * N + j] = e;
-    }
-    /* gradient row i, then shift row i into the "next" buffers */
-    double mass = 0.0;
-    for (int c = 0; c < d; ++c) {
-      double g = 0.0;
-      for (int64_t j = 0; j < N; ++j) g = g + ecur[j] * (2.0 * (X[i * d + c] - Y[j * d + c]));
-      grad[i * d + c] = g;
-    }
-    for (int64_t j = 0; j < N; ++j) mass = mass + ecur[j];
-    if (rowmass) rowmass[i] = mass;
-    for (int64_t j = 0; j < N; ++j) {
-      enext[j] = ecur[j];
-      rnext[j] = R[i * N + j];
-      dnext[j] = wts_o_cost(X + i * d, Y + j * d, d, O_SQEUCLID);
-    }
-    enext[N] = 0.0; rnext[N] = -INFINITY; dnext[N] = 0.0;
-  }
+  soft_e_init(N, R[(M - 1) * N + (N - 1)], enext, rnext, dnext);
+  for (int64_t i = M - 1; i >= 0; --i)
+    soft_e_row(X, M, Y, N, d, gamma, band, i, R + i * N, enext, ecur, rnext, dnext, grad,
+               rowmass, E);
   free(R); free(enext); free(ecur); free(rnext); free(dnext);
+  return 0;
+}
+
+/* The same gradient with square-root checkpointing, for pairs whose R does
+ * not fit in memory (50k x 50k: 20 GB).  The forward keeps only the R row
+ * above each segment of K = ceil(sqrt(M)) rows; the backward takes the
+ * segments from the last to the first, recomputes the segment's K rows of R
+ * from the row kept above it, and runs the E recursion over them.  Every
+ * value is produced by the same row functions as above, so value, grad and
+ * rowmass are bitwise those of wts_o_softdtw_grad_band; memory is about
+ * 2 sqrt(M) N doubles. */
+int wts_o_softdtw_grad_ckpt(const double* X, int64_t M, const double* Y, int64_t N, int d,
+                            double gamma, double band, double* value, double* grad,
+                            double* rowmass) {
+  int64_t K = (int64_t)sqrt((double)M);
+  while (K * K < M) ++K;
+  while (K > 1 && (K - 1) * (K - 1) >= M) --K;
+  const int64_t S = (M + K - 1) / K;
+  double* keep = (double*)malloc(sizeof(double) * (size_t)(S * (N + 1)));
+  double* seg = (double*)malloc(sizeof(double) * (size_t)(K * (N + 1)));
+  double* prev = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* enext = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* ecur = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* rnext = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* dnext = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  if (!keep || !seg || !prev || !enext || !ecur || !rnext || !dnext) {
+    free(keep); free(seg); free(prev); free(enext); free(ecur); free(rnext); free(dnext);
+    return -1;
+  }
+  /* forward: keep[s] = the row r(sK - 1, .) above segment s (index 0: the
+   * left boundary), the initial row r(-1, .) for s = 0 */
+  prev[0] = 0.0;
+  for (int64_t j = 0; j < N; ++j) prev[j + 1] = INFINITY;
+  for (int64_t i = 0; i < M; ++i) {
+    if (i % K == 0) memcpy(keep + (i / K) * (N + 1), prev, sizeof(double) * (size_t)(N + 1));
+    soft_row(X, M, Y, N, d, gamma, band, i, prev, ecur);
+    memcpy(prev, ecur, sizeof(double) * (size_t)(N + 1));
+    prev[0] = INFINITY;
+  }
+  *value = prev[N];
+  soft_e_init(N, prev[N], enext, rnext, dnext);
+  for (int64_t s = S - 1; s >= 0; --s) {
+    const int64_t a = s * K, b = (a + K < M) ? a + K : M;
+    /* rows a .. b-1 of R into seg (row i at seg + (i - a) (N + 1) + 1) */
+    const double* above = keep + s * (N + 1);
+    for (int64_t i = a; i < b; ++i) {
+      double* cur = seg + (i - a) * (N + 1);
+      soft_row(X, M, Y, N, d, gamma, band, i, i == a ? above : seg + (i - a - 1) * (N + 1), cur);
+    }
+    for (int64_t i = b - 1; i >= a; --i)
+      soft_e_row(X, M, Y, N, d, gamma, band, i, seg + (i - a) * (N + 1) + 1, enext, ecur,
+                 rnext, dnext, grad, rowmass, NULL);
+  }
+  free(keep); free(seg); free(prev); free(enext); free(ecur); free(rnext); free(dnext);
   return 0;
 }
 
@@ -458,8 +527,8 @@ int wts_o_softdtw_batch_band(const double* X, int64_t M, const double* Yall, con
     int64_t N = off[p + 1] - off[p];
     if (grad || rowmass) {
       double* g = pg ? pg + (int64_t)p * M * d : (double*)malloc(sizeof(double) * (size_t)(M * d));
-      err |= wts_o_softdtw_grad_band(X, M, Y, N, d, gamma, band, &values[p], g,
-                                ph ? ph + (int64_t)p * M : NULL, NULL);
+      err |= wts_o_softdtw_grad_ckpt(X, M, Y, N, d, gamma, band, &values[p], g,
+                                     ph ? ph + (int64_t)p * M : NULL);
       if (!pg) free(g);
     } else {
       err |= wts_o_softdtw_band(X, M, Y, N, d, gamma, band, &values[p], NULL);

@@ -534,3 +534,21 @@ def test_softdtw_band_gradient_finite_differences():
         Xm[i, c] -= h
         fd = (oracle.softdtw(Xp, Y, 0.7, band=0.3) - oracle.softdtw(Xm, Y, 0.7, band=0.3)) / (2 * h)
         assert abs(fd - g[i, c]) <= 1e-6 * max(1.0, abs(g[i, c]))
+
+
+@pytest.mark.parametrize("M,N,band", [(1, 9, 0.0), (2, 2, 0.0), (3, 8, 0.0), (15, 11, 0.0),
+                                      (16, 20, 0.0), (17, 13, 0.3), (24, 24, 0.0),
+                                      (25, 30, 0.6), (26, 7, 0.0), (301, 257, 0.0)])
+def test_softdtw_grad_checkpointed_is_bitwise_the_full_R(M, N, band):
+    """Square-root checkpointing of R (the memory plan for 50k-sample pairs)
+    recomputes each segment of ceil(sqrt(M)) rows from the row kept above it:
+    value, gradient and row mass must be bitwise those of the oracle that
+    keeps all of R, for M just below, at and just above perfect squares."""
+    r = rng(70 + M)
+    X, Y = r.standard_normal((M, 3)), r.standard_normal((N, 3))
+    for gamma in (0.1, 1.0):
+        v, g, h, _ = oracle.softdtw_grad(X, Y, gamma, band=band)
+        v2, g2, h2 = oracle.softdtw_grad_ckpt(X, Y, gamma, band=band)
+        assert v == v2
+        np.testing.assert_array_equal(g, g2)
+        np.testing.assert_array_equal(h, h2)
