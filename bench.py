@@ -1,18 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the WETSAND hot path on one MI355X.
 
-Workload (default): 64 cycles x 3 channels, float32, lengths U{4000..6000},
-random-Fourier template with random time warps, N(0, 0.05) noise and three
-cycles carrying a gradual drift.  One step is the whole DTW path over that
-batch: medoid initialisation (all-pairs DTW), 10 DBA iterations from the
-medoid, then the anomaly score of every cycle.  Inputs are resident in HBM
-before timing starts.
+Headline workload: 256 cycles x 6 channels, float32, lengths 40,000..50,000
+with 1 % of the samples dropped in gaps of 1..50 (the irregular workload the
+paper's robots produce: missing samples are dropped, Sec. III-A), barycenter
+of L = max N = 49,454 rows, nearest-length initialisation.  One step is one
+barycenter iteration of the paper's prototype computation on all cycles:
 
-Metric: DTW cell updates per second (GCUPS), cells = M * N per dynamic
-program (all pairs of the medoid, L * N_k per DBA iteration and for the
-scores).  Also reported: seconds per DBA iteration, per-phase GCUPS, the
-roofline fraction of the dominant kernel, and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+  * one DTW barycenter averaging (DBA) iteration: DTW of every cycle against
+    the barycenter with argmin codes, path backtrack, accumulate-and-average;
+  * one Soft-DTW refinement step (gamma 0.1, Eq. 7 weights 1/m_k) on the DBA
+    result: forward with checkpoints and E-matrix backward over cycle groups
+    whose checkpoints fit in HBM, then the preconditioned update.
+
+The whole step (every kernel of both halves) is captured once in a HIP graph
+and replayed; inputs are resident in HBM before timing starts.
+
+Metric: DTW cell updates per second (GCUPS): cells = L * sum_k N_k per
+dynamic-programming pass, one pass for DBA and two (forward + backward) for
+the Soft-DTW step; recomputation inside the backward is time, not cells.
+Also reported: seconds per barycenter iteration, the roofline of the dominant
+sweep kernel against the VALU lane-op peak with the algorithmic op floors
+(tau, the cost of a transcendental in add slots, measured live by a
+microbenchmark), the FP64 CPU oracle on a bounded sample, and extra sections
+on the other workloads (64 x 4-6k DBA + scores with the medoid; 512 x 1-20k
+graph-replayed DBA; 128 x 20k Soft-DTW descent, finite-difference check and
+L-BFGS; segmentation of robot-scale streams).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -35,31 +48,49 @@ VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9          # 39.32e12 lane-ops/s
 HBM_PEAK_GBS = 8000.0
 
 
-def c_min_dist(d: int) -> int:
-    """Algorithmic VALU ops per cell of the DTW value sweep (squared cost):
-    d subtractions, 1 multiply, d-1 FMAs, 2 minima, 1 add."""
+# ------------------------------------------------------------ op floors
+# Algorithmic VALU operations per DP cell (add/sub/mul/fma/min/cmp/select/cvt
+# count 1, a transcendental counts tau; loads, LDS and cross-lane moves are
+# not counted, and neither is recomputation).
+
+def c_dba(d: int) -> int:
+    """DTW with a 2-bit argmin code per cell (the DBA path sweep): the value
+    recursion (d subtractions, 1 multiply, d-1 FMAs, 2 minima, 1 add) plus
+    the two comparisons that decide the code."""
+    return 2 * d + 5
+
+
+def c_score(d: int) -> int:
+    """DTW value carrying the path length (scores): the value recursion, two
+    comparisons and the carried length's update."""
+    return 2 * d + 6
+
+
+def c_medoid(d: int) -> int:
+    """DTW value only (all pairs of the medoid): the value recursion; no path
+    length and no code are needed for the medoid's totals."""
     return 2 * d + 3
 
 
-def c_min_path(d: int) -> int:
-    """Algorithmic VALU ops per cell of a DTW sweep that also decides the argmin
-    (path code or carried path length): the value recursion (2d + 3), two
-    compares, two selects and one pack/add."""
-    return 2 * d + 8
+def c_sub(d: int) -> int:
+    """Sub-DTW sweep: the value recursion and the two comparisons that decide
+    which start column a cell inherits (as the DBA sweep decides its code)."""
+    return 2 * d + 5
 
 
-def c_min_soft(d: int, tau: int = 2) -> int:
-    """Algorithmic VALU ops per cell of one Soft-DTW forward + backward pass pair,
-    counted per DP pass (two passes per gradient step).  Forward: cost (2d),
-    scale (1), min of three (2), three differences, conversions and base-2
-    exponentials (3 + 3 + 3 tau), sum (2), logarithm (tau), conversion, two
-    adds.  Backward: the replayed forward plus the three weights (reciprocal
-    tau + 3 mul), the E recursion (3 conversions, 3 multiplies, 2 adds) and the
-    gradient sums (d FMAs + 1 add).  tau = 2: a transcendental costs two FP64
-    issue slots (measured)."""
-    fwd = 2 * d + 1 + 2 + 3 + 3 + 3 * tau + 2 + tau + 1 + 2
-    bwd = fwd + tau + 3 + 3 + 3 + 2 + d + 1
-    return (fwd + bwd + 1) // 2
+def c_soft_fwd(d: int, tau: float) -> float:
+    """Soft-DTW forward: cost (2d), three shifted differences, their
+    exponentials (3 tau) and sum, the logarithm (tau), min of three, scaling
+    and conversions: 2d + 13 + 4 tau."""
+    return 2 * d + 13 + 4 * tau
+
+
+def c_soft_bwd(d: int, tau: float) -> float:
+    """Soft-DTW backward: the three soft-min weights of the cell (3 tau and
+    their arguments), the E recursion (3 products, 2 sums), the gradient sums
+    (d FMAs + 1) and the cost terms it needs: 3d + 11 + 3 tau.  The
+    replayed forward of the checkpointed tiles is recomputation, not counted."""
+    return 3 * d + 11 + 3 * tau
 
 
 def kernel_source_hash() -> str:
@@ -68,6 +99,16 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_2404_12134_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+KERNELS = {   # sweep -> rocprofv3 kernel name ({rho}: rows per lane of the plan)
+    "medoid": "void wts::(anonymous namespace)::dtw_fwd_kernel<float, float, 3, {rho}, 0, false>",
+    "dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, {rho}, 2, false>",
+    "score": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, {rho}, 1, false>",
+    "c5_dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 6, {rho}, 2, false>",
+    "c5_soft_fwd": "void wts::(anonymous namespace)::soft_fwd_kernel<float, 6, {rho}, false>",
+    "c5_soft_bwd": "void wts::(anonymous namespace)::soft_bwd_kernel<float, 6, {rho}, false>",
+}
 
 
 def traffic_from_profiles(kernel: str, name: str = None):
@@ -90,69 +131,63 @@ def traffic_from_profiles(kernel: str, name: str = None):
     return None if hit is None else hit.get("bytes_per_launch")
 
 
-KERNELS = {   # sweep -> rocprofv3 kernel name, by rows per lane (rho) of the plan
-    "medoid": "void wts::(anonymous namespace)::dtw_fwd_kernel<float, float, 3, {rho}, 0, false>",
-    "dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, {rho}, 2, false>",
-    "score": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, {rho}, 1, false>",
-}
-
-
 def ingest_traffic(root: str):
     """Reads rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE passes (CSV) found under
     `root` and writes profiles/traffic.json: HBM bytes per launch of every sweep
     kernel, scaled by what the same counters read for the 1 GiB copy of
     `bench.py --only copy` (bytes_read / FETCH_SIZE_KiB, and the same for
-    writes), tagged with the current kernel source hash."""
+    writes), tagged with the current kernel source hash.  Each pass lives in a
+    directory named <phase>_<counter>, so launches of one kernel instance on
+    different workloads are told apart by the phase that ran them."""
     import csv
     import glob
-    # every pass must have run the current kernel source (its --only line says which)
     hashes = set()
-    used = {}              # phase -> the sweep kernel instance its timed steps ran
+    used = {}              # sweep key -> the kernel instance its phase ran
     for f in glob.glob(os.path.join(root, "**", "*.out"), recursive=True):
         for line in open(f, errors="replace"):
             if line.startswith("{") and '"phase"' in line:
                 rec = json.loads(line)
                 hashes.add(rec.get("source_hash"))
-                if rec.get("kernel"):
-                    used[rec["phase"]] = rec["kernel"]
+                for k, v in (rec.get("kernels") or {}).items():
+                    used[k] = v
     if hashes != {kernel_source_hash()}:
         raise SystemExit("counter passes under %s ran kernel sources %s, not the current %s"
                          % (root, sorted(map(str, hashes)), kernel_source_hash()))
     per_dispatch = {}      # counters come in several rows per dispatch: sum them
     for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        phase = os.path.relpath(f, root).split(os.sep)[0].split("_")[0]
         for r in csv.DictReader(open(f)):
-            key = (r["Kernel_Name"], r["Counter_Name"], f, r["Dispatch_Id"])
+            key = (phase, r["Kernel_Name"], r["Counter_Name"], f, r["Dispatch_Id"])
             per_dispatch[key] = per_dispatch.get(key, 0.0) + float(r["Counter_Value"])
     vals = {}
-    for (kname, cname, _, _), v in per_dispatch.items():
-        vals.setdefault((kname, cname), []).append(v)
+    for (phase, kn, cname, _, _), v in per_dispatch.items():
+        vals.setdefault((phase, kn.split("(wts::")[0], cname), []).append(v)
     avg = {k: sum(v) / len(v) for k, v in vals.items()}
     gib = float(1 << 30)
-    # the 1 GiB copies are the largest copyBuffer dispatches of all passes
-    f_cal = max(v for k, vs in vals.items() if "copyBuffer" in k[0] and k[1] == "FETCH_SIZE"
+    f_cal = max(v for k, vs in vals.items() if "copyBuffer" in k[1] and k[2] == "FETCH_SIZE"
                 for v in vs)
-    w_cal = max(v for k, vs in vals.items() if "copyBuffer" in k[0] and k[1] == "WRITE_SIZE"
+    w_cal = max(v for k, vs in vals.items() if "copyBuffer" in k[1] and k[2] == "WRITE_SIZE"
                 for v in vs)
     f_scale, w_scale = gib / f_cal, gib / w_cal        # bytes per counted KiB
     out = {"_calibration": {"copy_bytes": int(gib), "fetch_kib": f_cal, "write_kib": w_cal,
                             "fetch_scale": f_scale, "write_scale": w_scale}}
-    for key in KERNELS:
-        # every instance of this sweep that ran a complete launch in the
-        # passes (the sweep-shape tuner at the start of each phase launches
-        # all candidates); `kernel` is the one the phase itself chose
-        pre, post = KERNELS[key].split("{rho}")
-        names = sorted({k[0].split("(wts::")[0] for k in avg
-                        if k[0].startswith(pre) and k[0].split("(wts::")[0].endswith(post)})
+    for key, pattern in KERNELS.items():
+        phase = "c5" if key.startswith("c5") else key
+        pre, post = pattern.split("{rho}")
         inst = {}
-        for name in names:
-            fk = [avg[k] for k in avg if k[0].split("(wts::")[0] == name and k[1] == "FETCH_SIZE"]
-            wk = [avg[k] for k in avg if k[0].split("(wts::")[0] == name and k[1] == "WRITE_SIZE"]
-            if fk and wk:
-                inst[name] = {"fetch_bytes": fk[0] * f_scale, "write_bytes": wk[0] * w_scale,
-                              "bytes_per_launch": fk[0] * f_scale + wk[0] * w_scale}
+        for (ph, kn, cname), v in avg.items():
+            if ph != phase or not (kn.startswith(pre) and kn.endswith(post)):
+                continue
+            if cname not in ("FETCH_SIZE", "WRITE_SIZE"):
+                continue
+            rec = inst.setdefault(kn, {})
+            rec["fetch_bytes" if cname == "FETCH_SIZE" else "write_bytes"] = v * (
+                f_scale if cname == "FETCH_SIZE" else w_scale)
+        inst = {k: dict(v, bytes_per_launch=v["fetch_bytes"] + v["write_bytes"])
+                for k, v in inst.items() if "fetch_bytes" in v and "write_bytes" in v}
         if inst:
-            out[key] = {"kernel": used.get(key, names[0]), "source_hash": kernel_source_hash(),
-                        "instances": inst}
+            out[key] = {"kernel": used.get(key, sorted(inst)[0]),
+                        "source_hash": kernel_source_hash(), "instances": inst}
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
@@ -160,17 +195,87 @@ def ingest_traffic(root: str):
 
 def guarded(fn, *a, **kw):
     """Runs an optional section; an error is reported in its record instead of
-    ending the run before the JSON line."""
+    ending the run before the JSON line.  Device memory is released after it."""
+    import torch
     try:
         return fn(*a, **kw)
     except Exception as exc:   # noqa: BLE001 -- reported, not hidden
         print("section %s failed: %r" % (fn.__name__, exc), file=sys.stderr)
         return {"error": repr(exc)}
+    finally:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
 
 
-def cpu_baseline(w, n_sample: int = 40):
-    """The FP64 oracle on the first n_sample cycles: all-pairs medoid, one DBA
-    iteration from it and the scores.  Returns the record for the JSON line."""
+# ------------------------------------------------------------ VALU rates
+
+UBENCH_NAMES = ["add_f64", "fma_f64", "exp_log_f32", "add_f32", "cvt_f64_f32", "rcp_f64"]
+
+
+def valu_rates(reps: int = 5):
+    """Issue rates of single VALU instruction kinds (libwts_ubench.so: eight
+    independent chains per lane, 32 resident waves per CU), in lane-ops/s,
+    and tau = add_f64 rate / transcendental rate."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2404_12134_amd", "libwts_ubench.so"))
+    lib.wts_ubench_run.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    blocks, iters = 256 * 8, 4096
+    out = torch.empty(blocks * 256, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    chains = lib.wts_ubench_chains()
+    rates = {}
+    for op, name in enumerate(UBENCH_NAMES):
+        ms = ctypes.c_double(0.0)
+        if lib.wts_ubench_run(op, ctypes.c_void_p(out.data_ptr()), blocks, iters, reps,
+                              ctypes.byref(ms)) != 0:
+            raise RuntimeError("microbenchmark %s failed" % name)
+        lane_ops = blocks * 256 * iters * chains * lib.wts_ubench_ops_per_step(op)
+        rates[name] = {"ms": round(ms.value, 4), "lane_ops_per_s": lane_ops / (ms.value * 1e-3)}
+    tau_meas = rates["add_f64"]["lane_ops_per_s"] / rates["exp_log_f32"]["lane_ops_per_s"]
+    return {"rates": {k: {"ms": v["ms"], "T_lane_ops_per_s": round(v["lane_ops_per_s"] / 1e12, 3),
+                          "frac_of_peak": round(v["lane_ops_per_s"] / VALU_LANE_OPS_PEAK, 3)}
+                      for k, v in rates.items()},
+            "tau_measured": round(tau_meas, 3), "tau": max(1, int(round(tau_meas))),
+            "setup": "%d workgroups x 256 threads, %d steps x %d chains per lane"
+                     % (blocks, iters, chains)}
+
+
+# ------------------------------------------------------------ CPU baselines
+
+def cpu_baseline_c5(w, B, gamma: float, n_sample: int = 16, rows: int = 2048, seed: int = 5):
+    """The FP64 oracle (as it stands) on a bounded sample of the headline
+    workload: n_sample seeded cycles (full length) against the first `rows`
+    rows of the barycenter, one DBA iteration and one Soft-DTW forward +
+    backward (the oracle keeps square-root checkpoints of R), OpenMP across
+    the cycles.  Cells count as in the metric (DBA 1 pass, Soft-DTW 2)."""
+    import numpy as np
+    import oracle
+    r = np.random.Generator(np.random.PCG64(seed))
+    pick = np.sort(r.choice(w.n, size=n_sample, replace=False))
+    cyc = [np.asarray(w.cycles[k], dtype=np.float64) for k in pick]
+    Bs = np.ascontiguousarray(B[:rows])
+    wv = 1.0 / w.lengths[pick].astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.dba_iterate(Bs, cyc)
+    t1 = time.perf_counter()
+    oracle.softdtw_batch(Bs, cyc, gamma, wv)
+    t2 = time.perf_counter()
+    cells = rows * int(sum(c.shape[0] for c in cyc))
+    return {"value": round(3 * cells / (t2 - t0) / 1e9, 4), "unit": "GCUPS",
+            "cores": oracle.num_threads(), "kind": "oracle", "seconds": round(t2 - t0, 3),
+            "dba_gcups": round(cells / (t1 - t0) / 1e9, 4),
+            "soft_fwd_bwd_gcups": round(2 * cells / (t2 - t1) / 1e9, 4),
+            "sample": "%d seeded cycles of the workload (full length) against the first %d "
+                      "barycenter rows: one DBA iteration + one Soft-DTW gamma=%g forward and "
+                      "backward, %d cells per pass, rate extrapolated linearly in cells"
+                      % (n_sample, rows, gamma, cells)}
+
+
+def cpu_baseline_c2(w, n_sample: int = 40):
+    """The FP64 oracle on the first n_sample cycles of the 64-cycle workload:
+    all-pairs medoid, one DBA iteration from it and the scores."""
     import numpy as np
     import oracle
     cyc = [np.asarray(c, dtype=np.float64) for c in w.cycles[:n_sample]]
@@ -184,11 +289,13 @@ def cpu_baseline(w, n_sample: int = 40):
     n = len(cyc)
     cells = int(sum(int(lens[a]) * int(lens[b]) for a in range(n) for b in range(n) if a != b))
     cells += 2 * int(B.shape[0]) * int(lens.sum())
-    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": oracle.num_threads(),
+    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": round(dt, 3),
             "sample": "first %d of %d cycles: all-pairs medoid (both orders, as the oracle "
                       "computes them), 1 DBA iteration, scores; %d cells" % (n, w.n, cells)}
 
+
+# ------------------------------------------------------------ helpers
 
 def band_cells(L: int, lengths, w: float) -> int:
     """Cells inside the Sakoe-Chiba band of every (L x N) pair (the band the
@@ -211,92 +318,215 @@ def band_cells(L: int, lengths, w: float) -> int:
     return tot
 
 
-def soft_section(wts, dev, steps: int = 2, gamma: float = 0.1, band: float = 0.0):
-    """Soft-DTW barycenter gradient steps on the full 128-cycle workload:
-    forward (with checkpoints) + E-matrix backward + preconditioned step;
-    band > 0 restricts them to the Sakoe-Chiba band of Table I (every cell is
-    still swept, those outside the band masked; only cells inside count)."""
+def kname(key: str, rho: int) -> str:
+    return KERNELS[key].format(rho=rho).replace("void ", "")
+
+
+def issued_per_cell():
+    """Issued VALU instructions per cell of each sweep (rocprofv3
+    SQ_INSTS_VALU / cells), from the committed counter summary, if it was
+    taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "valu_issued.json")
+    try:
+        rec = json.load(open(p))
+    except (OSError, ValueError):
+        return {}
+    if rec.get("source_hash") != kernel_source_hash():
+        return {}
+    return rec.get("per_cell", {})
+
+
+def roofline(key: str, rho: int, ops: float, seconds: float, launches: int, cells: float,
+             ops_per_cell: float, name: str = None):
+    """Roofline record of one sweep kernel: `ops` algorithmic lane-ops over
+    `launches` launches taking `seconds` in total (HIP events around each
+    launch, on its stream)."""
+    name = name or kname(key, rho)
+    achieved = ops / seconds / 1e12
+    peak = VALU_LANE_OPS_PEAK / 1e12
+    tr = traffic_from_profiles(key, name)
+    rec = {"bound": "alu", "kernel": name, "achieved": round(achieved, 3),
+           "peak": round(peak, 3), "unit": "TOP/s", "frac": round(achieved / peak, 4),
+           "traffic": None if tr is None else round(tr, 1), "ops_per_cell": ops_per_cell,
+           "cells_per_launch": int(cells / launches),
+           "launch_ms": round(seconds / launches * 1e3, 3)}
+    iss = issued_per_cell().get(key)
+    if iss is not None:
+        rec["issued_valu_per_cell"] = iss
+    return rec
+
+
+# ------------------------------------------------------------ headline
+
+class BarycenterIteration:
+    """One barycenter iteration of the headline: a DBA iteration A -> D, then
+    a Soft-DTW descent step on D (in place), then A <- D.  All buffers are
+    allocated at construction (the DBA workspace and the Soft-DTW checkpoints
+    share one arena: the two halves run one after the other on one stream),
+    so run() allocates nothing and can be captured into a graph."""
+
+    def __init__(self, wts, plan, groups, Y, off, B0, gamma, gv, eta, arena):
+        import torch
+        self.wts, self.plan = wts, plan
+        self.Y = Y
+        self.A = B0.clone()
+        self.D = torch.empty_like(B0)
+        self.counts = torch.empty(plan.L, dtype=torch.int64, device=B0.device)
+        self.dist = torch.empty(plan.n, dtype=torch.float64, device=B0.device)
+        self.soft = wts.SoftDescent(groups, Y, off, plan.L, plan.d, gamma, gv, eta, ckpt=arena)
+        self.ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def run(self, mark: bool = False):
+        wts = self.wts
+        if mark:
+            self.ev[0].record()
+        wts.dba_iterate(self.plan, self.A, self.Y, bary_out=self.D, counts=self.counts,
+                        dist=self.dist)
+        if mark:
+            self.ev[1].record()
+        self.soft.step(self.D)
+        self.A.copy_(self.D)
+        if mark:
+            self.ev[2].record()
+
+    def halves_s(self):
+        return (self.ev[0].elapsed_time(self.ev[1]) / 1e3,
+                self.ev[1].elapsed_time(self.ev[2]) / 1e3)
+
+
+def c5_setup(wts, dev, gamma: float = 0.1, max_group_gib: float = 215.0):
     import numpy as np
     import torch
     from paper_2404_12134_amd import synth
-    w = synth.make(4)
+    w = synth.make(5)
     Y, off, dt = wts.pack_cycles(w.cycles)
-    L = w.L
-    plan = wts.Plan(off, w.d, dt, L, band=band)
-    B, _ = wts.init_barycenter(plan, Y, wts.INIT_EUCLID_MEAN)
+    plan = wts.Plan(off, w.d, dt, w.L)
+    groups = wts.subset_plans(off, w.d, dt, w.L, int(max_group_gib * 2 ** 30))
+    arena_bytes = max(plan.workspace_bytes(wts.OP_DBA), wts.SoftDescent.ckpt_bytes(groups))
+    arena = wts.aligned_buffer(arena_bytes, dev)
+    plan.set_workspace(wts.OP_DBA, arena)
+    B0, _ = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
     gv = torch.from_numpy(1.0 / w.lengths.astype(np.float64)).to(dev)   # Eq. 7: lambda / m
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    tf, tb = [], []
+    it = BarycenterIteration(wts, plan, groups, Y, off, B0, gamma, gv, 0.5, arena)
+    return w, Y, off, dt, plan, groups, arena, it
 
-    def step(record):
-        ev[0].record()
-        val, ck = wts.softdtw_forward(plan, B, Y, gamma)
-        ev[1].record()
-        g, h = wts.softdtw_backward(plan, B, Y, gamma, ck, gv, with_mass=True)
-        ev[2].record()
-        wts.precond_step(B, g, h, 0.5)
-        ev[3].record()
-        if record:
-            torch.cuda.synchronize()
-            tf.append(ev[0].elapsed_time(ev[1]) / 1e3)
-            tb.append(ev[1].elapsed_time(ev[2]) / 1e3)
-        return val
 
-    step(False)
+def c5_kernel_times(wts, it, groups):
+    """One eager iteration with HIP events around every sweep launch (on the
+    launch stream): (DBA path sweep s, [soft fwd s per group], [soft bwd s per
+    group], DBA iteration s, Soft-DTW step s)."""
+    import torch
+    it.plan.enable_timing(4)
+    for _, _, gp in groups:
+        gp.enable_timing(4)
+    it.run(mark=True)
     torch.cuda.synchronize()
+    dba_ms, _ = it.plan.sweep_ms(wts.OP_DBA)
+    fwd = [gp.sweep_ms(wts.OP_SOFT_FWD)[0] / 1e3 for _, _, gp in groups]
+    bwd = [gp.sweep_ms(wts.OP_SOFT_BWD)[0] / 1e3 for _, _, gp in groups]
+    it.plan.enable_timing(0)
+    for _, _, gp in groups:
+        gp.enable_timing(0)
+    t_dba, t_soft = it.halves_s()
+    return dba_ms / 1e3, fwd, bwd, t_dba, t_soft
+
+
+def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.1,
+                speedup: bool = True, cpu: bool = True):
+    import torch
+    w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, gamma)
+    L, d = w.L, w.d
+    cells = L * int(w.lengths.sum())
+    # capture the whole iteration once (every allocation was made above)
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        it.run()
+    torch.cuda.current_stream(dev).wait_stream(s)
+    torch.cuda.synchronize()
+
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()      # one GPU: the barrier of the multi-rank contract is a no-op
     t0 = time.perf_counter()
     for _ in range(steps):
-        step(True)
+        graph.replay()
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / steps
-    for op in (wts.OP_SOFT_BWD,):
-        st = wts.device_status(plan, op)
-        if st != 0:
-            raise RuntimeError("device status %d after the Soft-DTW backward" % st)
-    cells = band_cells(L, w.lengths, band)
-    counted = 2 * cells
-    gcups = counted / sec / 1e9
-    cm = c_min_soft(w.d)
-    frac = gcups * 1e9 * cm / VALU_LANE_OPS_PEAK
-    rec = {"workload": w.name + ": Soft-DTW gamma=%g, forward + backward + preconditioned "
-                                "step (eta 0.5), weights 1/m_k%s"
-                                % (gamma, ", Sakoe-Chiba band %g" % band if band else ""),
-           "gcups_fwd_bwd": round(gcups, 2), "s_per_gradient_step": round(sec, 4),
-           "forward_ms": round(1e3 * float(np.mean(tf)), 2),
-           "backward_ms": round(1e3 * float(np.mean(tb)), 2),
-           "cells_per_pass": cells, "ops_per_cell": cm, "alu_frac": round(frac, 4)}
-    if band == 0.0:
-        # the gradient with respect to the cycles: one more forward and
-        # backward over the same cells, with the cycles on the rows
-        Y64 = Y.to(torch.float64)
-        wts.softdtw_grad_cycles(plan, B, Y64, gamma, gv)
-        torch.cuda.synchronize()
-        ev[0].record()
-        for _ in range(steps):
-            wts.softdtw_grad_cycles(plan, B, Y64, gamma, gv)
-        ev[1].record()
-        torch.cuda.synchronize()
-        if wts.device_status(plan, wts.OP_SOFT_GRAD_C) != 0:
-            raise RuntimeError("device status after the cycles gradient")
-        tg = ev[0].elapsed_time(ev[1]) / 1e3 / steps
-        gg = 2 * cells / tg / 1e9
-        rec["grad_cycles"] = {"ms": round(1e3 * tg, 2), "gcups_fwd_bwd": round(gg, 2),
-                              "alu_frac": round(gg * 1e9 * cm / VALU_LANE_OPS_PEAK, 4)}
-        # Table I's optimizer, bounded to 3 iterations / 8 evaluations: the
-        # host L-BFGS share is the wall time beyond the evaluations' sweeps.
-        # A first run loads the optimizer's own torch kernels (once per process).
-        wts.lbfgs_barycenter(plan, Y, B, gamma, gv, max_iter=3, max_eval=8)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, hist = wts.lbfgs_barycenter(plan, Y, B, gamma, gv, max_iter=3, max_eval=8)
-        torch.cuda.synchronize()
-        tl = time.perf_counter() - t0
-        rec["lbfgs"] = {"iterations_max": 3, "evaluations": len(hist),
-                        "s_per_evaluation": round(tl / len(hist), 4),
-                        "objective_first_last": [round(hist[0], 6), round(hist[-1], 6)],
-                        "sweep_share": round(len(hist) * sec / tl, 3)}
+    t1 = time.perf_counter()
+    plan.check()
+    for _, _, gp in groups:
+        gp.check()
+    sec = (t1 - t0) / steps
+    counted = 3 * cells
+    value = counted / sec / 1e9
+
+    # per-kernel launch times: one eager iteration with HIP events per sweep
+    dba_s, fwd, bwd, t_dba, t_soft = c5_kernel_times(wts, it, groups)
+    plan.check()
+    kern = {   # name: (seconds per step, launches, cells, floor, KERNELS key, rho)
+        "dba_path_sweep": (dba_s, 1, cells, c_dba(d), "c5_dba", plan.rho(wts.OP_DBA)),
+        "soft_fwd": (sum(fwd), len(groups), cells, c_soft_fwd(d, tau), "c5_soft_fwd", 2),
+        "soft_bwd": (sum(bwd), len(groups), cells, c_soft_bwd(d, tau), "c5_soft_bwd", 2),
+    }
+    dom = max(kern, key=lambda k: kern[k][0])
+    ksec, kl, kcells, kc, kkey, krho = kern[dom]
+    roof = roofline(kkey, krho, kcells * kc, ksec, kl, kcells, kc)
+    roof["per_kernel_ms_per_step"] = {k: round(v[0] * 1e3, 2) for k, v in kern.items()}
+    roof["per_kernel_alu_frac"] = {k: round(v[2] * v[3] / v[0] / VALU_LANE_OPS_PEAK, 4)
+                                   for k, v in kern.items()}
+    issued = issued_per_cell()
+    roof["per_kernel_issued_valu_per_cell"] = {k: issued.get(v[4]) for k, v in kern.items()}
+    roof["ops_per_cell_floors"] = {k: v[3] for k, v in kern.items()}
+    roof["step_alu_frac"] = round(sum(v[2] * v[3] for v in kern.values()) / sec /
+                                  VALU_LANE_OPS_PEAK, 4)
+    roof["soft_group_launch_ms"] = {"fwd": [round(x * 1e3, 2) for x in fwd],
+                                    "bwd": [round(x * 1e3, 2) for x in bwd]}
+
+    # the anomaly scores of all cycles (after the iterations)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wts.anomaly_score(plan, it.A, Y)
+    torch.cuda.synchronize()
+    e0.record()
+    wts.anomaly_score(plan, it.A, Y)
+    e1.record()
+    torch.cuda.synchronize()
+    plan.check()
+    t_score = e0.elapsed_time(e1) / 1e3
+    speed = None
+    if speedup:
+        speed = dba_per_cycle_speedup(wts, plan, off, d, dt, L, Y, it.A, sequential=True)
+    Bhost = it.A.cpu().numpy()
+    rec = {
+        "value": round(value, 3), "ms_per_step": round(sec * 1e3, 3),
+        "config": {"workload": w.name + ": one barycenter iteration per step = 1 DBA iteration "
+                                        "+ 1 Soft-DTW gamma=%g descent step (forward + backward "
+                                        "over %d checkpoint groups, eta 0.5, weights 1/m_k), the "
+                                        "whole step one captured hipGraph" % (gamma, len(groups)),
+                   "n": w.n, "d": d, "L": L, "cells_per_pass": cells,
+                   "counted_cells_per_step": counted, "soft_groups": len(groups),
+                   "arena_gib": round(arena.numel() / 2 ** 30, 1)},
+        "s_per_iteration": round(sec, 4),
+        "halves_s": {"dba_iteration": round(t_dba, 4), "soft_step": round(t_soft, 4)},
+        "phase_gcups": {"dba": round(cells / t_dba / 1e9, 2),
+                        "soft_fwd_bwd": round(2 * cells / t_soft / 1e9, 2)},
+        "score_s": round(t_score, 4),
+        "workload_s": round(w.dba_iters * t_dba + 10 * t_soft + t_score, 2),
+        "roofline": roof,
+        "batched_vs_per_cycle": speed,
+    }
+    del graph, it, arena
+    for _, _, gp in groups:
+        gp.close()
+    plan.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if cpu:
+        rec["cpu_baseline"] = cpu_baseline_c5(w, Bhost, gamma)
     return rec
 
+
+# ------------------------------------------------------------ extra sections
 
 def dba_per_cycle_speedup(wts, plan, off, d, dt, L, Y, B, sequential=False):
     """Batched vs one-cycle-per-launch DBA iteration: the same kernels, run
@@ -344,17 +574,120 @@ def dba_per_cycle_speedup(wts, plan, off, d, dt, L, Y, B, sequential=False):
         per = e0.elapsed_time(e1) / 1e3
         for one in single:
             one.close()
+    plan.check()
     return {"op": "dba_iterate", "one_cycle_per_launch_s": round(per, 5),
             "batched_s": round(batched, 5), "speedup": round(per / batched, 2),
             "per_cycle_timing": "sum of per-launch events" if sequential else "back to back"}
 
 
-def dba_large_section(wts, dev, iters: int = 10, speedup: bool = True):
-    """DBA on the 512-cycle workload (6 channels, lengths log-uniform
-    1000..20000, L = 10000, nearest-length init): `iters` iterations replayed
-    from a captured hipGraph (two iterations per graph), plus the path
-    sweep's own launch time measured eagerly for its ALU fraction."""
+def c2_section(wts, dev, steps: int = 3, speedup: bool = True):
+    """64 x 3 ch, 4000..6000 (3 cycles with an injected drift): medoid
+    initialisation (all 2016 pairs), 10 DBA iterations from the medoid, the
+    anomaly scores, and detection of the drifted cycles (Sec. V-C
+    thresholds)."""
     import numpy as np
+    import torch
+    from paper_2404_12134_amd import autotune, detect, synth
+    w = synth.make(2)
+    lens = w.lengths
+    Y, off, dt = wts.pack_cycles(w.cycles)
+    mplan, mtuned = autotune.tuned_plan(off, w.d, dt, 0, op="medoid", cycles=Y, cache_path=None)
+    k0 = int(wts.medoid(mplan, Y, with_matrix=False)[0].item())
+    L = int(lens[k0])
+    B0, _ = wts.init_barycenter(wts.Plan(off, w.d, dt, L), Y, wts.INIT_COPY, k0)
+    plan, tuned = autotune.tuned_plan(off, w.d, dt, L, op="dba", cycles=Y, bary=B0,
+                                      cache_path=None)
+    n = w.n
+    Ba = torch.empty((L, w.d), dtype=torch.float64, device=dev)
+    Bb = torch.empty_like(Ba)
+    counts = torch.empty(L, dtype=torch.int64, device=dev)
+    dist = torch.empty(n, dtype=torch.float64, device=dev)
+    cells_medoid = int(sum(int(lens[a]) * int(lens[b]) for a in range(n) for b in range(a + 1, n)))
+    cells_bary = L * int(lens.sum())
+    iters = w.dba_iters
+    cells_step = cells_medoid + iters * cells_bary + cells_bary
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in ("medoid", "dba", "score")}
+    times = {k: [] for k in ev}
+
+    def step(record: bool):
+        e = ev["medoid"]
+        e[0].record()
+        kk, _, _ = wts.medoid(mplan, Y, with_matrix=False)
+        e[1].record()
+        Bi, _ = wts.init_barycenter(plan, Y, wts.INIT_COPY, k0)
+        Ba.copy_(Bi)
+        src, dst = Ba, Bb
+        ev["dba"][0].record()
+        for _ in range(iters):
+            wts.dba_iterate(plan, src, Y, bary_out=dst, counts=counts, dist=dist)
+            src, dst = dst, src
+        ev["dba"][1].record()
+        ev["score"][0].record()
+        out = wts.anomaly_score(plan, src, Y)
+        ev["score"][1].record()
+        if record:
+            torch.cuda.synchronize()
+            if int(kk.item()) != k0:
+                raise RuntimeError("medoid changed between steps")
+            for key, (a, b) in ev.items():
+                times[key].append(a.elapsed_time(b) / 1e3)
+        return out
+
+    step(False)
+    torch.cuda.synchronize()
+    mplan.enable_timing(4 * steps)
+    plan.enable_timing(16 * steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        last = step(True)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    mplan.check()
+    plan.check()
+    t_med = float(np.mean(times["medoid"]))
+    t_dba = float(np.mean(times["dba"])) / iters
+    t_score = float(np.mean(times["score"]))
+    sweeps = {"medoid": (mplan, wts.OP_MEDOID, cells_medoid, c_medoid(w.d)),
+              "dba": (plan, wts.OP_DBA, cells_bary, c_dba(w.d)),
+              "score": (plan, wts.OP_SCORE, cells_bary, c_score(w.d))}
+    per = {}
+    for key, (pl, op, cells, cm) in sweeps.items():
+        tot, cnt = pl.sweep_ms(op)
+        per[key] = roofline(key, pl.rho(op), cells * cm * cnt, tot / 1e3, cnt, cells * cnt, cm)
+        per[key]["ms_per_step"] = round(tot / steps, 3)
+    mplan.enable_timing(0)
+    plan.enable_timing(0)
+    sc = last[0].cpu().numpy()
+    truth = np.zeros(n, dtype=bool)
+    truth[w.meta["drift"]] = True
+    detection = {"drifted_cycles": [int(i) for i in w.meta["drift"]],
+                 "top_scores": [int(i) for i in np.argsort(-sc)[:len(w.meta["drift"])]]}
+    for name, thr in (("two_sigma", detect.two_sigma_threshold(sc)),
+                      ("boxplot", detect.boxplot_threshold(sc))):
+        tp, fn, fp, tn = detect.confusion(detect.flag(sc, thr), truth)
+        detection[name] = {"threshold": round(thr, 6), "tp": tp, "fn": fn, "fp": fp, "tn": tn,
+                           "f2": round(detect.f_beta(tp, fn, fp), 3)}
+    speed = dba_per_cycle_speedup(wts, plan, off, w.d, dt, L, Y, Ba) if speedup else None
+    return {"workload": w.name + ": medoid init + %d DBA iterations + anomaly scores" % iters,
+            "n": n, "d": w.d, "L": L, "cells_per_step": cells_step,
+            "gcups": round(cells_step / sec / 1e9, 2), "ms_per_step": round(sec * 1e3, 3),
+            "s_per_dba_iteration": round(t_dba, 6),
+            "phase_gcups": {"medoid": round(cells_medoid / t_med / 1e9, 2),
+                            "dba_iteration": round(cells_bary / t_dba / 1e9, 2),
+                            "score": round(cells_bary / t_score / 1e9, 2)},
+            "sweeps": per,
+            "autotune": {"dba": {"rows_per_lane": tuned["rho"], "grid": tuned["grid"],
+                                 "candidates_ms": tuned["table"]},
+                         "medoid": {"rows_per_lane": mtuned["rho"], "grid": mtuned["grid"],
+                                    "candidates_ms": mtuned["table"]}},
+            "batched_vs_per_cycle": speed, "detection": detection}
+
+
+def c3_section(wts, dev, iters: int = 10, speedup: bool = True):
+    """512 x 6 ch, lengths log-uniform 1000..20000, L = 10000, nearest-length
+    init: `iters` DBA iterations replayed from a captured hipGraph (two
+    iterations per graph), plus the path sweep's own launch time."""
     import torch
     from paper_2404_12134_amd import synth
     w = synth.make(3)
@@ -370,125 +703,173 @@ def dba_large_section(wts, dev, iters: int = 10, speedup: bool = True):
     for _ in range(3):
         wts.dba_iterate(plan, B0, Y)
     tot, cnt = plan.sweep_ms(wts.OP_DBA)
-    sweep_s = tot / max(cnt, 1) / 1e3
     plan.enable_timing(0)
-    st = wts.device_status(plan, wts.OP_DBA)
-    if st != 0:
-        raise RuntimeError("device status %d after the large DBA" % st)
+    plan.check()
     runner = wts.DBARunner(plan, Y, B0, graph=True)
     runner.run(2)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    runner.run(iters)
+    runner.run(iters, check=False)
     e1.record()
     torch.cuda.synchronize()
+    plan.check()
     it_s = e0.elapsed_time(e1) / 1e3 / iters
     del runner
     speed = dba_per_cycle_speedup(wts, plan, off, w.d, dt, w.L, Y, B0) if speedup else None
-    cm = c_min_path(w.d)
+    cm = c_dba(w.d)
+    rho = plan.rho(wts.OP_DBA)
+    rf = roofline("c5_dba", rho, cells * cm * cnt, tot / 1e3, cnt, cells * cnt, cm)
+    rf["traffic"] = None          # the committed counters are those of the headline workload
+    rf.pop("issued_valu_per_cell", None)
     return {"workload": w.name + ": %d DBA iterations replayed from a hipGraph, nearest-length "
                                  "init" % iters,
             "s_per_dba_iteration": round(it_s, 5), "gcups": round(cells / it_s / 1e9, 2),
-            "cells_per_iteration": cells, "rows_per_lane": plan.rho(wts.OP_DBA),
-            "path_sweep_ms": round(sweep_s * 1e3, 3), "ops_per_cell": cm,
-            "path_sweep_alu_frac": round(cells * cm / sweep_s / VALU_LANE_OPS_PEAK, 4),
-            "batched_vs_per_cycle": speed}
+            "cells_per_iteration": cells, "rows_per_lane": rho,
+            "path_sweep": rf, "batched_vs_per_cycle": speed}
 
 
-def irregular_section(wts, dev, dba_iters: int = 10, soft_steps: int = 10, gamma: float = 0.1,
-                      max_ckpt_gib: float = 96.0, speedup: bool = True):
-    """The 256-cycle workload (6 channels, lengths 40000..50000 with 1 % of the
-    samples dropped in gaps, L = max N): nearest-length init, `dba_iters` DBA
-    iterations replayed from a hipGraph, then `soft_steps` preconditioned
-    Soft-DTW (gamma) descent steps over checkpoint-bounded cycle groups, then
-    the anomaly scores of all cycles.  Each phase is timed on its own."""
+def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
+    """128 x 6 ch, 18000..22000, L = 20000, Euclidean-mean init (Table I):
+    for gamma in (0.1, 1): `steps` preconditioned Soft-DTW descent steps
+    (eta 0.5, Eq. 7 weights 1/m_k) with the objective trajectory, and at
+    step 0 a directional finite-difference check of the GPU gradient on the
+    whole batch; the forward and backward launch times and their roofline;
+    the gradient with respect to the cycles; the Table I band (0.6); and
+    Table I's L-BFGS (gamma 1, 40 iterations, 200 evaluations at most)."""
     import numpy as np
     import torch
     from paper_2404_12134_amd import synth
-    w = synth.make(5)
+    w = synth.make(4)
     Y, off, dt = wts.pack_cycles(w.cycles)
-    L = w.L
-    cells = L * int(w.lengths.sum())
-    plan = wts.Plan(off, w.d, dt, L)
-    B0, _ = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
-    plan.enable_timing(4)
-    wts.dba_iterate(plan, B0, Y)
-    torch.cuda.synchronize()
-    plan.sweep_ms(wts.OP_DBA)
-    wts.dba_iterate(plan, B0, Y)
-    tot, cnt = plan.sweep_ms(wts.OP_DBA)
-    sweep_s = tot / max(cnt, 1) / 1e3
-    plan.enable_timing(0)
-    st = wts.device_status(plan, wts.OP_DBA)
-    if st != 0:
-        raise RuntimeError("device status %d after the DBA iteration" % st)
-    dba_ws_gib = plan.workspace_bytes(wts.OP_DBA) / 2 ** 30
-    speed = dba_per_cycle_speedup(wts, plan, off, w.d, dt, L, Y, B0, sequential=True) \
-        if speedup else None
-    runner = wts.DBARunner(plan, Y, B0, graph=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    B = runner.run(dba_iters).clone()
-    torch.cuda.synchronize()
-    t_dba = (time.perf_counter() - t0) / dba_iters
-    del runner
-    plan.close()
-    torch.cuda.empty_cache()
-
-    groups = wts.subset_plans(off, w.d, dt, L, int(max_ckpt_gib * 2 ** 30))
+    L, d = w.L, w.d
+    plan = wts.Plan(off, d, dt, L)
+    B0, _ = wts.init_barycenter(plan, Y, wts.INIT_EUCLID_MEAN)
     gv = torch.from_numpy(1.0 / w.lengths.astype(np.float64)).to(dev)   # Eq. 7: lambda / m
-    t_soft = []
-    for _ in range(soft_steps):
+    cells = L * int(w.lengths.sum())
+    cf, cb = c_soft_fwd(d, tau), c_soft_bwd(d, tau)
+    rec = {"workload": w.name + ": Soft-DTW barycenter, Euclidean-mean init, weights 1/m_k",
+           "cells_per_pass": cells, "ops_per_cell": {"fwd": cf, "bwd": cb}}
+    groups = [(0, w.n, plan)]
+    for gamma in (0.1, 1.0):
+        sd = wts.SoftDescent(groups, Y, off, L, d, gamma, gv, 0.5)
+        B = B0.clone()
+        # directional finite differences at step 0 on the whole batch:
+        # (f(B + hV) - f(B - hV)) / 2h against <G, V> for V = G / |G| and a
+        # seeded random unit direction; h moves f by about 1e-5 of itself
+        v0, ck = wts.softdtw_forward(plan, B, Y, gamma)
+        G = wts.softdtw_backward(plan, B, Y, gamma, ck, gv)
+        del ck
+        f0 = wts.barycenter_objective(v0, gv).item()
+        g = G.cpu().numpy()
+        r = np.random.Generator(np.random.PCG64(11))
+        fd = {}
+        for name, V in (("gradient_direction", g), ("random_direction",
+                                                    r.standard_normal(g.shape))):
+            V = V / np.linalg.norm(V)
+            dd = float(np.sum(g * V))
+            h = 1e-5 * abs(f0) / max(abs(dd), 1e-30)
+            Vt = torch.from_numpy(V).to(dev)
+            fp = wts.barycenter_objective(wts.softdtw_forward(plan, B + h * Vt, Y, gamma)[0],
+                                          gv).item()
+            fm = wts.barycenter_objective(wts.softdtw_forward(plan, B - h * Vt, Y, gamma)[0],
+                                          gv).item()
+            est = (fp - fm) / (2 * h)
+            fd[name] = {"h": h, "directional_derivative": dd, "finite_difference": est,
+                        "rel_err": abs(est - dd) / abs(dd)}
+        plan.check()
+        traj = torch.empty(steps, dtype=torch.float64, device=dev)
+        sd.step(B)
+        torch.cuda.synchronize()
+        B.copy_(B0)
+        plan.enable_timing(2 * steps)
+        t0 = time.perf_counter()
+        for s in range(steps):
+            sd.step(B)
+            traj[s:s + 1].copy_(sd.objective)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        tf, nf = plan.sweep_ms(wts.OP_SOFT_FWD)
+        tb, nb = plan.sweep_ms(wts.OP_SOFT_BWD)
+        plan.enable_timing(0)
+        plan.check()
+        tr = traj.cpu().numpy()
+        fwd = roofline("c5_soft_fwd", 2, cells * cf * nf, tf / 1e3, nf, cells * nf, cf)
+        bwd = roofline("c5_soft_bwd", 2, cells * cb * nb, tb / 1e3, nb, cells * nb, cb)
+        for rf in (fwd, bwd):
+            rf["traffic"] = None   # the committed counters are those of the headline workload
+            rf.pop("issued_valu_per_cell", None)
+        pair_s = (tf / nf + tb / nb) / 1e3
+        rec["gamma_%g" % gamma] = {
+            "steps": steps, "s_per_step": round(sec, 4),
+            "gcups_fwd_bwd": round(2 * cells / sec / 1e9, 2),
+            "objective_trajectory": {"step_%d" % k: round(float(tr[k]), 8)
+                                     for k in sorted({0, 1, 9, 19, 29, 39, steps - 1})
+                                     if k < steps},
+            "objective_non_increasing": bool(np.all(np.diff(tr) <= 1e-12 * np.abs(tr[:-1]))),
+            "fd_check_step0": fd,
+            "forward": fwd, "backward": bwd,
+            "alu_frac_fwd_bwd": round(cells * (cf + cb) / pair_s / VALU_LANE_OPS_PEAK, 4),
+        }
+        del sd
+    # the gradient with respect to the cycles (gamma 0.1)
+    Y64 = Y.to(torch.float64)
+    wts.softdtw_grad_cycles(plan, B0, Y64, 0.1, gv)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    wts.softdtw_grad_cycles(plan, B0, Y64, 0.1, gv)
+    e1.record()
+    torch.cuda.synchronize()
+    plan.check()
+    tg = e0.elapsed_time(e1) / 1e3
+    rec["grad_cycles"] = {"ms": round(1e3 * tg, 2),
+                          "gcups_fwd_bwd": round(2 * cells / tg / 1e9, 2)}
+    del Y64
+    # the Table I band (0.6), gamma 0.1
+    bplan = wts.Plan(off, d, dt, L, band=0.6)
+    bcells = band_cells(L, w.lengths, 0.6)
+    sdb = wts.SoftDescent([(0, w.n, bplan)], Y, off, L, d, 0.1, gv, 0.5)
+    B = B0.clone()
+    sdb.step(B)
+    torch.cuda.synchronize()
+    bplan.enable_timing(8)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        sdb.step(B)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / 3
+    tf, nf = bplan.sweep_ms(wts.OP_SOFT_FWD)
+    tb, nb = bplan.sweep_ms(wts.OP_SOFT_BWD)
+    bplan.enable_timing(0)
+    bplan.check()
+    rec["band_0.6"] = {"cells_in_band_per_pass": bcells,
+                       "band_fraction": round(bcells / cells, 4), "s_per_step": round(sec, 4),
+                       "gcups_fwd_bwd_in_band": round(2 * bcells / sec / 1e9, 2),
+                       "forward_ms": round(tf / nf, 2), "backward_ms": round(tb / nb, 2)}
+    del sdb
+    bplan.close()
+    if lbfgs:
+        # Table I: gamma 1, L-BFGS, max_iter 40, max_fun 200, gtol 1e-8, tol 1e-5
+        wts.lbfgs_barycenter(plan, Y, B0, 1.0, gv, max_iter=1, max_eval=2)   # loads torch kernels
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        wts.softdtw_descent_step(groups, Y, off, B, gamma, gv, 0.5)
+        _, hist = wts.lbfgs_barycenter(plan, Y, B0, 1.0, gv, max_iter=40, max_eval=200)
         torch.cuda.synchronize()
-        t_soft.append(time.perf_counter() - t0)
-    for a, b, gp in groups:
-        st = wts.device_status(gp, wts.OP_SOFT_BWD)
-        if st != 0:
-            raise RuntimeError("device status %d after the Soft-DTW backward" % st)
-        gp.close()
-    torch.cuda.empty_cache()
-
-    splan = wts.Plan(off, w.d, dt, L)
-    wts.anomaly_score(splan, B, Y)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    wts.anomaly_score(splan, B, Y)
-    torch.cuda.synchronize()
-    t_score = time.perf_counter() - t0
-    splan.close()
-    torch.cuda.empty_cache()
-    s_soft = float(np.median(t_soft))
-    cm = c_min_path(w.d)
-    return {"workload": w.name + ": nearest-length init, %d DBA iterations (hipGraph), %d "
-                                 "Soft-DTW gamma=%g descent steps in %d checkpoint groups, "
-                                 "scores" % (dba_iters, soft_steps, gamma, len(groups)),
-            "cells_per_pass": cells,
-            "s_per_dba_iteration": round(t_dba, 4), "dba_gcups": round(cells / t_dba / 1e9, 2),
-            "path_sweep_ms": round(sweep_s * 1e3, 2), "ops_per_cell": cm,
-            "path_sweep_alu_frac": round(cells * cm / sweep_s / VALU_LANE_OPS_PEAK, 4),
-            "dba_workspace_gib": round(dba_ws_gib, 1),
-            "s_per_soft_step": round(s_soft, 3),
-            "soft_gcups_fwd_bwd": round(2 * cells / s_soft / 1e9, 2),
-            "soft_alu_frac": round(2 * cells * c_min_soft(w.d) / s_soft / VALU_LANE_OPS_PEAK, 4),
-            "score_s": round(t_score, 4),
-            "workload_s": round(dba_iters * t_dba + float(np.sum(t_soft)) + t_score, 2),
-            "batched_vs_per_cycle": speed}
-
-
-def c_min_sub(d: int) -> int:
-    """Sub-DTW sweep: the value recursion (2d + 3), two compares and two
-    selects of the carried start column."""
-    return 2 * d + 7
+        tl = time.perf_counter() - t0
+        s_step = rec["gamma_1"]["s_per_step"]
+        rec["lbfgs_table1"] = {"gamma": 1.0, "max_iter": 40, "max_eval": 200,
+                               "evaluations": len(hist), "seconds": round(tl, 2),
+                               "s_per_evaluation": round(tl / len(hist), 4),
+                               "objective_first_last": [round(hist[0], 8), round(hist[-1], 8)],
+                               "sweep_share": round(min(1.0, len(hist) * s_step / tl), 3)}
+    plan.close()
+    return rec
 
 
 def segmentation_section(wts, dev, n_streams: int = 16, n_cycles: int = 37,
                          speedup: bool = True):
-    """The segmentation step (Sec. III-A) at the scale the paper reports for
-    its robot (Sec. IV-B: a reference cycle of about 16,300 samples, streams
+    """The segmentation step (Sec. III-B) at the scale the paper reports for
+    its robot (Sec. V-A: a reference cycle of about 16,300 samples, streams
     of about 6e5 samples): a reference of 15,500..16,500 samples, 3 channels,
     float32 streams of `n_cycles` cycles each.  `n_streams` streams are
     segmented together (one Sub-DTW launch per round over their windows),
@@ -524,11 +905,12 @@ def segmentation_section(wts, dev, n_streams: int = 16, n_cycles: int = 37,
     rounds = max(len(sg) for sg in segs)
     rec = {"workload": "segmentation: %d streams x %d cycles (3 ch f32, %d..%d samples per "
                        "cycle, ~%d samples per stream), reference of %d samples"
-                       % (n_streams, n_cycles, lr[0], lr[1], int(np.mean([Y.shape[0] for Y in streams])), M),
+                       % (n_streams, n_cycles, lr[0], lr[1],
+                          int(np.mean([Y.shape[0] for Y in streams])), M),
            "segments_per_stream": [len(sg) for sg in segs][:4], "rounds": rounds,
            "cells": cells, "batched_s": round(t_batch, 4),
-           "gcups": round(cells / t_batch / 1e9, 2), "ops_per_cell": c_min_sub(3),
-           "loop_alu_frac": round(cells * c_min_sub(3) / t_batch / VALU_LANE_OPS_PEAK, 4)}
+           "gcups": round(cells / t_batch / 1e9, 2), "ops_per_cell": c_sub(3),
+           "loop_alu_frac": round(cells * c_sub(3) / t_batch / VALU_LANE_OPS_PEAK, 4)}
     if speedup:
         t0 = time.perf_counter()
         one = [wts.segment(Xt, [y], "f32")[0] for y in St]
@@ -542,10 +924,12 @@ def segmentation_section(wts, dev, n_streams: int = 16, n_cycles: int = 37,
     return rec
 
 
+# ------------------------------------------------------------ profiling phases
+
 def only_phase(args, wts, dev):
-    """One phase of the step, --steps times, for rocprofv3 counter passes.  The
-    'copy' phase is a plain 1 GiB device-to-device copy: the reference for
-    scaling FETCH_SIZE / WRITE_SIZE to bytes."""
+    """One phase, --steps times, for rocprofv3 passes.  'copy' is a plain
+    1 GiB device-to-device copy: the reference for scaling FETCH_SIZE /
+    WRITE_SIZE to bytes.  'c5' runs the headline iteration eagerly."""
     import torch
     from paper_2404_12134_amd import synth
     if args.only == "copy":
@@ -554,25 +938,39 @@ def only_phase(args, wts, dev):
         for _ in range(args.steps):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"phase": "copy", "bytes_read": a.numel() * 8, "bytes_written": b.numel() * 8,
-                          "source_hash": kernel_source_hash()}))
+        print(json.dumps({"phase": "copy", "bytes_read": a.numel() * 8,
+                          "bytes_written": b.numel() * 8, "source_hash": kernel_source_hash()}))
         return
-    if args.only in ("large", "irregular", "segment"):
-        fn = {"large": dba_large_section, "irregular": irregular_section,
-              "segment": segmentation_section}[args.only]
-        rec = fn(wts, dev, speedup=not args.no_speedup)
+    if args.only == "valu":
+        print(json.dumps({"phase": "valu", "source_hash": kernel_source_hash(),
+                          "valu": valu_rates()}))
+        return
+    if args.only == "c5":
+        w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev)
+        for _ in range(args.steps):
+            it.run()
+        torch.cuda.synchronize()
+        plan.check()
+        print(json.dumps({"phase": "c5", "source_hash": kernel_source_hash(),
+                          "kernels": {"c5_dba": KERNELS["c5_dba"].format(rho=plan.rho(wts.OP_DBA)),
+                                      "c5_soft_fwd": KERNELS["c5_soft_fwd"].format(rho=2),
+                                      "c5_soft_bwd": KERNELS["c5_soft_bwd"].format(rho=2)},
+                          "cells_per_pass": w.L * int(w.lengths.sum()),
+                          "soft_groups": [[a, b] for a, b, _ in groups]}))
+        return
+    if args.only in ("c3", "segment"):
+        fn = {"c3": c3_section, "segment": segmentation_section}[args.only]
+        rec = fn(wts, dev, speedup=False)
         print(json.dumps({"phase": args.only, "source_hash": kernel_source_hash(),
                           args.only: rec}))
         return
-    if args.only == "soft":
-        rec = soft_section(wts, dev, args.steps)
-        torch.cuda.synchronize()
-        print(json.dumps({"phase": "soft", "source_hash": kernel_source_hash(), "soft_dtw": rec}))
+    if args.only == "c4":
+        rec = c4_section(wts, dev, 2.0, steps=args.steps, lbfgs=False)
+        print(json.dumps({"phase": "c4", "source_hash": kernel_source_hash(), "c4": rec}))
         return
     from paper_2404_12134_amd import autotune
     w = synth.make(2)
     Y, off, dt = wts.pack_cycles(w.cycles)
-    # the same tuned sweep shapes as the full bench
     mplan, _ = autotune.tuned_plan(off, w.d, dt, 0, op="medoid", cycles=Y, cache_path=None)
     k0 = int(wts.medoid(mplan, Y, with_matrix=False)[0].item())
     L = int(w.lengths[k0])
@@ -592,7 +990,7 @@ def only_phase(args, wts, dev):
     used = {"medoid": mplan.rho(wts.OP_MEDOID), "dba": plan.rho(wts.OP_DBA),
             "score": plan.rho(wts.OP_SCORE)}[args.only]
     print(json.dumps({"phase": args.only, "L": L, "source_hash": kernel_source_hash(),
-                      "kernel": KERNELS[args.only].format(rho=used)}))
+                      "kernels": {args.only: KERNELS[args.only].format(rho=used)}}))
 
 
 def main():
@@ -602,17 +1000,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-speedup", action="store_true",
-                    help="skip the batched vs one-cycle-per-launch comparison")
-    ap.add_argument("--no-soft", action="store_true", help="skip the Soft-DTW section")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 512-cycle DBA section")
-    ap.add_argument("--no-irregular", action="store_true",
-                    help="skip the 256-cycle 40k..50k section (DBA, Soft-DTW, scores)")
-    ap.add_argument("--no-segment", action="store_true",
-                    help="skip the Sub-DTW segmentation section")
-    ap.add_argument("--soft-steps", type=int, default=2)
-    ap.add_argument("--only", choices=["medoid", "dba", "score", "soft", "copy", "large",
-                                       "irregular", "segment"],
+                    help="skip the batched vs one-cycle-per-launch comparisons")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline (no 64-, 512- and 128-cycle or segmentation sections)")
+    ap.add_argument("--soft-steps", type=int, default=50,
+                    help="Soft-DTW descent steps per gamma in the 128-cycle section")
+    ap.add_argument("--only", choices=["medoid", "dba", "score", "copy", "valu", "c5", "c3", "c4",
+                                       "segment"],
                     help="run only one phase --steps times (for hardware-counter passes)")
     ap.add_argument("--traffic-from", metavar="DIR",
                     help="write profiles/traffic.json from rocprofv3 FETCH/WRITE_SIZE passes")
@@ -625,9 +1019,7 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2404_12134_amd import synth
     from paper_2404_12134_amd import wetsand as wts
 
     wts.load()
@@ -635,171 +1027,40 @@ def main():
     if args.only:
         only_phase(args, wts, dev)
         return
-    w = synth.make(2)
-    lens = w.lengths
-    Y, off, dt = wts.pack_cycles(w.cycles)
-    # sweep shapes of the medoid and barycenter plans: picked by timing the
-    # candidates on this batch (outside the timed region)
-    from paper_2404_12134_amd import autotune
-    mplan, mtuned = autotune.tuned_plan(off, w.d, dt, 0, op="medoid", cycles=Y, cache_path=None)
-    k0 = int(wts.medoid(mplan, Y, with_matrix=False)[0].item())
-    L = int(lens[k0])
-    B0, _ = wts.init_barycenter(wts.Plan(off, w.d, dt, L), Y, wts.INIT_COPY, k0)
-    plan, tuned = autotune.tuned_plan(off, w.d, dt, L, op="dba", cycles=Y, bary=B0,
-                                      cache_path=None)
-    n = w.n
-    Ba = torch.empty((L, w.d), dtype=torch.float64, device=dev)
-    Bb = torch.empty_like(Ba)
-    counts = torch.empty(L, dtype=torch.int64, device=dev)
-    dist = torch.empty(n, dtype=torch.float64, device=dev)
-
-    cells_medoid = int(sum(int(lens[a]) * int(lens[b]) for a in range(n) for b in range(a + 1, n)))
-    cells_bary = L * int(lens.sum())
-    iters = w.dba_iters
-    cells_step = cells_medoid + iters * cells_bary + cells_bary
-
-    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for k in ("medoid", "dba", "score")}
-    times = {k: [] for k in ev}
-
-    def step(record: bool):
-        e = ev["medoid"]
-        e[0].record()
-        kk, _, _ = wts.medoid(mplan, Y, with_matrix=False)
-        e[1].record()
-        if int(kk.item()) != k0:
-            raise RuntimeError("medoid changed between steps")
-        Bi, _ = wts.init_barycenter(plan, Y, wts.INIT_COPY, k0)
-        Ba.copy_(Bi)
-        src, dst = Ba, Bb
-        ev["dba"][0].record()
-        for _ in range(iters):
-            wts.dba_iterate(plan, src, Y, bary_out=dst, counts=counts, dist=dist)
-            src, dst = dst, src
-        ev["dba"][1].record()
-        ev["score"][0].record()
-        out = wts.anomaly_score(plan, src, Y)
-        ev["score"][1].record()
-        if record:
-            torch.cuda.synchronize()
-            for k, (a, b) in ev.items():
-                times[k].append(a.elapsed_time(b) / 1e3)
-        return out
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    mplan.enable_timing(4 * args.steps)
-    plan.enable_timing(16 * args.steps)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        last = step(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for op in (wts.OP_MEDOID, wts.OP_DBA, wts.OP_SCORE):
-        st = wts.device_status(mplan if op == wts.OP_MEDOID else plan, op)
-        if st != 0:
-            raise RuntimeError("device status %d after op %d" % (st, op))
-
-    sec = (t1 - t0) / args.steps
-    value = cells_step / sec / 1e9
-    t_med = float(np.mean(times["medoid"]))
-    t_dba = float(np.mean(times["dba"])) / iters
-    t_score = float(np.mean(times["score"]))
-
-    # roofline of the dominant sweep kernel (largest total time over the timed
-    # steps), timed with HIP events around each launch on its stream
-    sweeps = {
-        "medoid": (mplan, wts.OP_MEDOID, cells_medoid, c_min_dist(w.d)),
-        "dba": (plan, wts.OP_DBA, cells_bary, c_min_path(w.d)),
-        "score": (plan, wts.OP_SCORE, cells_bary, c_min_path(w.d)),
-    }
-    kt = {}
-    for key, (pl, op, cells, cm) in sweeps.items():
-        tot, cnt = pl.sweep_ms(op)
-        kt[key] = (tot, cnt)
-    dom = max(kt, key=lambda k: kt[k][0])
-    pl, op, cells, cm = sweeps[dom]
-    launch_s = kt[dom][0] / max(1, kt[dom][1]) / 1e3
-    achieved = cells * cm / launch_s / 1e12
-    peak = VALU_LANE_OPS_PEAK / 1e12
-    kname = KERNELS[dom].format(rho=pl.rho(op)).replace("void ", "")
-    roofline = {"bound": "alu", "kernel": kname,
-                "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(dom, kname),
-                "ops_per_cell": cm, "cells_per_launch": cells,
-                "launch_ms": round(launch_s * 1e3, 3),
-                "per_kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in kt.items()},
-                "per_kernel_alu_frac": {k: round(sweeps[k][2] * sweeps[k][3] /
-                                                 (kt[k][0] / max(1, kt[k][1]) / 1e3) /
-                                                 VALU_LANE_OPS_PEAK, 4) for k in kt}}
-
-    # detection on the step's scores (Sec. IV-D thresholds), against the
-    # cycles that carry an injected drift (a sanity check, not a gate)
-    from paper_2404_12134_amd import detect
-    sc = last[0].cpu().numpy()
-    truth = np.zeros(n, dtype=bool)
-    truth[w.meta["drift"]] = True
-    detection = {"drifted_cycles": [int(i) for i in w.meta["drift"]],
-                 "top_scores": [int(i) for i in np.argsort(-sc)[:len(w.meta["drift"])]]}
-    for name, thr in (("two_sigma", detect.two_sigma_threshold(sc)),
-                      ("boxplot", detect.boxplot_threshold(sc))):
-        tp, fn, fp, tn = detect.confusion(detect.flag(sc, thr), truth)
-        detection[name] = {"threshold": round(thr, 6), "tp": tp, "fn": fn, "fp": fp, "tn": tn,
-                           "f2": round(detect.f_beta(tp, fn, fp), 3)}
-
-    speed = None
-    if not args.no_speedup:
-        # same kernels, one launch per cycle vs one batched launch
-        single = [wts.Plan(off[k:k + 2] - off[k], w.d, dt, L) for k in range(n)]
-        Ys = [Y[int(off[k]):int(off[k + 1])] for k in range(n)]
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for k in range(n):
-            wts.dba_iterate(single[k], Ba, Ys[k])
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        wts.dba_iterate(plan, Ba, Y, bary_out=Bb, counts=counts, dist=dist)
-        torch.cuda.synchronize()
-        tc = time.perf_counter()
-        speed = {"op": "dba_iterate", "one_cycle_per_launch_s": round(tb - ta, 5),
-                 "batched_s": round(tc - tb, 5), "speedup": round((tb - ta) / (tc - tb), 2)}
-
-    soft = None if args.no_soft else guarded(soft_section, wts, dev, args.soft_steps)
-    soft_band = None if args.no_soft else guarded(soft_section, wts, dev, args.soft_steps,
-                                                  band=0.6)
-    large = None if args.no_large else guarded(dba_large_section, wts, dev,
-                                               speedup=not args.no_speedup)
-    irregular = None if args.no_irregular else guarded(irregular_section, wts, dev,
-                                                       speedup=not args.no_speedup)
-    segment = None if args.no_segment else guarded(segmentation_section, wts, dev,
-                                                   speedup=not args.no_speedup)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
-
+    valu = valu_rates()
+    tau = valu["tau"]
+    print("valu rates measured (tau %s); headline next" % tau, file=sys.stderr, flush=True)
+    head = c5_headline(wts, dev, args.steps, args.warmup, tau, speedup=not args.no_speedup,
+                       cpu=not args.no_cpu_baseline)
+    print("headline done: %.1f GCUPS" % head["value"], file=sys.stderr, flush=True)
+    extras = {}
+    if not args.no_extras:
+        for key, fn, kw in (("c4_soft_dtw", c4_section, {"tau": tau, "steps": args.soft_steps}),
+                            ("c3_dba_large", c3_section, {"speedup": not args.no_speedup}),
+                            ("c2_medoid_dba_scores", c2_section,
+                             {"speedup": not args.no_speedup}),
+                            ("segmentation", segmentation_section,
+                             {"speedup": not args.no_speedup})):
+            extras[key] = guarded(fn, wts, dev, **kw)
+            print("section %s done" % key, file=sys.stderr, flush=True)
+        if not args.no_cpu_baseline:
+            from paper_2404_12134_amd import synth
+            extras["c2_cpu_baseline"] = cpu_baseline_c2(synth.make(2))
     line = {
-        "metric": "DTW cell updates/s (GCUPS): medoid init + 10 DBA iterations + anomaly scores",
-        "value": round(value, 3), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True,
+        "metric": "DTW cell updates/s (GCUPS): batched DBA iteration + Soft-DTW forward and "
+                  "backward, one barycenter iteration per step",
+        "value": head["value"], "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": w.name + ": medoid init + %d DBA iterations + anomaly scores" % iters,
-                   "n": n, "d": w.d, "L": L, "cells_per_step": cells_step},
-        "s_per_dba_iteration": round(t_dba, 6),
-        "phase_gcups": {"medoid": round(cells_medoid / t_med / 1e9, 2),
-                        "dba_iteration": round(cells_bary / t_dba / 1e9, 2),
-                        "score": round(cells_bary / t_score / 1e9, 2)},
-        "roofline": roofline,
-        "autotune": {"dba": {"rows_per_lane": tuned["rho"], "grid": tuned["grid"],
-                             "candidates_ms": tuned["table"]},
-                     "medoid": {"rows_per_lane": mtuned["rho"], "grid": mtuned["grid"],
-                                "candidates_ms": mtuned["table"]}},
-        "batched_vs_per_cycle": speed,
-        "detection": detection,
-        "soft_dtw": soft,
-        "soft_dtw_band": soft_band,
-        "dba_large": large,
-        "irregular": irregular,
-        "segmentation": segment,
-        "cpu_baseline": cpu,
+        "config": head["config"],
+        "s_per_iteration": head["s_per_iteration"],
+        "halves_s": head["halves_s"], "phase_gcups": head["phase_gcups"],
+        "score_s": head["score_s"], "workload_s": head["workload_s"],
+        "roofline": head["roofline"],
+        "cpu_baseline": head.get("cpu_baseline"),
+        "batched_vs_per_cycle": head["batched_vs_per_cycle"],
+        "valu": valu,
+        "extras": extras,
     }
     print(json.dumps(line))
 

@@ -16,10 +16,13 @@
  *   wts_anomaly_score    d_score = DTW(B, C_k) / |pi_k|        (Sec. III-D, Eq. 8)
  *   wts_subdtw           Sub-DTW of a reference cycle X against many windows,
  *                        with the first and last matched window columns
- *                        (Sec. III-A, Eq. 2: the segmentation step)
+ *                        (Sec. III-B, Eq. 2: the segmentation step)
  *   wts_precond_step     one preconditioned gradient step on B (Eq. 7 driver)
+ *   wts_barycenter_objective  sum_k w_k Soft-DTW(B, C_k), the Eq. 7 objective
  *   wts_medoid           all-pairs DTW and the medoid cycle (barycenter init)
- *   wts_init_barycenter  Euclidean-mean / nearest-length / copy initialisation
+ *   wts_init_barycenter  Euclidean-mean (Table I "Init", Sec. V-D) /
+ *                        nearest-length / copy initialisation
+ *   wts_plan_status      reads the device status word of a plan's calls
  *
  * Conventions
  *  - Every pointer argument is DEVICE memory unless its name ends in _host.
@@ -40,11 +43,19 @@
  *    cumulative cost equals the minimum.  Distances, paths, path lengths and
  *    alignment counts are bitwise identical to a float64 CPU evaluation of
  *    the same definitions.
- *  - Inputs must be finite (the paper drops NaN samples before any DTW,
- *    Sec. III-A); non-finite inputs give unspecified results.
+ *  - Inputs must be finite: the paper drops samples with missing values
+ *    before any DTW (Sec. III-A).  A plan created with opts.validate = 1
+ *    checks this on the device at the start of every compute call (one pass
+ *    over the call's input values); a call that finds a NaN or an infinity
+ *    skips its sweeps and leaves its outputs undefined, and the next
+ *    wts_plan_status returns WTS_E_NONFINITE.  Without validation,
+ *    non-finite inputs give unspecified results.
  *  - Errors: a non-zero wts_status is returned before anything is enqueued;
  *    wts_last_error() gives a message (thread-local).  WTS_E_HIP reports a
- *    failed HIP call (for instance a launch failure).
+ *    failed HIP call (for instance a launch failure).  What the kernels find
+ *    while they run (non-finite inputs, a strip that gave up waiting for its
+ *    neighbour, inconsistent path tags) goes into the plan's device status
+ *    word, which wts_plan_status reads.
  */
 #ifndef WETSAND_MI_H
 #define WETSAND_MI_H
@@ -64,8 +75,14 @@ typedef enum {
   WTS_E_SHAPE = -2,        /* n, d, L or a cycle length out of range */
   WTS_E_DTYPE = -3,        /* dtype is not WTS_F32 / WTS_F64 */
   WTS_E_WORKSPACE = -4,    /* ws_bytes (or ckpt_bytes) smaller than required */
+  WTS_E_CAPACITY = -5,     /* a size beyond a fixed limit of this build: L or a cycle longer
+                              than 2^24 samples, more than 2^30 sweep items (pairs x strips) */
   WTS_E_HIP = -6,          /* a HIP runtime call failed */
-  WTS_E_UNSUPPORTED = -8   /* valid request this build does not implement */
+  WTS_E_NONFINITE = -7,    /* (wts_plan_status) a validated call found a NaN or an infinity */
+  WTS_E_UNSUPPORTED = -8,  /* valid request this build does not implement */
+  WTS_E_DEVICE = -9        /* (wts_plan_status) a kernel reported an inconsistency: a strip
+                              gave up waiting for its neighbour (about a second), or path
+                              recovery met inconsistent tags; results are undefined        */
 } wts_status;
 
 enum { WTS_F32 = 0, WTS_F64 = 1 };
@@ -94,7 +111,8 @@ typedef struct {
                          2, 4 or 5 for any plan (Soft-DTW sweeps always use 2); other
                          values return WTS_E_UNSUPPORTED                                     */
   int32_t grid;       /* workgroups of the persistent sweep (0 = tuned default)              */
-  int32_t reserved;   /* must be 0                                                           */
+  int32_t validate;   /* 1: every compute call first checks its inputs for NaN / infinity on
+                         the device (see Conventions); 0: no check                           */
   double band;        /* Soft-DTW only: Sakoe-Chiba bandwidth as a fraction w of the longer
                          length (Table I: 0.6); 0 = no band.  Cell (i, j) of an M x N pair
                          is kept iff |i (N-1) - j (M-1)| <= R min(M-1, N-1) with
@@ -112,8 +130,14 @@ typedef struct {
  * L = 0 makes a plan for wts_medoid only (all n(n-1)/2 cycle pairs); the
  * barycenter operations need L > 0.
  * The plan binds the lengths, L and the device; cycle and barycenter VALUES
- * may change between calls.  It allocates a small device table (hipMalloc)
- * here, never in the compute calls.  opts may be NULL (defaults). */
+ * may change between calls.  It allocates small device tables and the
+ * plan's status word (hipMalloc) here, never in the compute calls.  opts may
+ * be NULL (defaults).  Errors: WTS_E_ARG (null out or offsets_host, bad opts,
+ * no such device), WTS_E_SHAPE (n < 1, d < 1, L < 0, offsets_host[0] != 0,
+ * an empty cycle), WTS_E_UNSUPPORTED (d > 8, rho not 0/2/4/5), WTS_E_DTYPE,
+ * WTS_E_CAPACITY (L or a cycle longer than 2^24, more than 2^30 sweep items),
+ * WTS_E_HIP.  Calls on one plan share its status word: run them on one
+ * stream, or read the status after synchronising all of them. */
 wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int32_t dtype,
                            const int64_t* offsets_host, int64_t L, const wts_opts* opts);
 void wts_plan_destroy(wts_plan* plan);
@@ -143,6 +167,18 @@ int32_t wts_plan_rho(const wts_plan* plan, int op);
 
 /* Message describing the last non-OK status returned on this thread. */
 const char* wts_last_error(void);
+
+/* Synchronises `stream`, then reads and clears the plan's device status word
+ * (one atomic exchange on `stream`, so a bit set by a call still running on
+ * another stream is reported by the next read, never lost).  The word
+ * collects what every kernel of every call on this plan reported since the
+ * last read: WTS_E_NONFINITE if a validated call found a NaN or an infinity
+ * (that call skipped its sweeps), else WTS_E_DEVICE if a strip gave up
+ * waiting for its neighbour or path recovery met inconsistent tags (the
+ * results of those calls are undefined), else WTS_OK.  WTS_E_ARG for a null
+ * plan, WTS_E_HIP if a HIP call fails.  It synchronises, so it cannot be
+ * captured into a graph. */
+wts_status wts_plan_status(const wts_plan* plan, void* stream);
 
 /* Eq. 1 (DTW) and the optimal path of every (B, C_k).
  *   bary      [L][d] float64
@@ -176,7 +212,7 @@ wts_status wts_anomaly_score(const wts_plan* plan, const double* bary, const voi
                              double* score, double* dist, int64_t* path_len, void* ws,
                              size_t ws_bytes, void* stream);
 
-/* Sec. III-A, Eq. 2: Sub-DTW of the reference X (the plan's L rows, float64
+/* Sec. III-B, Eq. 2: Sub-DTW of the reference X (the plan's L rows, float64
  * [L][d], passed where the other calls take the barycenter) against every
  * window C_k of the batch: the minimum over alignment paths that cover all
  * rows of X and any run of columns of C_k,
@@ -200,13 +236,20 @@ wts_status wts_softdtw_forward(const wts_plan* plan, const double* bary, const v
 
 /* Eq. 6-7: grad_bary = sum_{k ascending} grad_value_k * d Soft-DTW^gamma(B, C_k) / d B,
  * with E from the chain rule on Eq. 5 (E(L, N) = 1 and zero outside the grid).
- * grad_value [n] float64 (the upstream gradient, e.g. lambda_k / m_k for Eq. 7);
- * grad_bary [L][d] float64 out; row_mass [L] float64 out or NULL:
- * row_mass_l = sum_k grad_value_k * sum_j E^k_{lj}. */
+ * grad_value [n] float64 (the upstream gradient, e.g. lambda_k / m_k for Eq. 7;
+ * NULL = all 1); grad_bary [L][d] float64 out; row_mass [L] float64 out or
+ * NULL: row_mass_l = sum_k grad_value_k * sum_j E^k_{lj}.
+ * accumulate = 0: the sums start from 0 (grad_bary and row_mass are
+ * overwritten); accumulate = 1: they start from the values already in
+ * grad_bary and row_mass.  A batch split into consecutive cycle groups (one
+ * plan each, for instance so that each group's checkpoints fit in memory),
+ * run in order with accumulate = 1 after the first group, gives bitwise the
+ * result of one call over the whole batch: the same additions in the same
+ * order.  WTS_E_ARG also for accumulate not 0 or 1. */
 wts_status wts_softdtw_backward(const wts_plan* plan, const double* bary, const void* cycles,
                                 double gamma, const void* ckpt, size_t ckpt_bytes,
                                 const double* grad_value, double* grad_bary, double* row_mass,
-                                void* ws, size_t ws_bytes, void* stream);
+                                int32_t accumulate, void* ws, size_t ws_bytes, void* stream);
 
 /* Eq. 6 for the other argument: the gradient of sum_k w_k Soft-DTW^gamma(B, C_k)
  * with respect to the cycle values,
@@ -232,7 +275,18 @@ wts_status wts_softdtw_grad_cycles(const wts_plan* plan, const double* bary, con
 wts_status wts_precond_step(double* bary, const double* grad, const double* row_mass, int64_t L,
                             int32_t d, double eta, void* stream);
 
-/* Medoid initialisation: D[k][i] = DTW(C_k, C_i) (squared cost, D[k][k] = 0),
+/* Eq. 7 objective of a batch: out = sum_{k ascending} weights_k value_k (weights
+ * NULL = all 1), for instance the Soft-DTW values of wts_softdtw_forward
+ * with weights lambda_k / m_k.  accumulate = 1 adds to the value already in
+ * out (cycle groups, as for wts_softdtw_backward).  values [n], weights [n]
+ * float64, out [1] float64.  No plan needed.  WTS_E_ARG for a null values or
+ * out, or accumulate not 0 or 1; WTS_E_SHAPE for n < 1. */
+wts_status wts_barycenter_objective(const double* values, const double* weights, int32_t n,
+                                    int32_t accumulate, double* out, void* stream);
+
+/* Medoid initialisation (the workload recipes' barycenter init for DTW
+ * barycenter averaging; the paper itself starts the Soft-DTW barycenter from
+ * the Euclidean mean): D[k][i] = DTW(C_k, C_i) (squared cost, D[k][k] = 0),
  * total_k = sum_{i ascending} D[k][i], medoid = argmin_k total_k (lowest k on
  * ties).  dist_matrix [n][n] float64 or NULL, totals [n] float64 or NULL,
  * medoid [1] int32 out. */
@@ -241,9 +295,12 @@ wts_status wts_medoid(const wts_plan* plan, const void* cycles, double* dist_mat
 
 /* Barycenter initialisation into bary_out [L][d] float64 (plan L > 0):
  *   WTS_INIT_EUCLID_MEAN: pad every cycle with its last sample to the longest
- *     length Nmax, average per index (ascending k, then / n), resample to L;
+ *     length Nmax (Sec. IV-A pads cycles this way), average per index
+ *     (ascending k, then / n), resample to L: the "Euclidean barycenter"
+ *     Table I starts from (Sec. V-D finds it the best start);
  *   WTS_INIT_NEAREST: the cycle whose length is closest to L (lowest k on
- *     ties), resampled to L;
+ *     ties), resampled to L (a choice of the workload recipes, not the
+ *     paper's);
  *   WTS_INIT_COPY: cycle `index` resampled to L (a copy when its length is L).
  * Resampling: t_l = l (N-1) / (L-1), value = y[a] + f (y[a+1] - y[a]) with
  * a = floor(t_l), f = t_l - a.  chosen_host: HOST int32 out (the cycle used,

@@ -265,7 +265,7 @@ def nearest_init(cycles, L):
 
 
 def subdtw(X, Y, kind=SQEUCLID):
-    """Sub-DTW (Sec. III-A, Eq. 2): (value, a*, b*), 0-based columns of Y."""
+    """Sub-DTW (Sec. III-B, Eq. 2): (value, a*, b*), 0-based columns of Y."""
     X, Y = _series(X), _series(Y)
     v = np.zeros(1)
     a = np.zeros(1, dtype=np.int64)
@@ -289,12 +289,12 @@ def subdtw_batch(X, windows, kind=SQEUCLID):
 
 
 def segment_alpha(M: int) -> int:
-    """alpha = 0.15 M (Sec. III-A), rounded down to whole samples."""
+    """alpha = 0.15 M (Sec. III-B), rounded down to whole samples."""
     return int(0.15 * M)
 
 
 def segment(X, Y, kind=SQEUCLID):
-    """The segmentation loop of Sec. III-A, 0-based and half-open windows:
+    """The segmentation loop of Sec. III-B, 0-based and half-open windows:
     ws = 0; repeat: window Y[ws : min(ws + 2M, N)], (a*, b*) of its Sub-DTW
     made absolute, cycle Y[a* .. b*] kept, ws <- b* - alpha, while ws < N.
     Where b* - alpha would not move the window forward (the paper does not

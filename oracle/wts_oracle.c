@@ -442,7 +442,7 @@ int wts_o_softdtw_grad_ckpt(const double* X, int64_t M, const double* Y, int64_t
   return 0;
 }
 
-/* Sub-DTW (Sec. III-A, Eq. 2): the minimum cost over subsequence alignment
+/* Sub-DTW (Sec. III-B, Eq. 2): the minimum cost over subsequence alignment
  * paths, which run from row 1 to row M of X but may start and end at any
  * column of Y.  The dynamic program is Eq. 1's with a free start: the row
  * above the first one is 0 at every column (r_{0,j} = 0 in the paper's

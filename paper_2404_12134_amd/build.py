@@ -23,7 +23,7 @@ OBJDIR = os.path.join(HERE, "_build")
 # The Soft-DTW kernels never subtract two infinities: every computed cell has
 # at least one finite predecessor, so the same holds there.
 SOURCES = {"wts_dtw.hip": ["-fno-honor-nans"], "wts_soft.hip": ["-fno-honor-nans"],
-           "wts_abi.hip": []}
+           "wts_abi.hip": [], "wts_aux.hip": []}
 ARCH = os.environ.get("WTS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -44,11 +44,30 @@ def _compile(src: str) -> str:
     return obj
 
 
+# The VALU issue-rate microbenchmark behind the roofline's op counts: its own
+# library, outside the C ABI of the hot path.
+UBENCH_SRC = "wts_ubench.hip"
+UBENCH_LIB = os.path.join(HERE, "libwts_ubench.so")
+
+
+def _build_ubench() -> str:
+    tmp = UBENCH_LIB + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-shared", os.path.join(CSRC, UBENCH_SRC), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed on " + UBENCH_SRC)
+    os.replace(tmp, UBENCH_LIB)
+    return UBENCH_LIB
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source (always) and link the shared library."""
+    """Compile every source (always) and link the shared libraries."""
     os.makedirs(OBJDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        ub = ex.submit(_build_ubench)
         objs = list(ex.map(_compile, list(SOURCES)))
+        ub.result()
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -167,6 +167,9 @@ struct wts_plan {
   PairSet bary, med, soft;
   PairSet softT;   // Soft-DTW with the roles swapped: the cycles on the rows, B on the columns
   int64_t nmax = 0;
+  // device words: [0] sticky status bits (wts_plan_status reads and clears
+  // them), [1] the current call's validation flag, [2] read-out slot
+  int* d_status = nullptr;
   // optional sweep timing: pool of (start, stop) event pairs, one per sweep launch
   std::vector<hipEvent_t> ev;
   size_t ev_next = 0;
@@ -274,6 +277,24 @@ wts_status check_bary_plan(const wts_plan* p) {
   return WTS_OK;
 }
 
+const int* skip_of(const wts_plan* p) { return p->opts.validate ? p->d_status + 1 : nullptr; }
+
+// opts.validate: clear the call's flag, then scan its inputs; a value that is
+// not finite sets the flag (every sweep and path-recovery kernel of the call
+// then returns at once) and the sticky WTS_E_NONFINITE bit.
+wts_status validate_inputs(const wts_plan* p, hipStream_t st, wts::ScanSeg a, wts::ScanSeg b = {},
+                           wts::ScanSeg c = {}) {
+  if (!p->opts.validate) return WTS_OK;
+  const wts::ScanSeg segs[3] = {a, b, c};
+  HIP_TRY(wts::launch_zero(p->d_status + 1, 1, st));
+  HIP_TRY(wts::launch_finite_scan(segs, 3, p->d_status + 1, p->d_status, st));
+  return WTS_OK;
+}
+wts::ScanSeg seg_f64(const void* ptr, int64_t n) { return wts::ScanSeg{ptr, n, 0}; }
+wts::ScanSeg seg_cycles(const wts_plan* p, const void* ptr) {
+  return wts::ScanSeg{ptr, p->off[p->n] * p->d, p->dtype == WTS_F32 ? 1 : 0};
+}
+
 // Sweep timing (off unless wts_plan_timing enabled it): records a pair of
 // events around the sweep kernel of operation `op` on its stream.
 int timing_begin(const wts_plan* p, int op, hipStream_t st) {
@@ -303,7 +324,8 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
   a.items = ps.d_sweep_items;
   a.n_items = ps.n_items;
   a.queue = at<int>(ws, l.queue);
-  a.status = at<int>(ws, l.queue) + 1;
+  a.status = p->d_status;
+  a.skip = skip_of(p);
   a.x = x;
   a.y = y;
   a.bnd_r = at<double>(ws, l.bnd_r);
@@ -331,8 +353,8 @@ wts_status run_paths(const wts_plan* p, const double* bary, const void* cycles, 
   wts_status rc = run_sweep(p, ps, wts::MODE_PATH, false, false, bary, cycles, ws, l, out_dist, st);
   if (rc != WTS_OK) return rc;
   HIP_TRY(wts::launch_chain(ps.d_pairs, ps.n_pairs, at<int>(ws, l.bnd_aux),
-                            at<int>(ws, l.out_aux), at<int2>(ws, l.seg),
-                            at<int>(ws, l.queue) + 1, st));
+                            at<int>(ws, l.out_aux), at<int2>(ws, l.seg), p->d_status,
+                            skip_of(p), st));
   wts::WalkArgs w{};
   w.pairs = ps.d_pairs;
   w.items = ps.d_items;
@@ -343,7 +365,8 @@ wts_status run_paths(const wts_plan* p, const double* bary, const void* cycles, 
   w.pcnt = pcnt;
   w.L = p->L;
   w.seg_len = at<int>(ws, l.seg_len);
-  w.status = at<int>(ws, l.queue) + 1;
+  w.status = p->d_status;
+  w.skip = skip_of(p);
   HIP_TRY(wts::launch_walk(p->d, ps.rho, p->dtype, false, w, ps.n_items, st));
   return WTS_OK;
 }
@@ -362,19 +385,22 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   if (n < 1) return fail(WTS_E_SHAPE, "n = %d: need at least one cycle", n);
   if (d < 1 || d > 8) return fail(d < 1 ? WTS_E_SHAPE : WTS_E_UNSUPPORTED, "d = %d: 1..8 supported", d);
   if (dtype != WTS_F32 && dtype != WTS_F64) return fail(WTS_E_DTYPE, "dtype %d", dtype);
-  if (L < 0 || L > (1 << 24)) return fail(WTS_E_SHAPE, "L = %lld out of range", (long long)L);
+  if (L < 0) return fail(WTS_E_SHAPE, "L = %lld out of range", (long long)L);
   if (offsets_host[0] != 0) return fail(WTS_E_SHAPE, "offsets_host[0] must be 0");
+  if (L > (1 << 24)) return fail(WTS_E_CAPACITY, "L = %lld: at most 2^24 rows", (long long)L);
   for (int k = 0; k < n; ++k) {
     const int64_t len = offsets_host[k + 1] - offsets_host[k];
     if (len < 1) return fail(WTS_E_SHAPE, "cycle %d has length %lld", k, (long long)len);
-    if (len > (1 << 24)) return fail(WTS_E_SHAPE, "cycle %d too long", k);
+    if (len > (1 << 24))
+      return fail(WTS_E_CAPACITY, "cycle %d has %lld samples: at most 2^24", k, (long long)len);
   }
   wts_opts o{};
   if (opts) o = *opts;
   if (o.cost != WTS_COST_SQEUCLID && o.cost != WTS_COST_EUCLID) return fail(WTS_E_ARG, "opts.cost");
   if (o.rho != 0 && o.rho != 2 && o.rho != 4 && o.rho != 5)
     return fail(WTS_E_UNSUPPORTED, "opts.rho = %d: 2, 4 or 5 supported", o.rho);
-  if (o.grid < 0 || o.reserved != 0) return fail(WTS_E_ARG, "opts.grid / opts.reserved");
+  if (o.grid < 0) return fail(WTS_E_ARG, "opts.grid = %d", o.grid);
+  if (o.validate != 0 && o.validate != 1) return fail(WTS_E_ARG, "opts.validate = %d: 0 or 1", o.validate);
   if (!(o.band >= 0.0) || !std::isfinite(o.band)) return fail(WTS_E_ARG, "opts.band must be finite and >= 0");
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev));
@@ -455,7 +481,14 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
     if ((e = hipMemcpy(ps->d_items, ps->items.data(), sizeof(int2) * ps->items.size(), hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup_fail(e, "hipMemcpy");
   }
+  for (PairSet* ps : {&p->bary, &p->med, &p->soft, &p->softT})
+    if (ps->items.size() > (size_t(1) << 30)) {
+      wts_plan_destroy(p);
+      return fail(WTS_E_CAPACITY, "more than 2^30 sweep items (pairs x strips)");
+    }
   hipError_t e;
+  if ((e = hipMalloc(&p->d_status, 4 * sizeof(int))) != hipSuccess) return cleanup_fail(e, "hipMalloc");
+  if ((e = hipMemset(p->d_status, 0, 4 * sizeof(int))) != hipSuccess) return cleanup_fail(e, "hipMemset");
   if ((e = hipMalloc(&p->d_off, sizeof(int64_t) * (n + 1))) != hipSuccess) return cleanup_fail(e, "hipMalloc");
   if ((e = hipMemcpy(p->d_off, p->off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup_fail(e, "hipMemcpy");
@@ -533,6 +566,7 @@ void wts_plan_destroy(wts_plan* p) {
     if (ps->d_sweep_items) (void)hipFree(ps->d_sweep_items);
   }
   if (p->d_off) (void)hipFree(p->d_off);
+  if (p->d_status) (void)hipFree(p->d_status);
   if (p->d_path_base) (void)hipFree(p->d_path_base);
   if (p->d_med_ab) (void)hipFree(p->d_med_ab);
   delete p;
@@ -569,6 +603,8 @@ wts_status wts_dtw_align(const wts_plan* p, const double* bary, const void* cycl
   if ((rc = check_ws(p, op, ws, ws_bytes)) != WTS_OK) return rc;
   DeviceGuard g(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = validate_inputs(p, st, seg_f64(bary, p->L * p->d), seg_cycles(p, cycles))) != WTS_OK)
+    return rc;
   const Layout l = layout(p, op);
   if (!paths) {
     rc = run_sweep(p, p->bary, wts::MODE_DIST_LEN, p->opts.cost == WTS_COST_EUCLID, false, bary,
@@ -593,7 +629,8 @@ wts_status wts_dtw_align(const wts_plan* p, const double* bary, const void* cycl
   w.seg_off = at<int>(ws, l.seg_off);
   w.path_base = p->d_path_base;
   w.paths = paths;
-  w.status = at<int>(ws, l.queue) + 1;
+  w.status = p->d_status;
+  w.skip = skip_of(p);
   HIP_TRY(wts::launch_walk(p->d, ps.rho, p->dtype, true, w, ps.n_items, st));
   return WTS_OK;
 }
@@ -608,6 +645,9 @@ wts_status wts_dba_iterate(const wts_plan* p, const double* bary_in, const void*
   if ((rc = check_ws(p, WTS_OP_DBA, ws, ws_bytes)) != WTS_OK) return rc;
   DeviceGuard g(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = validate_inputs(p, st, seg_f64(bary_in, p->L * p->d), seg_cycles(p, cycles),
+                            seg_f64(weights, p->n))) != WTS_OK)
+    return rc;
   const Layout l = layout(p, WTS_OP_DBA);
   rc = run_paths(p, bary_in, cycles, ws, l, dist, at<double>(ws, l.psum), at<int>(ws, l.pcnt), st);
   if (rc != WTS_OK) return rc;
@@ -625,6 +665,8 @@ wts_status wts_anomaly_score(const wts_plan* p, const double* bary, const void* 
   if ((rc = check_ws(p, WTS_OP_SCORE, ws, ws_bytes)) != WTS_OK) return rc;
   DeviceGuard g(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = validate_inputs(p, st, seg_f64(bary, p->L * p->d), seg_cycles(p, cycles))) != WTS_OK)
+    return rc;
   const Layout l = layout(p, WTS_OP_SCORE);
   double* dv = dist ? dist : at<double>(ws, l.out_dist);
   rc = run_sweep(p, p->bary, wts::MODE_DIST_LEN, p->opts.cost == WTS_COST_EUCLID, false, bary,
@@ -645,6 +687,8 @@ wts_status wts_subdtw(const wts_plan* p, const double* x, const void* windows, d
   if ((rc = check_ws(p, WTS_OP_SUBDTW, ws, ws_bytes)) != WTS_OK) return rc;
   DeviceGuard g(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = validate_inputs(p, st, seg_f64(x, p->L * p->d), seg_cycles(p, windows))) != WTS_OK)
+    return rc;
   const Layout l = layout(p, WTS_OP_SUBDTW);
   rc = run_sweep(p, p->bary, wts::MODE_SUB, false, false, x, windows, ws, l, value, st);
   if (rc != WTS_OK) return rc;
@@ -663,6 +707,8 @@ wts_status wts_softdtw_forward(const wts_plan* p, const double* bary, const void
   if ((rc = check_ws(p, WTS_OP_SOFT_FWD, ckpt, ckpt_bytes)) != WTS_OK) return rc;
   DeviceGuard g(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = validate_inputs(p, st, seg_f64(bary, p->L * p->d), seg_cycles(p, cycles))) != WTS_OK)
+    return rc;
   const Layout l = layout(p, WTS_OP_SOFT_FWD);
   const PairSet& ps = p->soft;
   HIP_TRY(wts::launch_zero(at<int>(ckpt, l.queue), 2, st));
@@ -672,7 +718,8 @@ wts_status wts_softdtw_forward(const wts_plan* p, const double* bary, const void
   a.items = ps.d_sweep_items;
   a.n_items = ps.n_items;
   a.queue = at<int>(ckpt, l.queue);
-  a.status = at<int>(ckpt, l.queue) + 1;
+  a.status = p->d_status;
+  a.skip = skip_of(p);
   a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
   a.progress = at<int>(ckpt, l.progress);
   a.x = bary;
@@ -692,15 +739,19 @@ wts_status wts_softdtw_forward(const wts_plan* p, const double* bary, const void
 wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const void* cycles,
                                 double gamma, const void* ckpt, size_t ckpt_bytes,
                                 const double* grad_value, double* grad_bary, double* row_mass,
-                                void* ws, size_t ws_bytes, void* stream) {
+                                int32_t accumulate, void* ws, size_t ws_bytes, void* stream) {
   wts_status rc = check_bary_plan(p);
   if (rc != WTS_OK) return rc;
   if (!bary || !cycles || !grad_bary) return fail(WTS_E_ARG, "null bary/cycles/grad_bary");
   if (!(gamma > 0) || !(gamma < INFINITY)) return fail(WTS_E_ARG, "gamma must be finite and > 0");
   if ((rc = check_ws(p, WTS_OP_SOFT_FWD, const_cast<void*>(ckpt), ckpt_bytes)) != WTS_OK) return rc;
   if ((rc = check_ws(p, WTS_OP_SOFT_BWD, ws, ws_bytes)) != WTS_OK) return rc;
+  if (accumulate != 0 && accumulate != 1) return fail(WTS_E_ARG, "accumulate = %d: 0 or 1", accumulate);
   DeviceGuard g(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = validate_inputs(p, st, seg_f64(bary, p->L * p->d), seg_cycles(p, cycles),
+                            seg_f64(grad_value, p->n))) != WTS_OK)
+    return rc;
   const Layout lc = layout(p, WTS_OP_SOFT_FWD);
   const Layout l = layout(p, WTS_OP_SOFT_BWD);
   const PairSet& ps = p->soft;
@@ -712,7 +763,8 @@ wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const voi
   a.items = ps.d_items_rev;
   a.n_items = ps.n_items;
   a.queue = at<int>(ws, l.queue);
-  a.status = at<int>(ws, l.queue) + 1;
+  a.status = p->d_status;
+  a.skip = skip_of(p);
   a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
   a.progress = at<int>(ws, l.progress);
   a.x = bary;
@@ -730,7 +782,7 @@ wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const voi
   HIP_TRY(wts::launch_soft(p->d, p->dtype, true, a, default_grid(p, ps), st));
   timing_end(p, tk, st);
   HIP_TRY(wts::launch_soft_reduce(a.gsum, a.hsum, grad_value, p->n, p->L, p->d, grad_bary,
-                                  row_mass, st));
+                                  row_mass, accumulate, st));
   return WTS_OK;
 }
 
@@ -744,13 +796,17 @@ wts_status wts_softdtw_grad_cycles(const wts_plan* p, const double* bary, const 
   if ((rc = check_ws(p, WTS_OP_SOFT_GRAD_C, ws, ws_bytes)) != WTS_OK) return rc;
   DeviceGuard g(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = validate_inputs(p, st, seg_f64(bary, p->L * p->d), seg_f64(cycles64, p->off[p->n] * p->d),
+                            seg_f64(grad_value, p->n))) != WTS_OK)
+    return rc;
   const Layout l = layout(p, WTS_OP_SOFT_GRAD_C);
   const PairSet& ps = p->softT;
   wts::SoftArgs a{};
   a.pairs = ps.d_pairs;
   a.n_items = ps.n_items;
   a.queue = at<int>(ws, l.queue);
-  a.status = at<int>(ws, l.queue) + 1;
+  a.status = p->d_status;
+  a.skip = skip_of(p);
   a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
   a.progress = at<int>(ws, l.progress);
   a.x = cycles64;          // rows: every cycle, at its own offset (PairDesc.x_off)
@@ -798,6 +854,7 @@ wts_status wts_medoid(const wts_plan* p, const void* cycles, double* dist_matrix
   if (rc != WTS_OK) return rc;
   DeviceGuard g(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = validate_inputs(p, st, seg_cycles(p, cycles))) != WTS_OK) return rc;
   const Layout l = layout(p, WTS_OP_MEDOID);
   double* Dm = dist_matrix ? dist_matrix : at<double>(ws, l.dm);
   double* tot = totals ? totals : at<double>(ws, l.totals);
@@ -838,9 +895,41 @@ wts_status wts_init_barycenter(const wts_plan* p, const void* cycles, int32_t ki
   }
   DeviceGuard g(p->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const wts_status rc = validate_inputs(p, st, seg_cycles(p, cycles));
+  if (rc != WTS_OK) return rc;
   HIP_TRY(wts::launch_init(p->dtype, cycles, p->d_off, p->n, p->d, src, Nsrc, p->L, euclid,
                            bary_out, st));
   if (chosen_host) *chosen_host = euclid ? -1 : src;
+  return WTS_OK;
+}
+
+wts_status wts_plan_status(const wts_plan* p, void* stream) {
+  if (!p) return fail(WTS_E_ARG, "plan is null");
+  DeviceGuard g(p->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(wts::launch_status_take(p->d_status, p->d_status + 2, st));
+  int word = 0;
+  HIP_TRY(hipMemcpyAsync(&word, p->d_status + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (word & wts::kStatusNonFinite)
+    return fail(WTS_E_NONFINITE, "a validated call found a NaN or an infinity in its inputs; "
+                "the sweeps of that call were skipped and its outputs are undefined");
+  if (word & wts::kStatusSpinTimeout)
+    return fail(WTS_E_DEVICE, "a strip gave up waiting for its neighbour; the results of the "
+                "calls since the last status read are undefined");
+  if (word & wts::kStatusBadPath)
+    return fail(WTS_E_DEVICE, "path recovery found inconsistent strip tags; the paths and DBA "
+                "updates since the last status read are undefined");
+  return WTS_OK;
+}
+
+wts_status wts_barycenter_objective(const double* values, const double* weights, int32_t n,
+                                    int32_t accumulate, double* out, void* stream) {
+  if (!values || !out) return fail(WTS_E_ARG, "null values/out");
+  if (n < 1) return fail(WTS_E_SHAPE, "n = %d", n);
+  if (accumulate != 0 && accumulate != 1) return fail(WTS_E_ARG, "accumulate = %d: 0 or 1", accumulate);
+  HIP_TRY(wts::launch_objective(values, weights, n, accumulate, out,
+                                static_cast<hipStream_t>(stream)));
   return WTS_OK;
 }
 

@@ -100,6 +100,7 @@ struct FwdArgs {
   int* out_end;          // [pair slot] b* (SUB)
   int cost_kind;         // 0 squared, 1 Euclidean (sqrt)
   int relaxed_wait;      // 1: far more items than resident wavefronts; wait with long sleeps
+  const int* skip;       // non-zero flag: the call's inputs failed validation, do nothing (or null)
 };
 
 struct SoftArgs {
@@ -123,13 +124,20 @@ struct SoftArgs {
   int relaxed_wait;      // 1: far more items than resident wavefronts; wait with long sleeps
   double band;           // Sakoe-Chiba bandwidth as a fraction of the longer length (0: none)
   int rows_packed;       // 0: gsum/hsum rows at out * L + i; 1: at x_off + i (X rows packed)
+  const int* skip;       // non-zero flag: the call's inputs failed validation, do nothing (or null)
 };
 
 __device__ __forceinline__ double inf_d() { return __builtin_huge_val(); }
 
-// Status bits reported in the workspace status word.
+// Status bits of a plan's device status word (sticky until wts_plan_status
+// reads and clears it).
 constexpr int kStatusSpinTimeout = 1;   // a strip gave up waiting for its predecessor
 constexpr int kStatusBadPath = 2;       // path recovery left the strip (inconsistent tags)
+constexpr int kStatusNonFinite = 4;     // a validated call found a NaN or an infinity in its inputs
+
+// A validated call whose inputs hold a non-finite value sets its skip flag;
+// every sweep and path-recovery kernel of the call then returns at once.
+__device__ __forceinline__ bool skipped(const int* skip) { return skip != nullptr && *skip != 0; }
 // Sleep between two polls of a strip that waits for its neighbour: two quick
 // polls, then short sleeps, or long ones when far more items than resident
 // wavefronts keep the SIMD busy meanwhile (each poll costs issue slots).

@@ -103,6 +103,7 @@ void dtw_fwd_kernel(FwdArgs a) {
   const TX* __restrict__ X = static_cast<const TX*>(a.x);
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const double INF = inf_d();
+  if (skipped(a.skip)) return;   // every wave of every workgroup: no strip waits for another
 
   for (;;) {
     if (lane == 0) s_item = atomicAdd(a.queue, 1);
@@ -406,9 +407,10 @@ void dtw_fwd_kernel(FwdArgs a) {
 // strip, where the path crosses its bottom row and its top row.
 __global__ void chain_kernel(const PairDesc* __restrict__ pairs, int n_pairs,
                              const int* __restrict__ bnd_aux, const int* __restrict__ out_aux,
-                             int2* __restrict__ seg, int* __restrict__ status) {
+                             int2* __restrict__ seg, int* __restrict__ status,
+                             const int* __restrict__ skip) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
+  if (p >= n_pairs || skipped(skip)) return;
   const PairDesc pd = pairs[p];
   int e = out_aux[pd.out];
   int jx = pd.N - 1;
@@ -449,6 +451,7 @@ __global__ __launch_bounds__(kWave) void walk_kernel(WalkArgs a) {
   __shared__ int run_hi[H];
   const int lane = threadIdx.x;
   const int item = blockIdx.x;
+  if (skipped(a.skip)) return;
   const int2 it = a.items[item];
   const PairDesc pd = a.pairs[it.x];
   const int s = it.y;
@@ -821,9 +824,10 @@ hipError_t launch_walk(int d, int rho, int ydtype, bool emit, const WalkArgs& a,
 }
 
 hipError_t launch_chain(const PairDesc* pairs, int n_pairs, const int* bnd_aux,
-                        const int* out_aux, int2* seg, int* status, hipStream_t st) {
+                        const int* out_aux, int2* seg, int* status, const int* skip,
+                        hipStream_t st) {
   hipLaunchKernelGGL(chain_kernel, dim3((n_pairs + 63) / 64), dim3(64), 0, st, pairs, n_pairs,
-                     bnd_aux, out_aux, seg, status);
+                     bnd_aux, out_aux, seg, status, skip);
   return hipGetLastError();
 }
 

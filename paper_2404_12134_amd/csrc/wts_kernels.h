@@ -21,6 +21,7 @@ struct WalkArgs {
   const int64_t* path_base; // per pair slot: first path row
   int32_t* paths;           // [rows][2]
   int* status;              // device status word
+  const int* skip;          // validation flag of the call (or null)
 };
 
 hipError_t launch_fwd(int d, int rho, int mode, bool euc, bool x_is_cycle, int ydtype,
@@ -28,7 +29,8 @@ hipError_t launch_fwd(int d, int rho, int mode, bool euc, bool x_is_cycle, int y
 hipError_t launch_walk(int d, int rho, int ydtype, bool emit, const WalkArgs& a, int n_items,
                        hipStream_t st);
 hipError_t launch_chain(const PairDesc* pairs, int n_pairs, const int* bnd_aux,
-                        const int* out_aux, int2* seg, int* status, hipStream_t st);
+                        const int* out_aux, int2* seg, int* status, const int* skip,
+                        hipStream_t st);
 hipError_t launch_zero(int* p, int64_t n, hipStream_t st);
 hipError_t launch_fill_sentinels(double* r, int64_t nr, int* x, int64_t nx, hipStream_t st);
 hipError_t launch_seg_prefix(const PairDesc* pairs, int n_pairs, const int* seg_len,
@@ -45,7 +47,20 @@ hipError_t launch_soft(int d, int ydtype, bool bwd, const SoftArgs& a, int grid,
 hipError_t launch_soft_rows_scale(const double* g, const int64_t* off, int n, int64_t rows, int d,
                                   const double* w, double* out, hipStream_t st);
 hipError_t launch_soft_reduce(const double* gsum, const double* hsum, const double* w, int n,
-                              int64_t L, int d, double* grad, double* mass, hipStream_t st);
+                              int64_t L, int d, double* grad, double* mass, int accumulate,
+                              hipStream_t st);
+
+// wts_aux.hip: input validation, the status word, the Eq. 7 objective.
+struct ScanSeg {
+  const void* p;   // values to check (or null)
+  int64_t n;       // number of values
+  int f32;         // 1: float32, 0: float64
+};
+hipError_t launch_finite_scan(const ScanSeg* segs, int nseg, int* flag, int* status,
+                              hipStream_t st);
+hipError_t launch_status_take(int* status, int* out, hipStream_t st);
+hipError_t launch_objective(const double* values, const double* weights, int n, int accumulate,
+                            double* out, hipStream_t st);
 hipError_t launch_precond_step(double* bary, const double* grad, const double* mass, int64_t L,
                                int d, double eta, hipStream_t st);
 hipError_t launch_init(int ydtype, const void* Y, const int64_t* off, int n, int d, int src,

@@ -143,6 +143,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const double INF = inf_d();
   const double k = a.kscale;
+  if (skipped(a.skip)) return;   // every workgroup: no strip waits for another
 
   for (;;) {
     if (lane == 0) s_item = atomicAdd(a.queue, 1);
@@ -370,6 +371,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const double INF = inf_d();
   const double k = a.kscale;
+  if (skipped(a.skip)) return;   // every workgroup: no strip waits for another
 
   for (;;) {
     if (lane == 0) s_item = atomicAdd(a.queue, 1);
@@ -657,19 +659,23 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
   }
 }
 
-// G_l = sum_k w_k * grad_k(l), h_l = sum_k w_k * mass_k(l), ascending k.
+// G_l = sum_k w_k * grad_k(l), h_l = sum_k w_k * mass_k(l), ascending k,
+// starting from 0 or (accumulate) from the values already in grad / mass.
+// Calls over consecutive cycle groups with accumulate = 1 after the first
+// therefore perform the very additions of one call over all cycles.
 __global__ void soft_reduce_kernel(const double* __restrict__ gsum, const double* __restrict__ hsum,
                                    const double* __restrict__ w, int n, int64_t L, int d,
-                                   double* __restrict__ grad, double* __restrict__ mass) {
+                                   double* __restrict__ grad, double* __restrict__ mass,
+                                   int accumulate) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= L * d) return;
   const int64_t l = idx / d;
   const int c = (int)(idx - l * d);
-  double g = 0.0;
+  double g = accumulate ? grad[idx] : 0.0;
   for (int p = 0; p < n; ++p) g = g + (w ? w[p] : 1.0) * gsum[((int64_t)p * L + l) * d + c];
   grad[idx] = g;
   if (c == 0 && mass) {
-    double h = 0.0;
+    double h = accumulate ? mass[l] : 0.0;
     for (int p = 0; p < n; ++p) h = h + (w ? w[p] : 1.0) * hsum[(int64_t)p * L + l];
     mass[l] = h;
   }
@@ -762,10 +768,11 @@ hipError_t launch_soft_rows_scale(const double* g, const int64_t* off, int n, in
 }
 
 hipError_t launch_soft_reduce(const double* gsum, const double* hsum, const double* w, int n,
-                              int64_t L, int d, double* grad, double* mass, hipStream_t st) {
+                              int64_t L, int d, double* grad, double* mass, int accumulate,
+                              hipStream_t st) {
   const int64_t tot = L * d;
   hipLaunchKernelGGL(soft_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                     gsum, hsum, w, n, L, d, grad, mass);
+                     gsum, hsum, w, n, L, d, grad, mass, accumulate);
   return hipGetLastError();
 }
 

@@ -1,4 +1,4 @@
-"""Detection thresholds on the similarity scores (Sec. IV-D) -- host helpers.
+"""Detection thresholds on the similarity scores (Sec. V-C) -- host helpers.
 
 The scores d_score = DTW(B, C_k) / |pi| come from the GPU (anomaly_score);
 choosing a threshold is left to the user by the paper, which evaluates two:

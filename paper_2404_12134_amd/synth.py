@@ -208,8 +208,8 @@ def make(k: int, *, n: Optional[int] = None, len_range=None, L: Optional[int] = 
 
 def make_stream(seed: int, n_cycles: int, len_range=(15000, 17500), d: int = 3,
                 idle_frac=(0.0, 0.08), dtype: str = "f32", template_seed: Optional[int] = None):
-    """A long quasi-periodic stream for the segmentation step (Sec. III-A,
-    Sec. IV-B: a robot repeating its task): ``n_cycles`` warped, noisy copies
+    """A long quasi-periodic stream for the segmentation step (Sec. III-B,
+    Sec. V-A: a robot repeating its task): ``n_cycles`` warped, noisy copies
     of one template, each with about 1 % of its samples dropped in gaps, and
     after each an idle stretch (the last value held, plus noise) of
     U(idle_frac) times the cycle length.  The reference cycle X is one more

@@ -33,9 +33,14 @@ class WtsError(RuntimeError):
         self.status = status
 
 
+# status codes of include/wetsand_mi.h
+(OK, E_ARG, E_SHAPE, E_DTYPE, E_WORKSPACE, E_CAPACITY, E_HIP, E_NONFINITE, E_UNSUPPORTED,
+ E_DEVICE) = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [("cost", ctypes.c_int32), ("rho", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("band", ctypes.c_double)]
+                ("validate", ctypes.c_int32), ("band", ctypes.c_double)]
 
 
 def load():
@@ -56,7 +61,7 @@ def load():
         "wts_dba_iterate": [P, P, P, P, P, P, P, P, SZ, P],
         "wts_anomaly_score": [P, P, P, P, P, P, P, SZ, P],
         "wts_softdtw_forward": [P, P, P, D, P, P, SZ, P],
-        "wts_softdtw_backward": [P, P, P, D, P, SZ, P, P, P, P, SZ, P],
+        "wts_softdtw_backward": [P, P, P, D, P, SZ, P, P, P, I32, P, SZ, P],
         "wts_medoid": [P, P, P, P, P, P, SZ, P],
         "wts_init_barycenter": [P, P, I32, I32, P, P, P],
         "wts_precond_step": [P, P, P, I64, I32, D, P],
@@ -65,6 +70,8 @@ def load():
         "wts_plan_rho": [P, ctypes.c_int],
         "wts_subdtw": [P, P, P, P, P, P, P, SZ, P],
         "wts_softdtw_grad_cycles": [P, P, P, D, P, P, P, SZ, P],
+        "wts_plan_status": [P, P],
+        "wts_barycenter_objective": [P, P, I32, I32, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -85,7 +92,7 @@ def exported_symbols():
             "wts_dtw_align", "wts_dba_iterate", "wts_anomaly_score", "wts_softdtw_forward",
             "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step",
             "wts_plan_timing", "wts_plan_sweep_ms", "wts_plan_rho", "wts_subdtw",
-            "wts_softdtw_grad_cycles"]
+            "wts_softdtw_grad_cycles", "wts_plan_status", "wts_barycenter_objective"]
 
 
 def _check(rc: int):
@@ -101,6 +108,50 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+# ---------------------------------------------------------- argument checks
+# The C ABI takes raw device pointers and trusts their sizes: every tensor is
+# checked here (dtype, device, contiguity, size) before its pointer is passed.
+
+def _need(t, what: str, dtype, device, shape=None, numel=None, min_numel=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor, not %s" % (what, type(t).__name__))
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, not %s" % (what, dtype, t.dtype))
+    if t.device != device:
+        raise ValueError("%s must be on %s, not %s" % (what, device, t.device))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, not %s" % (what, tuple(shape), tuple(t.shape)))
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must hold %d values, not %d" % (what, numel, t.numel()))
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError("%s must hold at least %d values, not %d" % (what, min_numel, t.numel()))
+    return t
+
+
+def _device(plan) -> torch.device:
+    return torch.device("cuda", plan.device)
+
+
+def _bary_arg(plan, t, what: str = "bary"):
+    """A float64 [L][d] barycenter (or reference) on the plan's device."""
+    return _need(t, what, torch.float64, _device(plan), shape=(plan.L, plan.d))
+
+
+def _cycles_arg(plan, t, what: str = "cycles"):
+    """The packed [sum N][d] cycle values of the plan's storage dtype."""
+    dt = torch.float32 if plan.dtype == "f32" else torch.float64
+    return _need(t, what, dt, _device(plan), numel=int(plan.offsets[-1]) * plan.d)
+
+
+def _vec_arg(plan, t, what: str, n: Optional[int] = None, dtype=torch.float64):
+    """An optional [n] vector (None passes through)."""
+    if t is None:
+        return None
+    return _need(t, what, dtype, _device(plan), numel=plan.n if n is None else n)
+
+
 class Plan:
     """A plan binds the cycle lengths, the channel count, the storage dtype and
     the barycenter length L (L = 0: a plan for the medoid only).  band > 0
@@ -108,7 +159,7 @@ class Plan:
     the longer length (Table I)."""
 
     def __init__(self, offsets, d: int, dtype: str, L: int, device: int = 0, cost: str = "sq",
-                 rho: int = 0, grid: int = 0, band: float = 0.0):
+                 rho: int = 0, grid: int = 0, band: float = 0.0, validate: bool = False):
         lib = load()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         self.offsets = off
@@ -117,8 +168,10 @@ class Plan:
         self.dtype = dtype
         self.L = int(L)
         self.device = int(device)
-        opts = _Opts(COST_EUCLID if cost == "euclid" else COST_SQ, int(rho), int(grid), 0,
-                     float(band))
+        if dtype not in ("f32", "f64"):
+            raise ValueError("dtype must be 'f32' or 'f64'")
+        opts = _Opts(COST_EUCLID if cost == "euclid" else COST_SQ, int(rho), int(grid),
+                     1 if validate else 0, float(band))
         h = ctypes.c_void_p()
         _check(lib.wts_plan_create(ctypes.byref(h), self.device, self.n, self.d,
                                    F32 if dtype == "f32" else F64,
@@ -145,6 +198,17 @@ class Plan:
             self._ws[op] = ws
         return ws[2]
 
+    def set_workspace(self, op: int, buf: torch.Tensor):
+        """Installs a caller-owned buffer as the workspace of `op` (uint8 on
+        the plan's device, 256-byte aligned, at least workspace_bytes(op)
+        bytes), for instance a view of memory that other work ordered on the
+        same stream also uses."""
+        nbytes = self.workspace_bytes(op)
+        if nbytes == 0:
+            raise ValueError("this plan cannot run operation %d" % op)
+        _buffer_arg(self, buf, "workspace", nbytes)
+        self._ws[op] = (buf, nbytes, buf[:nbytes])
+
     def enable_timing(self, max_launches: int = 256):
         """Bracket every sweep kernel of this plan with HIP events (eager use only)."""
         _check(load().wts_plan_timing(self._h, int(max_launches)))
@@ -162,6 +226,17 @@ class Plan:
         _check(min(r, 0))
         return r
 
+    def status(self) -> int:
+        """Reads and clears the plan's device status word after synchronising
+        the current stream: OK, E_NONFINITE (a validated call found a NaN or
+        an infinity) or E_DEVICE (a strip gave up waiting, or inconsistent
+        path tags)."""
+        return int(load().wts_plan_status(self._h, _stream()))
+
+    def check(self):
+        """status(), raising WtsError unless it is OK."""
+        _check(self.status())
+
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.wts_plan_destroy(self._h)
@@ -173,15 +248,6 @@ class Plan:
             self.close()
         except Exception:
             pass
-
-
-def device_status(plan: Plan, op: int) -> int:
-    """Status word the kernels of the last `op` call left in its workspace
-    (0 = clean; 1 = a strip gave up waiting; 2 = path recovery inconsistency)."""
-    ws = plan._ws.get(op)
-    if ws is None:
-        return 0
-    return int(ws[2][4:8].view(torch.int32).item())
 
 
 def pack_cycles(cycles: Sequence[np.ndarray], device: int = 0, dtype: Optional[str] = None):
@@ -205,6 +271,8 @@ def dtw_align(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, paths: bool 
     """Eq. 1 per cycle: (dist [n] f64, path_len [n] i64, paths or None).
 
     With paths=True the path rows of cycle k start at k*(L-1) + offsets[k]."""
+    _bary_arg(plan, bary)
+    _cycles_arg(plan, cycles)
     n = plan.n
     dist = torch.empty(n, dtype=torch.float64, device=_dev(plan))
     plen = torch.empty(n, dtype=torch.int64, device=_dev(plan))
@@ -229,12 +297,18 @@ def dba_iterate(plan: Plan, bary_in: torch.Tensor, cycles: torch.Tensor,
                 weights: Optional[torch.Tensor] = None, bary_out: Optional[torch.Tensor] = None,
                 counts: Optional[torch.Tensor] = None, dist: Optional[torch.Tensor] = None):
     """One DBA update: returns (bary_out [L][d] f64, counts [L] i64, dist [n] f64)."""
+    _bary_arg(plan, bary_in, "bary_in")
+    _cycles_arg(plan, cycles)
+    _vec_arg(plan, weights, "weights")
     if bary_out is None:
         bary_out = torch.empty((plan.L, plan.d), dtype=torch.float64, device=_dev(plan))
     if counts is None:
         counts = torch.empty(plan.L, dtype=torch.int64, device=_dev(plan))
     if dist is None:
         dist = torch.empty(plan.n, dtype=torch.float64, device=_dev(plan))
+    _bary_arg(plan, bary_out, "bary_out")
+    _vec_arg(plan, counts, "counts", n=plan.L, dtype=torch.int64)
+    _vec_arg(plan, dist, "dist")
     ws = plan.workspace(OP_DBA)
     _check(load().wts_dba_iterate(plan.handle, _ptr(bary_in), _ptr(cycles), _ptr(weights),
                                   _ptr(bary_out), _ptr(counts), _ptr(dist), _ptr(ws), ws.numel(),
@@ -244,6 +318,8 @@ def dba_iterate(plan: Plan, bary_in: torch.Tensor, cycles: torch.Tensor,
 
 def anomaly_score(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor):
     """Eq. 8: (score [n], dist [n], path_len [n])."""
+    _bary_arg(plan, bary)
+    _cycles_arg(plan, cycles)
     n = plan.n
     score = torch.empty(n, dtype=torch.float64, device=_dev(plan))
     dist = torch.empty(n, dtype=torch.float64, device=_dev(plan))
@@ -255,9 +331,11 @@ def anomaly_score(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor):
 
 
 def subdtw(plan: Plan, x: torch.Tensor, windows: torch.Tensor):
-    """Sec. III-A, Eq. 2: Sub-DTW of the reference x ([L][d] float64) against
+    """Sec. III-B, Eq. 2: Sub-DTW of the reference x ([L][d] float64) against
     every window of the plan's batch: (value [n] f64, a* [n] i64, b* [n] i64),
     0-based columns of each window."""
+    _bary_arg(plan, x, "x")
+    _cycles_arg(plan, windows, "windows")
     n = plan.n
     value = torch.empty(n, dtype=torch.float64, device=_dev(plan))
     a = torch.empty(n, dtype=torch.int64, device=_dev(plan))
@@ -270,6 +348,7 @@ def subdtw(plan: Plan, x: torch.Tensor, windows: torch.Tensor):
 
 def medoid(plan: Plan, cycles: torch.Tensor, with_matrix: bool = True):
     """All-pairs DTW: (medoid index tensor [1] i32, D [n][n] or None, totals [n])."""
+    _cycles_arg(plan, cycles)
     n = plan.n
     Dm = torch.empty((n, n), dtype=torch.float64, device=_dev(plan)) if with_matrix else None
     tot = torch.empty(n, dtype=torch.float64, device=_dev(plan))
@@ -282,6 +361,7 @@ def medoid(plan: Plan, cycles: torch.Tensor, with_matrix: bool = True):
 
 def init_barycenter(plan: Plan, cycles: torch.Tensor, kind: int, index: int = 0):
     """(bary [L][d] f64, index of the cycle used or -1 for the mean)."""
+    _cycles_arg(plan, cycles)
     out = torch.empty((plan.L, plan.d), dtype=torch.float64, device=_dev(plan))
     chosen = ctypes.c_int32(-2)
     _check(load().wts_init_barycenter(plan.handle, _ptr(cycles), int(kind), int(index), _ptr(out),
@@ -289,14 +369,39 @@ def init_barycenter(plan: Plan, cycles: torch.Tensor, kind: int, index: int = 0)
     return out, int(chosen.value)
 
 
-def softdtw_forward(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, gamma: float):
-    """Eq. 3-5: (values [n] f64, checkpoint buffer for softdtw_backward)."""
-    value = torch.empty(plan.n, dtype=torch.float64, device=_dev(plan))
-    nbytes = plan.workspace_bytes(OP_SOFT_FWD)
-    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=_dev(plan))
+def aligned_buffer(nbytes: int, device) -> torch.Tensor:
+    """A 256-byte aligned uint8 view of nbytes on `device` (the view keeps
+    its allocation alive)."""
+    raw = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
     shift = (-raw.data_ptr()) % 256
-    ckpt = raw[shift:shift + nbytes]
-    ckpt._wts_base = raw   # keep the allocation alive with the view
+    buf = raw[shift:shift + int(nbytes)]
+    buf._wts_base = raw
+    return buf
+
+
+def _buffer_arg(plan, t, what: str, nbytes: int):
+    _need(t, what, torch.uint8, _device(plan), min_numel=nbytes)
+    if t.data_ptr() % 256:
+        raise ValueError("%s must be 256-byte aligned" % what)
+    return t
+
+
+def softdtw_forward(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, gamma: float,
+                    ckpt: Optional[torch.Tensor] = None, value: Optional[torch.Tensor] = None):
+    """Eq. 3-5: (values [n] f64, checkpoint buffer for softdtw_backward).
+
+    ckpt: a caller-owned uint8 buffer of at least
+    plan.workspace_bytes(OP_SOFT_FWD) bytes, 256-byte aligned (else one is
+    allocated); value: a float64 [n] output (else allocated)."""
+    _bary_arg(plan, bary)
+    _cycles_arg(plan, cycles)
+    nbytes = plan.workspace_bytes(OP_SOFT_FWD)
+    if ckpt is None:
+        ckpt = aligned_buffer(nbytes, _dev(plan))
+    _buffer_arg(plan, ckpt, "ckpt", nbytes)
+    if value is None:
+        value = torch.empty(plan.n, dtype=torch.float64, device=_dev(plan))
+    _vec_arg(plan, value, "value")
     _check(load().wts_softdtw_forward(plan.handle, _ptr(bary), _ptr(cycles), float(gamma),
                                       _ptr(value), _ptr(ckpt), ckpt.numel(), _stream()))
     return value, ckpt
@@ -304,16 +409,32 @@ def softdtw_forward(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, gamma:
 
 def softdtw_backward(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, gamma: float,
                      ckpt: torch.Tensor, grad_value: Optional[torch.Tensor] = None,
-                     with_mass: bool = False):
-    """Eq. 6-7: grad_bary [L][d] = sum_k grad_value_k dSoft-DTW_k/dB (and row mass)."""
-    grad = torch.empty((plan.L, plan.d), dtype=torch.float64, device=_dev(plan))
-    mass = torch.empty(plan.L, dtype=torch.float64, device=_dev(plan)) if with_mass else None
+                     with_mass: bool = False, grad: Optional[torch.Tensor] = None,
+                     mass: Optional[torch.Tensor] = None, accumulate: bool = False):
+    """Eq. 6-7: grad_bary [L][d] = sum_k grad_value_k dSoft-DTW_k/dB (and row mass).
+
+    grad / mass: caller-owned float64 outputs ([L][d], [L]); with
+    accumulate=True the sums start from their contents (cycle groups)."""
+    _bary_arg(plan, bary)
+    _cycles_arg(plan, cycles)
+    _buffer_arg(plan, ckpt, "ckpt", plan.workspace_bytes(OP_SOFT_FWD))
+    _vec_arg(plan, grad_value, "grad_value")
+    if grad is None:
+        if accumulate:
+            raise ValueError("accumulate needs the grad (and mass) to add to")
+        grad = torch.empty((plan.L, plan.d), dtype=torch.float64, device=_dev(plan))
+    _bary_arg(plan, grad, "grad")
+    if with_mass and mass is None:
+        if accumulate:
+            raise ValueError("accumulate needs the grad (and mass) to add to")
+        mass = torch.empty(plan.L, dtype=torch.float64, device=_dev(plan))
+    _vec_arg(plan, mass, "mass", n=plan.L)
     ws = plan.workspace(OP_SOFT_BWD)
-    gv = None if grad_value is None else grad_value.to(torch.float64).contiguous()
     _check(load().wts_softdtw_backward(plan.handle, _ptr(bary), _ptr(cycles), float(gamma),
-                                       _ptr(ckpt), ckpt.numel(), _ptr(gv), _ptr(grad),
-                                       _ptr(mass), _ptr(ws), ws.numel(), _stream()))
-    return (grad, mass) if with_mass else grad
+                                       _ptr(ckpt), ckpt.numel(), _ptr(grad_value), _ptr(grad),
+                                       _ptr(mass), 1 if accumulate else 0, _ptr(ws), ws.numel(),
+                                       _stream()))
+    return (grad, mass) if mass is not None else grad
 
 
 def softdtw_grad_cycles(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, gamma: float,
@@ -321,13 +442,34 @@ def softdtw_grad_cycles(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, ga
     """Eq. 6 for the cycles: grad [sum N][d] f64, row j of cycle k holding
     grad_value_k dSoft-DTW^gamma(B, C_k)/dc_kj (the sweeps run with the
     cycles on the rows; float32 cycles are widened to float64 first)."""
+    _bary_arg(plan, bary)
+    _cycles_arg(plan, cycles)
+    _vec_arg(plan, grad_value, "grad_value")
     c64 = cycles.to(torch.float64).contiguous()
     grad = torch.empty_like(c64)
     ws = plan.workspace(OP_SOFT_GRAD_C)
-    gv = None if grad_value is None else grad_value.to(torch.float64).contiguous()
     _check(load().wts_softdtw_grad_cycles(plan.handle, _ptr(bary), _ptr(c64), float(gamma),
-                                          _ptr(gv), _ptr(grad), _ptr(ws), ws.numel(), _stream()))
+                                          _ptr(grad_value), _ptr(grad), _ptr(ws), ws.numel(),
+                                          _stream()))
     return grad
+
+
+def barycenter_objective(values: torch.Tensor, weights: Optional[torch.Tensor] = None,
+                         out: Optional[torch.Tensor] = None, accumulate: bool = False):
+    """Eq. 7: out [1] float64 = [out +] sum_k weights_k values_k (ascending k)."""
+    dev = values.device
+    n = values.numel()
+    _need(values, "values", torch.float64, dev, numel=n)
+    if weights is not None:
+        _need(weights, "weights", torch.float64, dev, numel=n)
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs the output to add to")
+        out = torch.empty(1, dtype=torch.float64, device=dev)
+    _need(out, "out", torch.float64, dev, numel=1)
+    _check(load().wts_barycenter_objective(_ptr(values), _ptr(weights), int(n),
+                                           1 if accumulate else 0, _ptr(out), _stream()))
+    return out
 
 
 class SoftDTW(torch.autograd.Function):
@@ -336,7 +478,8 @@ class SoftDTW(torch.autograd.Function):
     Usage: SoftDTW.apply(bary, plan, cycles, gamma) with bary a float64 [L][d]
     tensor and cycles the packed [sum N][d] buffer of the plan; the
     checkpoints of the forward are kept for the backward.  Gradients flow to
-    the barycenter and, when it requires them, to the cycle buffer."""
+    the barycenter and, when it requires them, to the cycle buffer.  The
+    backward reads the plan's status word and raises on a device error."""
 
     @staticmethod
     def forward(ctx, bary, plan, cycles, gamma):
@@ -350,7 +493,7 @@ class SoftDTW(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_value):
         (bary_c,) = ctx.saved_tensors
-        gv = grad_value.contiguous()
+        gv = grad_value.to(torch.float64).contiguous()
         grad_b = grad_c = None
         if ctx.needs_input_grad[0]:
             grad_b = softdtw_backward(ctx.plan, bary_c, ctx.cycles, ctx.gamma, ctx.ckpt, gv)
@@ -358,12 +501,48 @@ class SoftDTW(torch.autograd.Function):
         if ctx.needs_input_grad[2]:
             grad_c = softdtw_grad_cycles(ctx.plan, bary_c, ctx.cycles, ctx.gamma, gv)
             grad_c = grad_c.to(ctx.cycles.dtype)
+        ctx.plan.check()
         return grad_b, None, grad_c, None
+
+
+class SoftDTWObjective(torch.autograd.Function):
+    """f = sum_k w_k Soft-DTW^gamma(B, C_k) (Eq. 7), as a device scalar: the
+    forward sweep gives the values, wts_barycenter_objective folds them in
+    ascending k, and the backward runs the E-matrix sweep with upstream
+    weights w_k times the incoming gradient of f.
+
+    Usage: SoftDTWObjective.apply(bary, plan, cycles, gamma, weights)."""
+
+    @staticmethod
+    def forward(ctx, bary, plan, cycles, gamma, weights):
+        bary_c = bary.detach().contiguous()
+        value, ckpt = softdtw_forward(plan, bary_c, cycles.detach(), gamma)
+        f = barycenter_objective(value, weights)
+        ctx.plan, ctx.cycles, ctx.gamma, ctx.ckpt, ctx.weights = (plan, cycles.detach(), gamma,
+                                                                  ckpt, weights)
+        ctx.save_for_backward(bary_c)
+        return f.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        (bary_c,) = ctx.saved_tensors
+        w = ctx.weights if ctx.weights is not None else torch.ones(
+            ctx.plan.n, dtype=torch.float64, device=bary_c.device)
+        gv = (w * grad_f.to(torch.float64)).contiguous()   # chain rule through the sum
+        grad_b = softdtw_backward(ctx.plan, bary_c, ctx.cycles, ctx.gamma, ctx.ckpt, gv)
+        ctx.ckpt = None
+        ctx.plan.check()
+        return grad_b, None, None, None, None
 
 
 def precond_step(bary: torch.Tensor, grad: torch.Tensor, row_mass: torch.Tensor, eta: float):
     """In place: bary <- bary - eta * grad / (2 row_mass) (Soft-DTW barycenter descent)."""
+    if bary.dim() != 2:
+        raise ValueError("bary must be [L][d]")
     L, d = bary.shape
+    _need(bary, "bary", torch.float64, bary.device)
+    _need(grad, "grad", torch.float64, bary.device, shape=(L, d))
+    _need(row_mass, "row_mass", torch.float64, bary.device, numel=L)
     _check(load().wts_precond_step(_ptr(bary), _ptr(grad), _ptr(row_mass), int(L), int(d),
                                    float(eta), _stream()))
     return bary
@@ -379,6 +558,8 @@ class DBARunner:
 
     def __init__(self, plan: Plan, cycles: torch.Tensor, bary0: torch.Tensor,
                  weights: Optional[torch.Tensor] = None, graph: bool = True):
+        _cycles_arg(plan, cycles)
+        _vec_arg(plan, weights, "weights")
         self.plan, self.cycles, self.weights = plan, cycles, weights
         dev = _dev(plan)
         self.A = bary0.detach().to(device=dev, dtype=torch.float64).contiguous().clone()
@@ -400,8 +581,9 @@ class DBARunner:
         dba_iterate(self.plan, self.A, self.cycles, self.weights, self.B, self.counts, self.dist)
         dba_iterate(self.plan, self.B, self.cycles, self.weights, self.A, self.counts, self.dist)
 
-    def run(self, iters: int) -> torch.Tensor:
-        """Applies `iters` DBA iterations to the current barycenter; returns it."""
+    def run(self, iters: int, check: bool = True) -> torch.Tensor:
+        """Applies `iters` DBA iterations to the current barycenter; returns it.
+        check=True then reads the plan's status word (a synchronisation)."""
         for _ in range(iters // 2):
             if self.graph is not None:
                 self.graph.replay()
@@ -411,10 +593,13 @@ class DBARunner:
             dba_iterate(self.plan, self.A, self.cycles, self.weights, self.B, self.counts,
                         self.dist)
             self.A, self.B = self.B, self.A
+        if check:
+            self.plan.check()
         return self.A
 
 
-def subset_plans(offsets, d: int, dtype: str, L: int, max_ckpt_bytes: int, device: int = 0):
+def subset_plans(offsets, d: int, dtype: str, L: int, max_ckpt_bytes: int, device: int = 0,
+                 band: float = 0.0):
     """Splits a batch into consecutive cycle groups whose Soft-DTW checkpoint
     buffer stays below max_ckpt_bytes.  Returns [(first, last+1, plan)].
 
@@ -436,7 +621,7 @@ def subset_plans(offsets, d: int, dtype: str, L: int, max_ckpt_bytes: int, devic
             tot += est(b)
             b += 1
         while True:
-            plan = Plan(off[a:b + 1] - off[a], d, dtype, L, device=device)
+            plan = Plan(off[a:b + 1] - off[a], d, dtype, L, device=device, band=band)
             if b == a + 1 or plan.workspace_bytes(OP_SOFT_FWD) <= max_ckpt_bytes:
                 break
             plan.close()
@@ -446,36 +631,76 @@ def subset_plans(offsets, d: int, dtype: str, L: int, max_ckpt_bytes: int, devic
     return groups
 
 
+class SoftDescent:
+    """Preconditioned Soft-DTW descent steps (Eq. 7, weights w_k) over cycle
+    groups whose checkpoints fit in memory: per group one forward and one
+    backward (accumulating into one gradient and row mass, which gives
+    bitwise the result of one call over all cycles), the Eq. 7 objective
+    folded the same way, then bary <- bary - eta G / (2 h).
+
+    Every buffer is allocated here, once: the checkpoint buffer is shared by
+    the groups (ckpt: a caller-owned 256-byte aligned uint8 buffer of at
+    least ckpt_bytes(groups) bytes, for instance one that other stream-ordered
+    work also uses; else one is allocated), so step() allocates nothing and
+    can be captured into a graph."""
+
+    def __init__(self, groups, cycles: torch.Tensor, offsets, L: int, d: int, gamma: float,
+                 grad_value: torch.Tensor, eta: float, ckpt: Optional[torch.Tensor] = None):
+        self.groups = groups
+        off = np.asarray(offsets, dtype=np.int64)
+        dev = groups[0][2].device
+        n = off.size - 1
+        self.gamma, self.eta = float(gamma), float(eta)
+        self.parts = []
+        for a, b, plan in groups:
+            Y = cycles[int(off[a]):int(off[b])]
+            _cycles_arg(plan, Y, "cycles of group %d..%d" % (a, b))
+            plan.workspace(OP_SOFT_BWD)
+            self.parts.append((plan, Y, grad_value[a:b], a, b))
+        need = self.ckpt_bytes(groups)
+        self.ckpt = aligned_buffer(need, "cuda:%d" % dev) if ckpt is None else ckpt
+        self.G = torch.empty((L, d), dtype=torch.float64, device="cuda:%d" % dev)
+        self.H = torch.empty(L, dtype=torch.float64, device="cuda:%d" % dev)
+        self.values = torch.empty(n, dtype=torch.float64, device="cuda:%d" % dev)
+        self.objective = torch.empty(1, dtype=torch.float64, device="cuda:%d" % dev)
+        self.grad_value = _need(grad_value, "grad_value", torch.float64, self.G.device, numel=n)
+
+    @staticmethod
+    def ckpt_bytes(groups) -> int:
+        return max(plan.workspace_bytes(OP_SOFT_FWD) for _, _, plan in groups)
+
+    def step(self, bary: torch.Tensor, check: bool = False) -> torch.Tensor:
+        """One descent step on bary (in place); returns the values at the old
+        bary.  The objective sum_k w_k value_k is left in self.objective."""
+        for q, (plan, Y, gv, a, b) in enumerate(self.parts):
+            ck = self.ckpt[:plan.workspace_bytes(OP_SOFT_FWD)]
+            v, _ = softdtw_forward(plan, bary, Y, self.gamma, ckpt=ck, value=self.values[a:b])
+            softdtw_backward(plan, bary, Y, self.gamma, ck, gv, grad=self.G, mass=self.H,
+                             accumulate=q > 0)
+            barycenter_objective(v, gv, out=self.objective, accumulate=q > 0)
+        precond_step(bary, self.G, self.H, self.eta)
+        if check:
+            for _, _, plan in self.groups:
+                plan.check()
+        return self.values
+
+
 def softdtw_descent_step(groups, cycles: torch.Tensor, offsets, bary: torch.Tensor,
                          gamma: float, grad_value: torch.Tensor, eta: float):
-    """One preconditioned Soft-DTW descent step over cycle groups: forward and
-    backward per group (checkpoints freed between groups), gradients and row
-    masses summed group by group, then bary <- bary - eta G / (2 h)."""
-    off = np.asarray(offsets, dtype=np.int64)
-    G = torch.zeros_like(bary)
-    H = torch.zeros(bary.shape[0], dtype=torch.float64, device=bary.device)
-    values = torch.empty(off.size - 1, dtype=torch.float64, device=bary.device)
-    for a, b, plan in groups:
-        Y = cycles[int(off[a]):int(off[b])]
-        v, ck = softdtw_forward(plan, bary, Y, gamma)
-        g, h = softdtw_backward(plan, bary, Y, gamma, ck, grad_value[a:b].contiguous(),
-                                with_mass=True)
-        del ck
-        values[a:b] = v
-        G += g
-        H += h
-    precond_step(bary, G, H, eta)
-    return values
+    """One preconditioned Soft-DTW descent step over cycle groups (see
+    SoftDescent); returns the values at the old bary."""
+    sd = SoftDescent(groups, cycles, offsets, bary.shape[0], bary.shape[1], gamma, grad_value, eta)
+    return sd.step(bary, check=True)
 
 
 def segment_alpha(M: int) -> int:
-    """alpha = 0.15 M (Sec. III-A), in whole samples (rounded down)."""
+    """alpha = 0.15 M (Sec. III-B), in whole samples (rounded down)."""
     return int(0.15 * M)
 
 
 def segment(x: torch.Tensor, streams: Sequence[torch.Tensor], dtype: str,
             alpha: Optional[int] = None, device: int = 0):
-    """The segmentation of Sec. III-A for several streams at once.
+    """The segmentation of Sec. III-B for several streams at once.
 
     Each stream s keeps a window start ws_s (0 at first).  Every round runs
     one Sub-DTW launch over the windows streams[s][ws_s : ws_s + 2M] of the
@@ -535,12 +760,13 @@ def lbfgs_barycenter(plan: Plan, cycles: torch.Tensor, bary0: torch.Tensor, gamm
     supplied by the caller; default 1), at most `max_iter` iterations and
     `max_eval` evaluations of f, stopping on a gradient of max-norm below
     `tolerance_grad` or a change of f or B below `tolerance_change`.  Every
-    evaluation is one forward (checkpoints) and one E-matrix backward on the
-    GPU; torch.optim.LBFGS (strong-Wolfe line search) only combines the
-    resulting [L][d] gradients.  Returns (B, history of f values)."""
+    evaluation is one forward (checkpoints), the Eq. 7 sum and one E-matrix
+    backward on the GPU (SoftDTWObjective); torch.optim.LBFGS (strong-Wolfe
+    line search) only combines the resulting [L][d] gradients.  Returns
+    (B, history of f values)."""
     B = bary0.detach().to(dtype=torch.float64).contiguous().clone().requires_grad_(True)
     w = (torch.ones(plan.n, dtype=torch.float64, device=B.device) if weights is None
-         else weights.to(device=B.device, dtype=torch.float64))
+         else weights.to(device=B.device, dtype=torch.float64).contiguous())
     opt = torch.optim.LBFGS([B], lr=1.0, max_iter=max_iter, max_eval=max_eval,
                             tolerance_grad=tolerance_grad, tolerance_change=tolerance_change,
                             history_size=history_size, line_search_fn="strong_wolfe")
@@ -548,7 +774,7 @@ def lbfgs_barycenter(plan: Plan, cycles: torch.Tensor, bary0: torch.Tensor, gamm
 
     def closure():
         opt.zero_grad()
-        f = (SoftDTW.apply(B, plan, cycles, gamma) * w).sum()
+        f = SoftDTWObjective.apply(B, plan, cycles, gamma, w)
         f.backward()
         hist.append(float(f.detach()))
         return f.detach()

@@ -1,4 +1,4 @@
-"""Host helpers of the detection step (Sec. IV-D): thresholds and F2."""
+"""Host helpers of the detection step (Sec. V-C): thresholds and F2."""
 
 import json
 import os

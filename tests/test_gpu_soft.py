@@ -60,7 +60,7 @@ def test_soft_forward_and_gradient(wts, gamma, d, L, lens):
     grad, mass = wts.softdtw_backward(plan, Bt, Y, gamma, ckpt,
                                       torch.from_numpy(w).cuda(), with_mass=True)
     torch.cuda.synchronize()
-    assert wts.device_status(plan, wts.OP_SOFT_BWD) == 0
+    assert plan.status() == wts.OK
     ov, og, oh = oracle.softdtw_batch(B, [c.astype(np.float64) for c in cyc], gamma, w)
     check_vec(val.cpu().numpy(), ov)
     check_vec(grad.cpu().numpy(), og)
@@ -212,7 +212,7 @@ def test_soft_band_matches_oracle(wts, w, L, lens):
         g, h = wts.softdtw_backward(plan, Bt, Y, gamma, ck, torch.from_numpy(wv).cuda(),
                                     with_mass=True)
         torch.cuda.synchronize()
-        assert wts.device_status(plan, wts.OP_SOFT_BWD) == 0
+        assert plan.status() == wts.OK
         c64 = [np.asarray(c, dtype=np.float64) for c in cs]
         ov, og, oh = oracle.softdtw_batch(B, c64, gamma, wv, band=w)
         check_vec(val.cpu().numpy(), ov)

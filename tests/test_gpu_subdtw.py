@@ -1,4 +1,4 @@
-"""GPU parity of Sub-DTW (Sec. III-A, Eq. 2) and of the segmentation loop
+"""GPU parity of Sub-DTW (Sec. III-B, Eq. 2) and of the segmentation loop
 against the FP64 oracle, through the C ABI.
 
 The Sub-DTW sweep runs the DTW recurrence with a free start in float64 with
@@ -34,7 +34,7 @@ def run_sub(wts, X, windows, dtype=None, **kw):
     Xt = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).cuda()
     v, a, b = wts.subdtw(plan, Xt, Y)
     torch.cuda.synchronize()
-    assert wts.device_status(plan, wts.OP_SUBDTW) == 0
+    assert plan.status() == wts.OK
     return v.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy()
 
 
@@ -119,7 +119,7 @@ def test_subdtw_rejects_euclid_plans(wts):
 
 
 def test_segmentation_matches_oracle(wts):
-    """Sec. III-A loop, three streams segmented together (one Sub-DTW launch
+    """Sec. III-B loop, three streams segmented together (one Sub-DTW launch
     per round): the same cycles, in the same order, with the same costs as
     the oracle's loop on each stream alone."""
     import torch

@@ -413,7 +413,7 @@ def test_euclid_mean_and_nearest_init():
 
 @pytest.mark.parametrize("d", [1, 2])
 def test_subdtw_brute_random_reals(d):
-    """Sec. III-A, Eq. 2: the free-start dynamic program equals the minimum
+    """Sec. III-B, Eq. 2: the free-start dynamic program equals the minimum
     over every subsequence alignment path, with the same (a*, b*)."""
     r = rng(40 + d)
     for _ in range(25):
@@ -461,7 +461,7 @@ def test_subdtw_embedded_copy_and_single_row():
 
 
 def test_segmentation_of_exact_copies():
-    """Sec. III-A segmentation loop on a stream of exact copies of X with idle
+    """Sec. III-B segmentation loop on a stream of exact copies of X with idle
     stretches between them: every copy is found with cost 0."""
     r = rng(47)
     M = 30
