@@ -193,6 +193,11 @@ def ingest_traffic(root: str):
     print(json.dumps(out))
 
 
+def progress(msg: str):
+    """A progress line on stderr (long phases print one every so often)."""
+    print("[bench %s] %s" % (time.strftime("%H:%M:%S"), msg), file=sys.stderr, flush=True)
+
+
 def guarded(fn, *a, **kw):
     """Runs an optional section; an error is reported in its record instead of
     ending the run before the JSON line.  Device memory is released after it."""
@@ -434,9 +439,12 @@ def c5_kernel_times(wts, it, groups):
 def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.1,
                 speedup: bool = True, cpu: bool = True):
     import torch
+    progress("headline: generating the 256-cycle workload and its plans")
     w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, gamma)
     L, d = w.L, w.d
     cells = L * int(w.lengths.sum())
+    progress("headline: %d Soft-DTW groups, arena %.1f GiB; capturing the iteration"
+             % (len(groups), arena.numel() / 2 ** 30))
     # capture the whole iteration once (every allocation was made above)
     s = torch.cuda.Stream(device=dev)
     s.wait_stream(torch.cuda.current_stream(dev))
@@ -448,12 +456,15 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
 
     for _ in range(warmup):
         graph.replay()
+        torch.cuda.synchronize()
+        progress("headline: warm-up iteration done")
     torch.cuda.synchronize()      # one GPU: the barrier of the multi-rank contract is a no-op
     t0 = time.perf_counter()
     for _ in range(steps):
         graph.replay()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    progress("headline: %d timed iterations, %.3f s each" % (steps, (t1 - t0) / steps))
     plan.check()
     for _, _, gp in groups:
         gp.check()
@@ -495,6 +506,7 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
     t_score = e0.elapsed_time(e1) / 1e3
     speed = None
     if speedup:
+        progress("headline: one-cycle-per-launch DBA comparison")
         speed = dba_per_cycle_speedup(wts, plan, off, d, dt, L, Y, it.A, sequential=True)
     Bhost = it.A.cpu().numpy()
     rec = {
@@ -522,6 +534,7 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     if cpu:
+        progress("headline: oracle on the CPU")
         rec["cpu_baseline"] = cpu_baseline_c5(w, Bhost, gamma)
     return rec
 
@@ -1029,10 +1042,10 @@ def main():
         return
     valu = valu_rates()
     tau = valu["tau"]
-    print("valu rates measured (tau %s); headline next" % tau, file=sys.stderr, flush=True)
+    progress("valu rates measured (tau %s)" % tau)
     head = c5_headline(wts, dev, args.steps, args.warmup, tau, speedup=not args.no_speedup,
                        cpu=not args.no_cpu_baseline)
-    print("headline done: %.1f GCUPS" % head["value"], file=sys.stderr, flush=True)
+    progress("headline done: %.1f GCUPS" % head["value"])
     extras = {}
     if not args.no_extras:
         for key, fn, kw in (("c4_soft_dtw", c4_section, {"tau": tau, "steps": args.soft_steps}),
@@ -1041,8 +1054,8 @@ def main():
                              {"speedup": not args.no_speedup}),
                             ("segmentation", segmentation_section,
                              {"speedup": not args.no_speedup})):
+            progress("section %s" % key)
             extras[key] = guarded(fn, wts, dev, **kw)
-            print("section %s done" % key, file=sys.stderr, flush=True)
         if not args.no_cpu_baseline:
             from paper_2404_12134_amd import synth
             extras["c2_cpu_baseline"] = cpu_baseline_c2(synth.make(2))

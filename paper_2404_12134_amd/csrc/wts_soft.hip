@@ -18,11 +18,12 @@
 // where w_s(i, j) = 2^(m_s - r'(i, j)) / sum_s is the normalised weight of
 // (i, j) in the soft-min of its successor s, and e(M-1, N-1) = 1 (the cell
 // that closes the path).  The kernel walks each strip's tiles from the last
-// column to the first: it replays the tile forward, keeping the three base-2
-// exponentials of every cell in registers (float32, normalised in float64
-// when used), then sweeps the tile backwards in
-// "push" form -- each finished cell splits its e into its three predecessors
-// with its own weights -- so no cell ever needs a neighbour's weights.  The
+// column to the first: it replays the tile forward, keeping the normalised
+// weights of the up and left predecessors of every cell in registers
+// (float32), then sweeps the tile backwards in "push" form -- each finished
+// cell splits its e over its three predecessors with its own weights, the
+// diagonal taking what the other two do not, so that the split conserves e
+// to float64 rounding -- and no cell ever needs a neighbour's weights.  The
 // pushes of a strip's top row feed the strip above, so strips are pipelined
 // from the bottom up.  Per row l of the barycenter the kernel accumulates
 // sum_j e(l, j) and sum_j e(l, j) y_j, and the gradient is
@@ -57,6 +58,13 @@ __device__ __forceinline__ double shl1_f64(double v, double old) {
 }
 
 constexpr int kRing = 128;   // Y columns in LDS (>= 16 + 63 for a tile, power of 2)
+// The ring holds kRing + 16 slots: slots kRing .. kRing + 15 mirror slots
+// 0 .. 15, so the 16 steps of a group read consecutive slots yb .. yb + 15
+// from one base (immediate LDS offsets, no wrap-around per step).
+__device__ __forceinline__ void ring_put(double* row, int slot, double v) {
+  row[slot] = v;
+  if (slot < 16) row[slot + kRing] = v;
+}
 constexpr int kTile = 16;    // sweep steps per checkpoint / replay tile
 
 // Soft-min of the three predecessors in scaled units.  Returns the soft-min
@@ -135,8 +143,8 @@ template <typename TY, int D, int RHO, bool BAND>
 __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
   constexpr int H = kWave * RHO;
   constexpr int kChunk = 64;
-  __shared__ double ys[D][kRing];
-  __shared__ double binr[kChunk];
+  __shared__ double ys[D][kRing + 16];
+  __shared__ double binr[kChunk];       // the strip above's bottom row (+inf for the top strip)
   __shared__ double bor[kRing];
   __shared__ int s_item;
   const int lane = threadIdx.x;
@@ -192,7 +200,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
       for (int c = 0; c < D; ++c)
         yv[c] = lane < N ? static_cast<double>(Y[(pd.y_off + lane) * D + c]) : 0.0;
 #pragma unroll
-      for (int c = 0; c < D; ++c) ys[c][lane] = yv[c];
+      for (int c = 0; c < D; ++c) ring_put(ys[c], lane, yv[c]);
     }
     __syncthreads();
 
@@ -242,6 +250,8 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
         const int jn = t0 + kChunk + lane;
         have_next = more && seen_prev >= min(N, t0 + 2 * kChunk);
         if (have_next) pr_next = jn < N ? ld_dev(row_in + jn) : INF;
+      } else {
+        binr[lane] = INF;
       }
       __syncthreads();
 
@@ -254,18 +264,19 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
           for (int r = 0; r < RHO; ++r) p[r * kWave] = left[r];
           p[RHO * kWave] = upprev;
         }
+        const int yb = (tg - lane) & (kRing - 1);   // ring slot of step 0's column
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int t = tg + u;
           const int j = t - lane;
-          const double bval = has_prev ? binr[tb + u] : INF;
+          const double bval = binr[tb + u];
           const double upin = shr1_f64(bot, bval);
           const double dg0 = upprev;
           upprev = upin;
           if (FULL || (j >= 0 && j < N)) {
             double y[D];
 #pragma unroll
-            for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
+            for (int c = 0; c < D; ++c) y[c] = ys[c][yb + u];
             double dg = dg0, up = upin;
             // band coordinate of row ib at column j (exact in float64)
             const double bd0 = (double)ib * (double)(N - 1) - (double)j * (double)(M - 1);
@@ -333,7 +344,8 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
       if (more) {
         const int j = t0 + kChunk + lane;
 #pragma unroll
-        for (int c = 0; c < D; ++c) ys[c][j & (kRing - 1)] = j < N ? static_cast<double>(yraw[c]) : 0.0;
+        for (int c = 0; c < D; ++c)
+          ring_put(ys[c], j & (kRing - 1), j < N ? static_cast<double>(yraw[c]) : 0.0);
       }
       __syncthreads();
     }
@@ -355,12 +367,14 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
 
 // -------------------------------------------------------------- backward
 
-// The band test needs a few more registers: the banded instance is held to
-// two resident waves per SIMD (the unbanded one fits them by itself).
+// Occupancy: the unbanded instance is held to three resident waves per SIMD
+// (168 VGPRs; a few values of the tile setup spill), measured 5 % faster than
+// two waves without spills; the band test needs more registers, so the
+// banded instance is held to two.
 template <typename TY, int D, int RHO, bool BAND>
-__global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs a) {
+__global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs a) {
   constexpr int H = kWave * RHO;
-  __shared__ double ys[D][kRing];
+  __shared__ double ys[D][kRing + 16];
   __shared__ double bin_fwd[kTile];        // lane 0's upper input for the replay
   __shared__ double bin_up[kTile];         // lane 63's pushes from the strip below
   __shared__ double bin_dg[kTile];
@@ -391,6 +405,20 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
     const bool has_above = s > 0;            // a strip above consumes our top-row pushes
     const bool has_below = s + 1 < pd.S;     // the strip below feeds our bottom row
     const int G = pd.WT;                     // 16-step tiles
+    // Sakoe-Chiba band: a tile whose columns (tg - 63 .. tg + 15 over the
+    // lanes) all lie outside the band of the strip's rows has e = 0 in every
+    // cell (a cell outside the band gets nothing from its successors: their
+    // weight towards a +inf cell is 0), so the sweep runs tiles g_lo .. g_hi
+    // only.  The strip above never reads pushes right of our tiles (the
+    // band's right edge moves right from row to row); the columns left of
+    // them are published as zeros at the end.
+    int g_lo = 0, g_hi = G - 1;
+    if (BAND) {
+      int jlo_b, jhi_b;
+      band_strip_cols(M, N, a.band, i0, min(i0 + H, M) - 1, &jlo_b, &jhi_b);
+      g_hi = min(G - 1, (jhi_b + kWave - 1) / 16);   // last tile with tg - 63 <= jhi_b
+      g_lo = min(g_hi, jlo_b / 16);                  // first tile with tg + 15 >= jlo_b
+    }
     const double* row_fwd = a.rows + pd.aux_base + (int64_t)(s - 1) * N;
     const double* st = a.states + pd.state_base + (int64_t)s * G * (RHO + 1) * kWave;
     const __amdgpu_buffer_rsrc_t rf_in = rsrc(row_fwd, has_above ? N * 8 : 0);
@@ -400,11 +428,12 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
     double* pd_row = a.push_dg + pd.bnd_base;
     int* prog_below = a.progress + pd.flag_base + s + 1;
     int* prog_self = a.progress + pd.flag_base + s;
-    // the cell that closes the path, (M-1, N-1), receives e = 1
+    // the cell that closes the path, (M-1, N-1), receives e = 1: it is
+    // pending as a left push into that cell before the sweep starts (lane
+    // k_last computes no cell of its rows to the right of column N-1)
     const bool last = s + 1 == pd.S;
     const int k_last = (M - 1 - i0) / RHO;
     const int r_last = (M - 1 - i0) - k_last * RHO;
-    const int t_inj = last ? N - 1 + k_last : -1;
 
     double xr[RHO][D];
 #pragma unroll
@@ -418,7 +447,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
 #pragma unroll
     for (int r = 0; r < RHO; ++r) {
       acc_e[r] = 0.0;
-      pl[r] = 0.0;
+      pl[r] = (last && lane == k_last && r == r_last) ? 1.0 : 0.0;
       pdg[r] = 0.0;
 #pragma unroll
       for (int c = 0; c < D; ++c) acc_ey[r][c] = 0.0;
@@ -443,21 +472,23 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
       rf_n = __builtin_bit_cast(
           double, __builtin_amdgcn_raw_buffer_load_b64(rf_in, lane < kTile && j < N ? j * 8 : kDrop, 0, 0));
     };
-    load_tile_inputs(G - 1);
+    load_tile_inputs(g_hi);
 
-    // Y columns of the last tile
+    // Y columns of the first tile swept
     {
-      const int jlo = 16 * (G - 1) - (kWave - 1);
+      const int jlo = 16 * g_hi - (kWave - 1);
       for (int q = lane; q < 16 + kWave - 1; q += kWave) {
         const int j = jlo + q;
 #pragma unroll
         for (int c = 0; c < D; ++c)
-          ys[c][j & (kRing - 1)] = (j >= 0 && j < N) ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0;
+          ring_put(ys[c], j & (kRing - 1),
+                   (j >= 0 && j < N) ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0);
       }
     }
 
-    for (int g = G - 1; g >= 0; --g) {
+    for (int g = g_hi; g >= g_lo; --g) {
       const int tg = 16 * g;
+      const int yb = (tg - lane) & (kRing - 1);   // ring slot of step 0's column
       // next tile's 16 new Y columns, stored after this tile
       // (unconditional loads from a clamped column, kept in the storage type
       // until the store: a conditional load would be waited for on the spot)
@@ -515,7 +546,10 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
       for (int r = 0; r < RHO; ++r) left[r] = st_n[r];
       double upprev = st_n[RHO];
       double bot = left[RHO - 1];
-      float wd[16][RHO], wu[16][RHO], wl[16][RHO];
+      // normalised soft-min weights of the up and left predecessors (the
+      // diagonal takes the rest of the cell's e, so every cell passes on
+      // exactly what it received)
+      float wu[16][RHO], wl[16][RHO];
       const bool full = tg >= kWave - 1 && tg + 16 <= N;
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
@@ -527,7 +561,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
         if (full || (j >= 0 && j < N)) {
           double y[D];
 #pragma unroll
-          for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
+          for (int c = 0; c < D; ++c) y[c] = ys[c][yb + u];
           double dg = dgi, up = upin;
           const double bd0 = (double)ib * (double)(N - 1) - (double)j * (double)(M - 1);
 #pragma unroll
@@ -539,18 +573,18 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
               const bool inb = __builtin_fabs(bd0 + (double)r * (double)(N - 1)) <= band_b;
               const SoftMin sm = softmin3_band(dg, up, lf, inb);
               const double rv = inb ? sq_cost<D>(xr[r], y) * k + sm.v : INF;
-              wd[u][r] = inb ? sm.ed : 1.0f;
-              wu[u][r] = inb ? sm.eu : 0.0f;
-              wl[u][r] = inb ? sm.el : 0.0f;
+              const float rs = __builtin_amdgcn_rcpf(inb ? sm.s : 1.0f);
+              wu[u][r] = inb ? sm.eu * rs : 0.0f;
+              wl[u][r] = inb ? sm.el * rs : 0.0f;
               dg = lf;
               up = rv;
               left[r] = rv;
             } else {
               const SoftMin sm = softmin3(dg, up, lf);
               const double rv = sq_cost<D>(xr[r], y) * k + sm.v;
-              wd[u][r] = sm.ed;   // unnormalised; normalised in float64 below
-              wu[u][r] = sm.eu;
-              wl[u][r] = sm.el;
+              const float rs = __builtin_amdgcn_rcpf(sm.s);   // s >= 1: the minimum's term is 1
+              wu[u][r] = sm.eu * rs;
+              wl[u][r] = sm.el * rs;
               dg = lf;
               up = rv;
               left[r] = rv;
@@ -581,25 +615,23 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
         if (full || (j >= 0 && j < N)) {
           double y[D];
 #pragma unroll
-          for (int c = 0; c < D; ++c) y[c] = ys[c][j & (kRing - 1)];
+          for (int c = 0; c < D; ++c) y[c] = ys[c][yb + u];
           double below_up = recv_up;         // push up from (i+1, j)
           double new_pdg[RHO];
 #pragma unroll
           for (int r = RHO - 1; r >= 0; --r) {
             const double din = (r == RHO - 1) ? recv_dg : pdg[r];
-            double e = (below_up + pl[r]) + din;
-            if (t == t_inj && lane == k_last && r == r_last) e += 1.0;
-            // normalise the three weights in float64 so that every cell passes
-            // on exactly the mass it received (a float32 reciprocal would leak
-            // ~1e-8 per cell, which adds up over tens of thousands of cells)
-            const double xd = (double)wd[u][r], xu = (double)wu[u][r], xl = (double)wl[u][r];
-            const double sw = (xd + xu) + xl;
-            double inv = __builtin_amdgcn_rcp(sw);
-            inv = __builtin_fma(inv, __builtin_fma(-sw, inv, 1.0), inv);
-            const double en = e * inv;
-            below_up = en * xu;
-            pl[r] = en * xl;
-            const double dpush = en * xd;
+            const double e = (below_up + pl[r]) + din;
+            // split e over the three predecessors in float64: up and left by
+            // their weights, the diagonal takes the rest, so the three pushes
+            // add up to e to float64 rounding (weights that summed to 1 only
+            // to float32 rounding would leak ~1e-8 of the mass per cell, which
+            // adds up over tens of thousands of cells)
+            const double pu_ = e * (double)wu[u][r];
+            const double pl_ = e * (double)wl[u][r];
+            const double dpush = (e - pu_) - pl_;
+            below_up = pu_;
+            pl[r] = pl_;
             if (r > 0) new_pdg[r - 1] = dpush;
             else dg0 = dpush;
             acc_e[r] += e;
@@ -635,11 +667,39 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 1) void soft_bwd_kernel(SoftArgs 
       if (g > 0 && lane < 16) {
         const bool in = jn >= 0 && jn < N;
 #pragma unroll
-        for (int c = 0; c < D; ++c) ys[c][jn & (kRing - 1)] = in ? static_cast<double>(yraw[c]) : 0.0;
+        for (int c = 0; c < D; ++c)
+          ring_put(ys[c], jn & (kRing - 1), in ? static_cast<double>(yraw[c]) : 0.0);
       }
       __syncthreads();
     }
     if (has_above) {   // the last tile's columns
+      if (BAND && g_lo > 0) {
+        // columns 0 .. 16 g_lo - 1 of the top row push nothing: zeros, written
+        // once the strip below has finished with the shared row (it writes
+        // its own pushes for us there)
+        if (has_below && !gave_up) {
+          int got = 0, quit = 0;
+          if (lane == 0) {
+            int polls = 0;
+            got = ld_dev(prog_below);
+            while (got < N) {
+              poll_backoff(polls, a.relaxed_wait);
+              if (++polls > kSpinLimit) {
+                atomicOr(a.status, kStatusSpinTimeout);
+                quit = 1;
+                break;
+              }
+              got = ld_dev(prog_below);
+            }
+          }
+          gave_up = __builtin_amdgcn_readfirstlane(quit) != 0;
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        for (int j = lane; j < 16 * g_lo; j += kWave) {
+          st_dev(pu_out, j * 8, 0.0);
+          st_dev(pd_out, j * 8, 0.0);
+        }
+      }
       mem_drain();
       if (lane == 0) st_dev(prog_self, N);
     }

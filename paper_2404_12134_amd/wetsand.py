@@ -441,9 +441,14 @@ def softdtw_grad_cycles(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor, ga
                         grad_value: Optional[torch.Tensor] = None):
     """Eq. 6 for the cycles: grad [sum N][d] f64, row j of cycle k holding
     grad_value_k dSoft-DTW^gamma(B, C_k)/dc_kj (the sweeps run with the
-    cycles on the rows; float32 cycles are widened to float64 first)."""
+    cycles on the rows; cycles of the plan's dtype are widened to float64
+    first, float64 cycles are taken as they are)."""
     _bary_arg(plan, bary)
-    _cycles_arg(plan, cycles)
+    if cycles.dtype == torch.float64:    # already widened (any plan dtype)
+        _need(cycles, "cycles", torch.float64, _device(plan),
+              numel=int(plan.offsets[-1]) * plan.d)
+    else:
+        _cycles_arg(plan, cycles)
     _vec_arg(plan, grad_value, "grad_value")
     c64 = cycles.to(torch.float64).contiguous()
     grad = torch.empty_like(c64)

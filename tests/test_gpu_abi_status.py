@@ -123,10 +123,11 @@ def test_objective_is_the_ordered_weighted_sum(wts):
     for k in range(w.n):
         s = s + wv[k] * vh[k]
     assert f.item() == s
+    ov = oracle.softdtw_batch(B0.cpu().numpy(), cyc, 0.5, grad=False)
+    assert abs(f.item() - float(np.dot(wv, ov))) <= 1e-4 * abs(float(np.dot(wv, ov)))
+    # accumulate = 1 continues the fold from the value in out (here: in place)
     f2 = wts.barycenter_objective(v, None, out=f, accumulate=True)
     s2 = s
     for k in range(w.n):
         s2 = s2 + 1.0 * vh[k]
     assert f2.item() == s2
-    ov = oracle.softdtw_batch(B0.cpu().numpy(), cyc, 0.5, grad=False)
-    assert abs(f.item() - float(np.dot(wv, ov))) <= 1e-4 * abs(float(np.dot(wv, ov)))

@@ -175,8 +175,16 @@ def test_grad_cycles_rejects_bad_arguments(wts):
     with pytest.raises(wts.WtsError):
         wts.softdtw_grad_cycles(plan, Bt, Y, float("inf"))
     mplan = wts.Plan([0, 5], 2, "f64", 0)   # medoid-only plan: no barycenter
-    with pytest.raises(wts.WtsError):
+    with pytest.raises(ValueError):         # the binding: a [0][2] barycenter is expected
         wts.softdtw_grad_cycles(mplan, Bt, Y, 1.0)
+    # the C ABI itself refuses the plan before any launch
+    import ctypes
+    out = torch.empty_like(Y)
+    ws = wts.aligned_buffer(1 << 16, "cuda:0")
+    rc = wts.load().wts_softdtw_grad_cycles(mplan.handle, wts._ptr(Bt), wts._ptr(Y),
+                                            ctypes.c_double(1.0), None, wts._ptr(out),
+                                            wts._ptr(ws), ws.numel(), None)
+    assert rc == wts.E_ARG
     assert torch.isfinite(wts.softdtw_grad_cycles(plan, Bt, Y, 1.0)).all()
     assert plan.rho(wts.OP_SOFT_GRAD_C) == plan.rho(wts.OP_SOFT_FWD) == 2
     assert plan.workspace_bytes(wts.OP_SOFT_GRAD_C) > 0
