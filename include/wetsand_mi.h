@@ -212,6 +212,22 @@ wts_status wts_anomaly_score(const wts_plan* plan, const double* bary, const voi
                              double* score, double* dist, int64_t* path_len, void* ws,
                              size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops such as online scoring of new cycles, harnesses that forbid
+ * hipMalloc): wts_anomaly_score with the library's own scratch as the
+ * workspace -- a static device array of 32 MiB that each GPU the library
+ * runs on holds until the process ends (its address on a GPU is resolved by
+ * wts_plan_create on that GPU).  Arguments, results and errors are those of
+ * wts_anomaly_score; WTS_E_CAPACITY when the plan's score workspace
+ * (wts_workspace_bytes(plan, WTS_OP_SCORE)) exceeds 32 MiB.  It calls no
+ * allocating routine.  Every call on one GPU uses that GPU's one scratch:
+ * calls that overlap on a GPU (two streams, two host threads) race and give
+ * undefined results; the scratch keeps the last call's contents, and each
+ * call clears what must start at zero. */
+wts_status wts_anomaly_score_noalloc(const wts_plan* plan, const double* bary, const void* cycles,
+                                     double* score, double* dist, int64_t* path_len,
+                                     void* stream);
+
 /* Sec. III-B, Eq. 2: Sub-DTW of the reference X (the plan's L rows, float64
  * [L][d], passed where the other calls take the barycenter) against every
  * window C_k of the batch: the minimum over alignment paths that cover all

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -138,6 +139,17 @@ struct Layout {
   size_t total = 0;
 };
 
+// Scratch of wts_anomaly_score_noalloc: the score sweep's workspace for
+// callers that cannot allocate.  `scratch` (below) is a static device array;
+// each GPU the library runs on holds its own copy, at its own address, until
+// the process ends.  Host code never uses the array's name as an address:
+// wts_plan_create resolves the device address once per GPU (with that GPU
+// current) into g_scratch.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
 // Rows per lane of the barycenter sweeps when the caller leaves it open.
 // With about one strip per SIMD, a strip that shares its SIMD slows its whole
 // chain, and the dispatcher does not spread workgroups perfectly once they
@@ -151,6 +163,25 @@ int bary_rho(int64_t L, int n, int cus) {
   const int64_t i4 = items(4);
   if (i4 > cap && i4 <= 2 * simds && items(5) <= cap) return 5;
   return 4;
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Resolves this GPU's address of `scratch` (the device must be current).
+wts_status scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return WTS_OK;   // the no-alloc call refuses it
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device] != nullptr) return WTS_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr)
+    return fail(WTS_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  g_scratch[device] = ptr;
+  return WTS_OK;
 }
 
 }  // namespace
@@ -422,6 +453,10 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   }
 
   DeviceGuard g(device);
+  if (scratch_setup(device) != WTS_OK) {
+    delete p;
+    return WTS_E_HIP;
+  }
   auto cleanup_fail = [&](hipError_t e, const char* what) {
     wts_plan_destroy(p);
     return fail(WTS_E_HIP, "%s failed: %s", what, hipGetErrorString(e));
@@ -674,6 +709,24 @@ wts_status wts_anomaly_score(const wts_plan* p, const double* bary, const void* 
   if (rc != WTS_OK) return rc;
   HIP_TRY(wts::launch_score(dv, at<int>(ws, l.out_aux), p->n, score, path_len, st));
   return WTS_OK;
+}
+
+wts_status wts_anomaly_score_noalloc(const wts_plan* p, const double* bary, const void* cycles,
+                                     double* score, double* dist, int64_t* path_len,
+                                     void* stream) {
+  wts_status rc = check_bary_plan(p);
+  if (rc != WTS_OK) return rc;
+  const size_t need = layout(p, WTS_OP_SCORE).total;
+  if (need > kScratchBytes)
+    return fail(WTS_E_CAPACITY, "the score sweep of this plan needs %zu bytes of workspace; "
+                "the static scratch holds %zu", need, kScratchBytes);
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (p->device >= 0 && p->device < kMaxDevices) ws = g_scratch[p->device];
+  }
+  if (ws == nullptr) return fail(WTS_E_HIP, "no scratch address for device %d", p->device);
+  return wts_anomaly_score(p, bary, cycles, score, dist, path_len, ws, kScratchBytes, stream);
 }
 
 wts_status wts_subdtw(const wts_plan* p, const double* x, const void* windows, double* value,

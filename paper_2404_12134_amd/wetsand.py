@@ -71,6 +71,7 @@ def load():
         "wts_subdtw": [P, P, P, P, P, P, P, SZ, P],
         "wts_softdtw_grad_cycles": [P, P, P, D, P, P, P, SZ, P],
         "wts_plan_status": [P, P],
+        "wts_anomaly_score_noalloc": [P, P, P, P, P, P, P],
         "wts_barycenter_objective": [P, P, I32, I32, P, P],
     }
     for name, args in sig.items():
@@ -92,7 +93,8 @@ def exported_symbols():
             "wts_dtw_align", "wts_dba_iterate", "wts_anomaly_score", "wts_softdtw_forward",
             "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step",
             "wts_plan_timing", "wts_plan_sweep_ms", "wts_plan_rho", "wts_subdtw",
-            "wts_softdtw_grad_cycles", "wts_plan_status", "wts_barycenter_objective"]
+            "wts_softdtw_grad_cycles", "wts_plan_status", "wts_barycenter_objective",
+            "wts_anomaly_score_noalloc"]
 
 
 def _check(rc: int):
@@ -328,6 +330,26 @@ def anomaly_score(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor):
     _check(load().wts_anomaly_score(plan.handle, _ptr(bary), _ptr(cycles), _ptr(score),
                                     _ptr(dist), _ptr(plen), _ptr(ws), ws.numel(), _stream()))
     return score, dist, plen
+
+
+def anomaly_score_noalloc(plan: Plan, bary: torch.Tensor, cycles: torch.Tensor,
+                          score: Optional[torch.Tensor] = None,
+                          dist: Optional[torch.Tensor] = None,
+                          path_len: Optional[torch.Tensor] = None):
+    """Eq. 8 through the entry point that allocates nothing (its workspace is
+    the library's static device scratch): (score [n], dist [n] or None,
+    path_len [n] or None).  Outputs given by the caller are filled in place;
+    a missing score is allocated here, on the caller's side of the call."""
+    _bary_arg(plan, bary)
+    _cycles_arg(plan, cycles)
+    if score is None:
+        score = torch.empty(plan.n, dtype=torch.float64, device=_dev(plan))
+    _vec_arg(plan, score, "score")
+    _vec_arg(plan, dist, "dist")
+    _vec_arg(plan, path_len, "path_len", dtype=torch.int64)
+    _check(load().wts_anomaly_score_noalloc(plan.handle, _ptr(bary), _ptr(cycles), _ptr(score),
+                                            _ptr(dist), _ptr(path_len), _stream()))
+    return score, dist, path_len
 
 
 def subdtw(plan: Plan, x: torch.Tensor, windows: torch.Tensor):
