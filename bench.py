@@ -191,6 +191,34 @@ def ingest_traffic(root: str):
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
+    # issued VALU instructions per cell (SQ_INSTS_VALU counts wave
+    # instructions: x 64 lanes / cells), from a pass over one iteration of
+    # the headline ('c5' phase, --steps 1): the launches of one kernel cover
+    # one DP pass together
+    cells = {}
+    for f in glob.glob(os.path.join(root, "**", "*.out"), recursive=True):
+        for line in open(f, errors="replace"):
+            if line.startswith("{") and '"phase": "c5"' in line:
+                cells["c5"] = json.loads(line)["cells_per_pass"]
+    per_cell = {}
+    if "c5" in cells:
+        tot = {}
+        for (phase, kn, cname, _, _), v in per_dispatch.items():
+            if phase == "c5" and cname == "SQ_INSTS_VALU":
+                tot[kn.split("(wts::")[0]] = tot.get(kn.split("(wts::")[0], 0.0) + v
+        for key, pattern in KERNELS.items():
+            if not key.startswith("c5"):
+                continue
+            pre, post = pattern.split("{rho}")
+            for kn, v in tot.items():
+                if kn.startswith(pre) and kn.endswith(post):
+                    per_cell[key] = round(v * 64 / cells["c5"], 2)
+    if per_cell:
+        rec = {"source_hash": kernel_source_hash(), "per_cell": per_cell,
+               "note": "SQ_INSTS_VALU x 64 / cells of one pass, headline workload"}
+        with open(os.path.join(ROOT, "profiles", "valu_issued.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
 
 
 def progress(msg: str):
