@@ -143,6 +143,7 @@ def ingest_traffic(root: str):
     import glob
     hashes = set()
     used = {}              # sweep key -> the kernel instance its phase ran
+    last = {}              # kernel instance -> count of its final dispatches that count
     for f in glob.glob(os.path.join(root, "**", "*.out"), recursive=True):
         for line in open(f, errors="replace"):
             if line.startswith("{") and '"phase"' in line:
@@ -150,6 +151,9 @@ def ingest_traffic(root: str):
                 hashes.add(rec.get("source_hash"))
                 for k, v in (rec.get("kernels") or {}).items():
                     used[k] = v
+                for k, v in (rec.get("last_dispatches") or {}).items():
+                    if k in (rec.get("kernels") or {}):
+                        last[rec["kernels"][k].replace("void ", "")] = v
     if hashes != {kernel_source_hash()}:
         raise SystemExit("counter passes under %s ran kernel sources %s, not the current %s"
                          % (root, sorted(map(str, hashes)), kernel_source_hash()))
@@ -157,8 +161,22 @@ def ingest_traffic(root: str):
     for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
         phase = os.path.relpath(f, root).split(os.sep)[0].split("_")[0]
         for r in csv.DictReader(open(f)):
-            key = (phase, r["Kernel_Name"], r["Counter_Name"], f, r["Dispatch_Id"])
+            key = (phase, r["Kernel_Name"], r["Counter_Name"], f, int(r["Dispatch_Id"]))
             per_dispatch[key] = per_dispatch.get(key, 0.0) + float(r["Counter_Value"])
+    # a phase that tunes first (the sweep-shape candidates run the same kernel
+    # instances) names how many of each kernel's final dispatches are its own
+    if last:
+        keep = {}
+        for (phase, kn, cname, f, dsp), v in per_dispatch.items():
+            keep.setdefault((phase, kn.split("(wts::")[0], cname, f), []).append((dsp, v))
+        per_dispatch = {}
+        for (phase, kn, cname, f), lst in keep.items():
+            lst.sort()
+            n_last = last.get(kn.replace("void ", ""))
+            if n_last:
+                lst = lst[-n_last:]
+            for dsp, v in lst:
+                per_dispatch[(phase, kn, cname, f, dsp)] = v
     vals = {}
     for (phase, kn, cname, _, _), v in per_dispatch.items():
         vals.setdefault((phase, kn.split("(wts::")[0], cname), []).append(v)
@@ -212,7 +230,8 @@ def ingest_traffic(root: str):
             pre, post = pattern.split("{rho}")
             for kn, v in tot.items():
                 if kn.startswith(pre) and kn.endswith(post):
-                    per_cell[key] = round(v * 64 / cells["c5"], 2)
+                    per_cell[key] = {"kernel": kn.replace("void ", ""),
+                                     "per_cell": round(v * 64 / cells["c5"], 2)}
     if per_cell:
         rec = {"source_hash": kernel_source_hash(), "per_cell": per_cell,
                "note": "SQ_INSTS_VALU x 64 / cells of one pass, headline workload"}
@@ -355,18 +374,21 @@ def kname(key: str, rho: int) -> str:
     return KERNELS[key].format(rho=rho).replace("void ", "")
 
 
-def issued_per_cell():
-    """Issued VALU instructions per cell of each sweep (rocprofv3
-    SQ_INSTS_VALU / cells), from the committed counter summary, if it was
-    taken on the current kernel source."""
+def issued_per_cell(key: str, name: str):
+    """Issued VALU instructions per cell of one sweep kernel instance
+    (rocprofv3 SQ_INSTS_VALU / cells), from the committed counter summary, if
+    it was taken on the current kernel source and on that instance."""
     p = os.path.join(ROOT, "profiles", "valu_issued.json")
     try:
         rec = json.load(open(p))
     except (OSError, ValueError):
-        return {}
+        return None
     if rec.get("source_hash") != kernel_source_hash():
-        return {}
-    return rec.get("per_cell", {})
+        return None
+    hit = rec.get("per_cell", {}).get(key)
+    if not isinstance(hit, dict) or hit.get("kernel") != name.replace("void ", ""):
+        return None
+    return hit.get("per_cell")
 
 
 def roofline(key: str, rho: int, ops: float, seconds: float, launches: int, cells: float,
@@ -383,7 +405,7 @@ def roofline(key: str, rho: int, ops: float, seconds: float, launches: int, cell
            "traffic": None if tr is None else round(tr, 1), "ops_per_cell": ops_per_cell,
            "cells_per_launch": int(cells / launches),
            "launch_ms": round(seconds / launches * 1e3, 3)}
-    iss = issued_per_cell().get(key)
+    iss = issued_per_cell(key, name)
     if iss is not None:
         rec["issued_valu_per_cell"] = iss
     return rec
@@ -427,20 +449,43 @@ class BarycenterIteration:
                 self.ev[1].elapsed_time(self.ev[2]) / 1e3)
 
 
-def c5_setup(wts, dev, gamma: float = 0.1, max_group_gib: float = 215.0):
+def c5_setup(wts, dev, gamma: float = 0.1, max_group_gib: float = 215.0, tune: bool = False):
+    """The headline's plans, arena and iteration.  tune=True first times the
+    sweep shapes on the workload itself (DBA: 4 or 5 rows per lane x grid
+    candidates; Soft-DTW: grid candidates on the first checkpoint group),
+    every candidate using the arena as its workspace."""
     import numpy as np
     import torch
-    from paper_2404_12134_amd import synth
+    from paper_2404_12134_amd import autotune, synth
     w = synth.make(5)
     Y, off, dt = wts.pack_cycles(w.cycles)
     plan = wts.Plan(off, w.d, dt, w.L)
     groups = wts.subset_plans(off, w.d, dt, w.L, int(max_group_gib * 2 ** 30))
     arena_bytes = max(plan.workspace_bytes(wts.OP_DBA), wts.SoftDescent.ckpt_bytes(groups))
     arena = wts.aligned_buffer(arena_bytes, dev)
-    plan.set_workspace(wts.OP_DBA, arena)
     B0, _ = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
+    tuned = None
+    if tune:
+        cus = torch.cuda.get_device_properties(dev).multi_processor_count
+        shapes = [(r, g) for r in (4, 5) for g in autotune.grid_candidates("dba", cus)]
+        td = autotune.tune(off, w.d, dt, w.L, op="dba", cycles=Y, bary=B0, reps=1,
+                           cache_path=None, shapes=shapes, workspace=arena)
+        a, b, _ = groups[0]
+        ts = autotune.tune(off[a:b + 1] - off[a], w.d, dt, w.L, op="soft",
+                           cycles=Y[int(off[a]):int(off[b])], bary=B0, reps=1, cache_path=None,
+                           workspace=arena)
+        for _, _, gp in groups:
+            gp.close()
+        plan.close()
+        plan = wts.Plan(off, w.d, dt, w.L, rho=td["rho"], grid=td["grid"])
+        groups = wts.subset_plans(off, w.d, dt, w.L, int(max_group_gib * 2 ** 30),
+                                  grid=ts["grid"])
+        tuned = {"dba": {k: td[k] for k in ("rho", "grid", "table")},
+                 "soft": {k: ts[k] for k in ("rho", "grid", "table")}}
+    plan.set_workspace(wts.OP_DBA, arena)
     gv = torch.from_numpy(1.0 / w.lengths.astype(np.float64)).to(dev)   # Eq. 7: lambda / m
     it = BarycenterIteration(wts, plan, groups, Y, off, B0, gamma, gv, 0.5, arena)
+    it.tuned = tuned
     return w, Y, off, dt, plan, groups, arena, it
 
 
@@ -467,8 +512,8 @@ def c5_kernel_times(wts, it, groups):
 def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.1,
                 speedup: bool = True, cpu: bool = True):
     import torch
-    progress("headline: generating the 256-cycle workload and its plans")
-    w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, gamma)
+    progress("headline: generating the 256-cycle workload, tuning the sweep shapes")
+    w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, gamma, tune=True)
     L, d = w.L, w.d
     cells = L * int(w.lengths.sum())
     progress("headline: %d Soft-DTW groups, arena %.1f GiB; capturing the iteration"
@@ -514,8 +559,8 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
     roof["per_kernel_ms_per_step"] = {k: round(v[0] * 1e3, 2) for k, v in kern.items()}
     roof["per_kernel_alu_frac"] = {k: round(v[2] * v[3] / v[0] / VALU_LANE_OPS_PEAK, 4)
                                    for k, v in kern.items()}
-    issued = issued_per_cell()
-    roof["per_kernel_issued_valu_per_cell"] = {k: issued.get(v[4]) for k, v in kern.items()}
+    roof["per_kernel_issued_valu_per_cell"] = {k: issued_per_cell(v[4], kname(v[4], v[5]))
+                                               for k, v in kern.items()}
     roof["ops_per_cell_floors"] = {k: v[3] for k, v in kern.items()}
     roof["step_alu_frac"] = round(sum(v[2] * v[3] for v in kern.values()) / sec /
                                   VALU_LANE_OPS_PEAK, 4)
@@ -553,6 +598,7 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
         "score_s": round(t_score, 4),
         "workload_s": round(w.dba_iters * t_dba + 10 * t_soft + t_score, 2),
         "roofline": roof,
+        "autotune": it.tuned,
         "batched_vs_per_cycle": speed,
     }
     del graph, it, arena
@@ -731,10 +777,14 @@ def c3_section(wts, dev, iters: int = 10, speedup: bool = True):
     iterations per graph), plus the path sweep's own launch time."""
     import torch
     from paper_2404_12134_amd import synth
+    from paper_2404_12134_amd import autotune
     w = synth.make(3)
     Y, off, dt = wts.pack_cycles(w.cycles)
-    plan = wts.Plan(off, w.d, dt, w.L)
-    B0, _ = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
+    plan0 = wts.Plan(off, w.d, dt, w.L)
+    B0, _ = wts.init_barycenter(plan0, Y, wts.INIT_NEAREST)
+    plan0.close()
+    plan, tuned = autotune.tuned_plan(off, w.d, dt, w.L, op="dba", cycles=Y, bary=B0, reps=2,
+                                      cache_path=None)
     cells = w.L * int(w.lengths.sum())
     plan.enable_timing(8)
     for _ in range(3):
@@ -766,6 +816,7 @@ def c3_section(wts, dev, iters: int = 10, speedup: bool = True):
                                  "init" % iters,
             "s_per_dba_iteration": round(it_s, 5), "gcups": round(cells / it_s / 1e9, 2),
             "cells_per_iteration": cells, "rows_per_lane": rho,
+            "autotune": {k: tuned[k] for k in ("rho", "grid", "table")},
             "path_sweep": rf, "batched_vs_per_cycle": speed}
 
 
@@ -780,16 +831,21 @@ def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
     import numpy as np
     import torch
     from paper_2404_12134_amd import synth
+    from paper_2404_12134_amd import autotune
     w = synth.make(4)
     Y, off, dt = wts.pack_cycles(w.cycles)
     L, d = w.L, w.d
-    plan = wts.Plan(off, d, dt, L)
-    B0, _ = wts.init_barycenter(plan, Y, wts.INIT_EUCLID_MEAN)
+    plan0 = wts.Plan(off, d, dt, L)
+    B0, _ = wts.init_barycenter(plan0, Y, wts.INIT_EUCLID_MEAN)
+    plan0.close()
+    plan, tuned = autotune.tuned_plan(off, d, dt, L, op="soft", cycles=Y, bary=B0, reps=1,
+                                      cache_path=None)
     gv = torch.from_numpy(1.0 / w.lengths.astype(np.float64)).to(dev)   # Eq. 7: lambda / m
     cells = L * int(w.lengths.sum())
     cf, cb = c_soft_fwd(d, tau), c_soft_bwd(d, tau)
     rec = {"workload": w.name + ": Soft-DTW barycenter, Euclidean-mean init, weights 1/m_k",
-           "cells_per_pass": cells, "ops_per_cell": {"fwd": cf, "bwd": cb}}
+           "cells_per_pass": cells, "ops_per_cell": {"fwd": cf, "bwd": cb},
+           "autotune": {k: tuned[k] for k in ("rho", "grid", "table")}}
     groups = [(0, w.n, plan)]
     for gamma in (0.1, 1.0):
         sd = wts.SoftDescent(groups, Y, off, L, d, gamma, gv, 0.5)
@@ -867,7 +923,7 @@ def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
                           "gcups_fwd_bwd": round(2 * cells / tg / 1e9, 2)}
     del Y64
     # the Table I band (0.6), gamma 0.1
-    bplan = wts.Plan(off, d, dt, L, band=0.6)
+    bplan = wts.Plan(off, d, dt, L, band=0.6, grid=tuned["grid"])
     bcells = band_cells(L, w.lengths, 0.6)
     sdb = wts.SoftDescent([(0, w.n, bplan)], Y, off, L, d, 0.1, gv, 0.5)
     B = B0.clone()
@@ -987,7 +1043,7 @@ def only_phase(args, wts, dev):
                           "valu": valu_rates()}))
         return
     if args.only == "c5":
-        w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev)
+        w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, tune=True)
         for _ in range(args.steps):
             it.run()
         torch.cuda.synchronize()
@@ -997,7 +1053,11 @@ def only_phase(args, wts, dev):
                                       "c5_soft_fwd": KERNELS["c5_soft_fwd"].format(rho=2),
                                       "c5_soft_bwd": KERNELS["c5_soft_bwd"].format(rho=2)},
                           "cells_per_pass": w.L * int(w.lengths.sum()),
-                          "soft_groups": [[a, b] for a, b, _ in groups]}))
+                          "soft_groups": [[a, b] for a, b, _ in groups],
+                          "last_dispatches": {"c5_dba": args.steps,
+                                              "c5_soft_fwd": args.steps * len(groups),
+                                              "c5_soft_bwd": args.steps * len(groups)},
+                          "autotune": it.tuned}))
         return
     if args.only in ("c3", "segment"):
         fn = {"c3": c3_section, "segment": segmentation_section}[args.only]
@@ -1098,6 +1158,7 @@ def main():
         "halves_s": head["halves_s"], "phase_gcups": head["phase_gcups"],
         "score_s": head["score_s"], "workload_s": head["workload_s"],
         "roofline": head["roofline"],
+        "autotune": head["autotune"],
         "cpu_baseline": head.get("cpu_baseline"),
         "batched_vs_per_cycle": head["batched_vs_per_cycle"],
         "valu": valu,

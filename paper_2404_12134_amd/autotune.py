@@ -1,15 +1,20 @@
 """Autotuner for the sweep shape of a plan.
 
 A plan's wavefront sweeps have two shape parameters (`wts_opts`): the rows per
-lane of a strip (rho: 2, 4 or 5) and the number of
-persistent sweep wavefronts (grid).  Which shape is fastest depends on the
-batch: with few long pairs the chain fill and the one-wave-per-SIMD issue rate
-dominate, with many pairs the per-cell instruction count does.  `tune` times
-every candidate shape on the batch (the caller's cycles, or seeded random
-values of the same lengths) and keeps the fastest; results are cached in a
-JSON file keyed by (device, operation, d, dtype, L, n, length buckets).
+lane of a strip (rho: 2, 4 or 5 for the DTW sweeps; the Soft-DTW sweeps are
+built for 2 rows per lane only -- one row per lane was measured slower on the
+128 x 20k workload, three do not fit the backward's registers) and the
+number of persistent sweep wavefronts (grid).  Which shape is fastest depends
+on the batch: with few long pairs the chain fill and the one-wave-per-SIMD
+issue rate dominate, with many pairs the per-cell instruction count does.
+`tune` times every candidate shape on the batch (the caller's cycles, or
+seeded random values of the same lengths) and keeps the fastest; results are
+cached in a JSON file keyed by (GPU architecture, compute units, operation,
+d, dtype, L, n, length buckets).
 
-Every shape computes bit-identical results, so the choice only changes speed.
+Every shape computes bit-identical results (each pair's dynamic program runs
+the same operations whatever the strip-to-wave assignment), so the choice
+only changes speed.
 """
 
 from __future__ import annotations
@@ -20,7 +25,7 @@ from typing import Dict, Iterable, Optional, Sequence, Tuple
 
 import numpy as np
 
-OPS = ("dba", "score", "align", "medoid")
+OPS = ("dba", "score", "align", "medoid", "soft")
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "wetsand_mi", "autotune.json")
 
@@ -65,14 +70,28 @@ def store_cache(path: str, key: str, entry: dict) -> None:
     os.replace(tmp, path)
 
 
-def candidates(op: str) -> Iterable[Tuple[int, int]]:
-    """(rho, grid) shapes to try; grid 0 is the library's default."""
-    rhos = (2, 4, 5)
+def grid_candidates(op: str, cus: int) -> Tuple[int, ...]:
+    """Persistent sweep waves to try: 0 is the library's default (24 per
+    compute unit); fewer waves leave each SIMD fewer strips to interleave but
+    start fewer strips that then wait on their neighbours.  The Soft-DTW
+    backward holds three waves per SIMD (12 per compute unit)."""
+    if op == "soft":
+        return (0, 12 * cus, 6 * cus)
+    return (0, 16 * cus, 8 * cus)
+
+
+def candidates(op: str, cus: int = 256) -> Iterable[Tuple[int, int]]:
+    """(rho, grid) shapes to try for `op` on a GPU with `cus` compute units."""
+    rhos = (2,) if op == "soft" else (2, 4, 5)
     for rho in rhos:
-        yield rho, 0
+        for grid in grid_candidates(op, cus):
+            yield rho, grid
 
 
 def _run_op(wts, plan, op: str, bary, Y, outs):
+    if op == "soft":   # one forward (checkpoints in outs[0] if given) and backward
+        _, ck = wts.softdtw_forward(plan, bary, Y, 0.1, ckpt=outs[0])
+        return wts.softdtw_backward(plan, bary, Y, 0.1, ck)
     if op == "dba":
         return wts.dba_iterate(plan, bary, Y, bary_out=outs[0], counts=outs[1], dist=outs[2])
     if op == "score":
@@ -84,14 +103,17 @@ def _run_op(wts, plan, op: str, bary, Y, outs):
 
 def tune(offsets, d: int, dtype: str, L: int, op: str = "dba", cycles=None, bary=None,
          reps: int = 3, device: int = 0, cache_path: Optional[str] = DEFAULT_CACHE,
-         refresh: bool = False) -> dict:
+         refresh: bool = False, shapes=None, workspace=None) -> dict:
     """Times every candidate shape for `op` on this batch and returns
     {"rho": .., "grid": .., "ms": .., "table": [[rho, grid, ms], ...], "key": ..}.
 
     offsets: int64[n+1] cycle offsets; cycles: the packed device buffer
     ([ΣN][d], `dtype`), or None for seeded random values of the same shape;
     bary: [L][d] float64 device tensor (barycenter ops), or None for random
-    rows.  L = 0 with op = "medoid"."""
+    rows.  L = 0 with op = "medoid".  shapes: the (rho, grid) candidates
+    (default `candidates(op, cus)`); workspace: a caller-owned 256-byte
+    aligned uint8 buffer used as the DBA workspace or the Soft-DTW
+    checkpoints of every candidate (for batches whose buffers are large)."""
     import torch
     from . import wetsand as wts
 
@@ -102,7 +124,11 @@ def tune(offsets, d: int, dtype: str, L: int, op: str = "dba", cycles=None, bary
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     lengths = np.diff(off)
     dev = torch.device("cuda", device)
-    key = cache_key(torch.cuda.get_device_name(device), op, d, dtype, L, lengths)
+    props = torch.cuda.get_device_properties(device)
+    arch = getattr(props, "gcnArchName", torch.cuda.get_device_name(device)).split(":")[0]
+    cus = int(props.multi_processor_count)
+    shapes = list(candidates(op, cus) if shapes is None else shapes)
+    key = cache_key("%s-%dcu" % (arch, cus), op, d, dtype, L, lengths)
     if cache_path and not refresh:
         hit = load_cache(cache_path).get(key)
         if hit:
@@ -117,14 +143,18 @@ def tune(offsets, d: int, dtype: str, L: int, op: str = "dba", cycles=None, bary
     if B is None and L > 0:
         B = torch.from_numpy(g.standard_normal((L, d))).to(dev)
     outs = None
+    if op == "soft":
+        outs = (workspace,)
     if op == "dba":
         outs = (torch.empty((L, d), dtype=torch.float64, device=dev),
                 torch.empty(L, dtype=torch.int64, device=dev),
                 torch.empty(len(lengths), dtype=torch.float64, device=dev))
 
     table = []
-    for rho, grid in candidates(op):
+    for rho, grid in shapes:
         plan = wts.Plan(off, d, dtype, L, device=device, rho=rho, grid=grid)
+        if workspace is not None and op == "dba":
+            plan.set_workspace(wts.OP_DBA, workspace)
         _run_op(wts, plan, op, B, Y, outs)            # warm-up: workspace, code paths
         torch.cuda.synchronize(dev)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -138,7 +168,7 @@ def tune(offsets, d: int, dtype: str, L: int, op: str = "dba", cycles=None, bary
         table.append([rho, grid, round(best, 4)])
         plan.close()
     rho, grid, ms = min(table, key=lambda r: r[2])
-    entry = {"rho": rho, "grid": grid, "ms": ms, "table": table}
+    entry = {"rho": rho, "grid": grid, "ms": ms, "table": table, "arch": arch, "cus": cus}
     if cache_path:
         store_cache(cache_path, key, entry)
     return dict(entry, key=key, cached=False)

@@ -626,7 +626,7 @@ class DBARunner:
 
 
 def subset_plans(offsets, d: int, dtype: str, L: int, max_ckpt_bytes: int, device: int = 0,
-                 band: float = 0.0):
+                 band: float = 0.0, grid: int = 0):
     """Splits a batch into consecutive cycle groups whose Soft-DTW checkpoint
     buffer stays below max_ckpt_bytes.  Returns [(first, last+1, plan)].
 
@@ -648,7 +648,7 @@ def subset_plans(offsets, d: int, dtype: str, L: int, max_ckpt_bytes: int, devic
             tot += est(b)
             b += 1
         while True:
-            plan = Plan(off[a:b + 1] - off[a], d, dtype, L, device=device, band=band)
+            plan = Plan(off[a:b + 1] - off[a], d, dtype, L, device=device, band=band, grid=grid)
             if b == a + 1 or plan.workspace_bytes(OP_SOFT_FWD) <= max_ckpt_bytes:
                 break
             plan.close()

@@ -16,6 +16,9 @@ def test_length_signature_rounds_to_two_digits():
 
 
 def test_cache_key_separates_shapes():
+    k1 = autotune.cache_key("gfx950-256cu", "dba", 3, "f32", 4077, [5000] * 64)
+    assert k1 != autotune.cache_key("gfx950-304cu", "dba", 3, "f32", 4077, [5000] * 64)
+    assert k1 != autotune.cache_key("gfx942-256cu", "dba", 3, "f32", 4077, [5000] * 64)
     k1 = autotune.cache_key("dev", "dba", 3, "f32", 4077, [5000] * 64)
     assert k1 == autotune.cache_key("dev", "dba", 3, "f32", 4077, [5000] * 64)
     assert k1 != autotune.cache_key("dev", "score", 3, "f32", 4077, [5000] * 64)
@@ -33,8 +36,14 @@ def test_cache_round_trip(tmp_path):
 
 
 def test_candidates_cover_the_supported_shapes():
-    assert sorted(r for r, _ in autotune.candidates("dba")) == [2, 4, 5]
-    assert sorted(r for r, _ in autotune.candidates("medoid")) == [2, 4, 5]
+    for op in ("dba", "medoid", "score"):
+        shapes = list(autotune.candidates(op, 256))
+        assert sorted({r for r, _ in shapes}) == [2, 4, 5]
+        # every rows-per-lane choice with every grid: the default and fewer waves
+        assert sorted(shapes) == sorted((r, g) for r in (2, 4, 5) for g in (0, 16 * 256, 8 * 256))
+    # the Soft-DTW sweeps are built for 2 rows per lane: only their grid is tuned
+    soft = list(autotune.candidates("soft", 304))
+    assert soft == [(2, 0), (2, 12 * 304), (2, 6 * 304)]
 
 
 def test_tune_rejects_op_plan_mismatch_before_any_gpu_call():
