@@ -222,8 +222,8 @@ Layout layout(const wts_plan* p, int op) {
     l.progress = take(sizeof(int) * (size_t)ps.n_flags);
     l.rows = take(sizeof(double) * (size_t)ps.aux_strip_elems);
     l.states = take(sizeof(double) * (size_t)ps.state_elems);
-    l.push_up = take(sizeof(double) * (size_t)ps.bnd_elems);
-    l.push_dg = take(sizeof(double) * (size_t)ps.bnd_elems);
+    l.push_up = take(sizeof(float) * (size_t)ps.bnd_elems);
+    l.push_dg = take(sizeof(float) * (size_t)ps.bnd_elems);
     l.gsum = take(sizeof(double) * (size_t)rows * (size_t)p->d);
     l.hsum = take(sizeof(double) * (size_t)rows);
     l.out_dist = take(sizeof(double) * (size_t)p->n);
@@ -237,8 +237,8 @@ Layout layout(const wts_plan* p, int op) {
       l.rows = take(sizeof(double) * (size_t)ps.aux_strip_elems);
       l.states = take(sizeof(double) * (size_t)ps.state_elems);
     } else {
-      l.push_up = take(sizeof(double) * (size_t)ps.bnd_elems);
-      l.push_dg = take(sizeof(double) * (size_t)ps.bnd_elems);
+      l.push_up = take(sizeof(float) * (size_t)ps.bnd_elems);
+      l.push_dg = take(sizeof(float) * (size_t)ps.bnd_elems);
       l.gsum = take(sizeof(double) * (size_t)p->n * (size_t)p->L * (size_t)p->d);
       l.hsum = take(sizeof(double) * (size_t)p->n * (size_t)p->L);
     }
@@ -826,8 +826,8 @@ wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const voi
   a.states = at<double>(ck, lc.states);
   a.kscale = 1.0 / (gamma * 0.69314718055994530942);
   a.band = p->opts.band;
-  a.push_up = at<double>(ws, l.push_up);
-  a.push_dg = at<double>(ws, l.push_dg);
+  a.push_up = at<float>(ws, l.push_up);
+  a.push_dg = at<float>(ws, l.push_dg);
   a.gsum = at<double>(ws, l.gsum);
   a.hsum = at<double>(ws, l.hsum);
   a.L = p->L;
@@ -869,8 +869,8 @@ wts_status wts_softdtw_grad_cycles(const wts_plan* p, const double* bary, const 
   a.kscale = 1.0 / (gamma * 0.69314718055994530942);
   a.band = p->opts.band;   // the band is symmetric in the two series
   a.value = at<double>(ws, l.out_dist);
-  a.push_up = at<double>(ws, l.push_up);
-  a.push_dg = at<double>(ws, l.push_dg);
+  a.push_up = at<float>(ws, l.push_up);
+  a.push_dg = at<float>(ws, l.push_dg);
   a.gsum = at<double>(ws, l.gsum);
   a.hsum = at<double>(ws, l.hsum);
   a.L = p->L;

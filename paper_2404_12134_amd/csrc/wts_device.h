@@ -116,8 +116,8 @@ struct SoftArgs {
   double* states;        // sweep state every 16 steps (RHO + 1 values per lane)
   double kscale;         // log2(e) / gamma
   double* value;         // [n] Soft-DTW values (forward)
-  double* push_up;       // rolling top-row pushes between strips (backward)
-  double* push_dg;
+  float* push_up;        // rolling top-row pushes between strips (backward, float32 e)
+  float* push_dg;
   double* gsum;          // per-pair gradient rows ([n][L][d], or packed [sum M][d])
   double* hsum;          // per-pair row mass ([n][L], or packed [sum M])
   int64_t L;
@@ -196,6 +196,12 @@ __device__ __forceinline__ double ld_dev(__amdgpu_buffer_rsrc_t r, int byte_off)
 }
 __device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, int v) {
   __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, r, byte_off, 0, 16);
+}
+__device__ __forceinline__ void st_dev(__amdgpu_buffer_rsrc_t r, int byte_off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, byte_off, 0, 16);
+}
+__device__ __forceinline__ float ld_dev_f32(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 16));
 }
 // Wait for every outstanding memory operation of this wave (orders the
 // relaxed stores above before a following progress-counter store).

@@ -23,10 +23,12 @@
 // (float32), then sweeps the tile backwards in "push" form -- each finished
 // cell splits its e over its three predecessors with its own weights, the
 // diagonal taking what the other two do not, so that the split conserves e
-// to float64 rounding -- and no cell ever needs a neighbour's weights.  The
-// pushes of a strip's top row feed the strip above, so strips are pipelined
-// from the bottom up.  Per row l of the barycenter the kernel accumulates
-// sum_j e(l, j) and sum_j e(l, j) y_j, and the gradient is
+// up to the rounding of one float32 subtraction -- and no cell ever needs a
+// neighbour's weights.  e lies in [0, 1] and travels in float32 (registers,
+// lane shifts, LDS and the push rows between strips).  The pushes of a
+// strip's top row feed the strip above, so strips are pipelined from the
+// bottom up.  Per row l of the barycenter the kernel accumulates, in
+// float64, sum_j e(l, j) and sum_j e(l, j) y_j, and the gradient is
 //   d Soft-DTW / d b_l = 2 (b_l * sum_j e(l, j) - sum_j e(l, j) y_j).
 #include <type_traits>
 
@@ -55,6 +57,12 @@ __device__ __forceinline__ double shl1_f64(double v, double old) {
   const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x130, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x130, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float shl1_f32(float v, float old) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                               __builtin_bit_cast(int, v), 0x130,
+                                                               0xf, 0xf, false));
 }
 
 constexpr int kRing = 128;   // Y columns in LDS (>= 16 + 63 for a tile, power of 2)
@@ -376,10 +384,10 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
   constexpr int H = kWave * RHO;
   __shared__ double ys[D][kRing + 16];
   __shared__ double bin_fwd[kTile];        // lane 0's upper input for the replay
-  __shared__ double bin_up[kTile];         // lane 63's pushes from the strip below
-  __shared__ double bin_dg[kTile];
-  __shared__ double bout_up[kTile];        // lane 0's pushes for the strip above
-  __shared__ double bout_dg[kTile];
+  __shared__ float bin_up[kTile];          // lane 63's pushes from the strip below
+  __shared__ float bin_dg[kTile];
+  __shared__ float bout_up[kTile];         // lane 0's pushes for the strip above
+  __shared__ float bout_dg[kTile];
   __shared__ int s_item;
   const int lane = threadIdx.x;
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
@@ -424,8 +432,8 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
     const __amdgpu_buffer_rsrc_t rf_in = rsrc(row_fwd, has_above ? N * 8 : 0);
     // rolling push rows: the strip below wrote them for us, we overwrite them
     // for the strip above after reading
-    double* pu_row = a.push_up + pd.bnd_base;
-    double* pd_row = a.push_dg + pd.bnd_base;
+    float* pu_row = a.push_up + pd.bnd_base;
+    float* pd_row = a.push_dg + pd.bnd_base;
     int* prog_below = a.progress + pd.flag_base + s + 1;
     int* prog_self = a.progress + pd.flag_base + s;
     // the cell that closes the path, (M-1, N-1), receives e = 1: it is
@@ -442,24 +450,24 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       for (int c = 0; c < D; ++c)
         xr[r][c] = (ib + r < M) ? a.x[(pd.x_off + ib + r) * D + c] : 0.0;
 
-    double acc_e[RHO], acc_ey[RHO][D];
-    double pl[RHO], pdg[RHO];                 // pending left / diagonal pushes into each row
+    double acc_e[RHO], acc_ey[RHO][D];        // float64 row accumulators
+    float pl[RHO], pdg[RHO];                  // pending left / diagonal pushes into each row
 #pragma unroll
     for (int r = 0; r < RHO; ++r) {
       acc_e[r] = 0.0;
-      pl[r] = (last && lane == k_last && r == r_last) ? 1.0 : 0.0;
-      pdg[r] = 0.0;
+      pl[r] = (last && lane == k_last && r == r_last) ? 1.0f : 0.0f;
+      pdg[r] = 0.0f;
 #pragma unroll
       for (int c = 0; c < D; ++c) acc_ey[r][c] = 0.0;
     }
-    double up0 = 0.0, dg0 = 0.0;              // this lane's row-0 pushes, sent up next step
-    double recv_dg = 0.0;                     // diagonal push received last step
+    float up0 = 0.0f, dg0 = 0.0f;             // this lane's row-0 pushes, sent up next step
+    float recv_dg = 0.0f;                     // diagonal push received last step
     bool gave_up = false;                     // wave-uniform
     int seen_below = 0;                       // last progress read from the strip below (uniform)
-    const __amdgpu_buffer_rsrc_t pu_out = rsrc(pu_row, N * 8);
-    const __amdgpu_buffer_rsrc_t pd_out = rsrc(pd_row, N * 8);
-    const __amdgpu_buffer_rsrc_t pu_in = rsrc(pu_row, has_below ? N * 8 : 0);
-    const __amdgpu_buffer_rsrc_t pd_in = rsrc(pd_row, has_below ? N * 8 : 0);
+    const __amdgpu_buffer_rsrc_t pu_out = rsrc(pu_row, N * 4);
+    const __amdgpu_buffer_rsrc_t pd_out = rsrc(pd_row, N * 4);
+    const __amdgpu_buffer_rsrc_t pu_in = rsrc(pu_row, has_below ? N * 4 : 0);
+    const __amdgpu_buffer_rsrc_t pd_in = rsrc(pd_row, has_below ? N * 4 : 0);
     // a tile's replay inputs: the forward's sweep state at its first step and
     // (lanes 0..15) the strip above's bottom row at its 16 columns (the top
     // strip reads an empty buffer and uses +inf; columns past N are never used)
@@ -531,12 +539,12 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       // the pushes are only needed by the backward half: loaded now (one
       // unconditional load each, zero outside the row or without a strip
       // below) and written to LDS after the replay
-      double in_up, in_dg;
+      float in_up, in_dg;
       {
         const int j = tg - (kWave - 1) + lane;
-        const int off = lane < kTile && j >= 0 && j < N ? j * 8 : kDrop;
-        in_up = ld_dev(pu_in, off);
-        in_dg = ld_dev(pd_in, off);
+        const int off = lane < kTile && j >= 0 && j < N ? j * 4 : kDrop;
+        in_up = ld_dev_f32(pu_in, off);
+        in_dg = ld_dev_f32(pd_in, off);
       }
       __syncthreads();
 
@@ -610,33 +618,35 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
         const int j = t - lane;
         // pushes of the lane below (rows i+1): its up push for column j now,
         // its diagonal push for column j-1 next step
-        const double recv_up = shl1_f64(up0, bin_up[u]);
-        const double recv_dg_next = shl1_f64(dg0, bin_dg[u]);
+        const float recv_up = shl1_f32(up0, bin_up[u]);
+        const float recv_dg_next = shl1_f32(dg0, bin_dg[u]);
         if (full || (j >= 0 && j < N)) {
           double y[D];
 #pragma unroll
           for (int c = 0; c < D; ++c) y[c] = ys[c][yb + u];
-          double below_up = recv_up;         // push up from (i+1, j)
-          double new_pdg[RHO];
+          float below_up = recv_up;          // push up from (i+1, j)
+          float new_pdg[RHO];
 #pragma unroll
           for (int r = RHO - 1; r >= 0; --r) {
-            const double din = (r == RHO - 1) ? recv_dg : pdg[r];
-            const double e = (below_up + pl[r]) + din;
-            // split e over the three predecessors in float64: up and left by
+            const float din = (r == RHO - 1) ? recv_dg : pdg[r];
+            const float e = (below_up + pl[r]) + din;
+            // e in [0, 1] is carried in float32; the row sums take it in
+            // float64.  Split e over the three predecessors: up and left by
             // their weights, the diagonal takes the rest, so the three pushes
-            // add up to e to float64 rounding (weights that summed to 1 only
-            // to float32 rounding would leak ~1e-8 of the mass per cell, which
-            // adds up over tens of thousands of cells)
-            const double pu_ = e * (double)wu[u][r];
-            const double pl_ = e * (double)wl[u][r];
-            const double dpush = (e - pu_) - pl_;
+            // add up to e up to one rounding of each subtraction (unbiased,
+            // where weights that summed to 1 only to float32 rounding would
+            // drain or add ~1e-8 of the mass at every cell, systematically)
+            const float pu_ = e * wu[u][r];
+            const float pl_ = e * wl[u][r];
+            const float dpush = (e - pu_) - pl_;
             below_up = pu_;
             pl[r] = pl_;
             if (r > 0) new_pdg[r - 1] = dpush;
             else dg0 = dpush;
-            acc_e[r] += e;
+            const double e64 = e;
+            acc_e[r] += e64;
 #pragma unroll
-            for (int c = 0; c < D; ++c) acc_ey[r][c] = __builtin_fma(e, y[c], acc_ey[r][c]);
+            for (int c = 0; c < D; ++c) acc_ey[r][c] = __builtin_fma(e64, y[c], acc_ey[r][c]);
           }
           up0 = below_up;
 #pragma unroll
@@ -646,8 +656,8 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
             bout_dg[u] = dg0;
           }
         } else if (lane == 0 && has_above) {
-          bout_up[u] = 0.0;
-          bout_dg[u] = 0.0;
+          bout_up[u] = 0.0f;
+          bout_dg[u] = 0.0f;
         }
         recv_dg = recv_dg_next;
       }
@@ -659,8 +669,8 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
         // outstanding completes every older store without waiting for them
         const int j = tg + lane;
         const bool w = lane < kTile && j < N;
-        st_dev(pu_out, w ? j * 8 : kDrop, bout_up[lane & (kTile - 1)]);
-        st_dev(pd_out, w ? j * 8 : kDrop, bout_dg[lane & (kTile - 1)]);
+        st_dev(pu_out, w ? j * 4 : kDrop, bout_up[lane & (kTile - 1)]);
+        st_dev(pd_out, w ? j * 4 : kDrop, bout_dg[lane & (kTile - 1)]);
         mem_wait_all_but_2();
         if (lane == 0) st_dev(prog_self, N - min(N, tg + 16));
       }
@@ -696,8 +706,8 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         for (int j = lane; j < 16 * g_lo; j += kWave) {
-          st_dev(pu_out, j * 8, 0.0);
-          st_dev(pd_out, j * 8, 0.0);
+          st_dev(pu_out, j * 4, 0.0f);
+          st_dev(pd_out, j * 4, 0.0f);
         }
       }
       mem_drain();
