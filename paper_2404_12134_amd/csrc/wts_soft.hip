@@ -386,10 +386,13 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
   __shared__ double bin_fwd[kTile];        // lane 0's upper input for the replay
   __shared__ float bin_up[kTile];          // lane 63's pushes from the strip below
   __shared__ float bin_dg[kTile];
-  __shared__ float bout_up[kTile];         // lane 0's pushes for the strip above
-  __shared__ float bout_dg[kTile];
+  // lane 0's pushes for the strip above in slots 0..15; slots 16 + lane + u
+  // take the other lanes' writes
+  __shared__ float bout_up[kTile + kWave + kTile];
+  __shared__ float bout_dg[kTile + kWave + kTile];
   __shared__ int s_item;
   const int lane = threadIdx.x;
+  const int bsl = lane == 0 ? 0 : kTile + lane;
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const double INF = inf_d();
   const double k = a.kscale;
@@ -559,11 +562,21 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       // exactly what it received)
       float wu[16][RHO], wl[16][RHO];
       const bool full = tg >= kWave - 1 && tg + 16 <= N;
+      // The banded instances (two waves per SIMD, less latency hidden by
+      // the other waves) read the LDS inputs of the lane shifts one step ahead.
+      double bf_n = bin_fwd[0];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int t = tg + u;
         const int j = t - lane;
-        const double upin = shr1_f64(bot, bin_fwd[u]);
+        double bf;
+        if constexpr (BAND) {
+          bf = bf_n;
+          if (u + 1 < 16) bf_n = bin_fwd[u + 1];
+        } else {
+          bf = bin_fwd[u];
+        }
+        const double upin = shr1_f64(bot, bf);
         const double dgi = upprev;
         upprev = upin;
         if (full || (j >= 0 && j < N)) {
@@ -612,14 +625,27 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       __syncthreads();
 
       // ---- backward over the tile
+      float bu_n = bin_up[15], bd_n = bin_dg[15];
 #pragma unroll
       for (int u = 15; u >= 0; --u) {
         const int t = tg + u;
         const int j = t - lane;
+        float bu, bd;
+        if constexpr (BAND) {
+          bu = bu_n;
+          bd = bd_n;
+          if (u > 0) {
+            bu_n = bin_up[u - 1];
+            bd_n = bin_dg[u - 1];
+          }
+        } else {
+          bu = bin_up[u];
+          bd = bin_dg[u];
+        }
         // pushes of the lane below (rows i+1): its up push for column j now,
         // its diagonal push for column j-1 next step
-        const float recv_up = shl1_f32(up0, bin_up[u]);
-        const float recv_dg_next = shl1_f32(dg0, bin_dg[u]);
+        const float recv_up = shl1_f32(up0, bu);
+        const float recv_dg_next = shl1_f32(dg0, bd);
         if (full || (j >= 0 && j < N)) {
           double y[D];
 #pragma unroll
@@ -651,14 +677,11 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
           up0 = below_up;
 #pragma unroll
           for (int r = 0; r + 1 < RHO; ++r) pdg[r] = new_pdg[r];
-          if (lane == 0 && has_above) {
-            bout_up[u] = up0;
-            bout_dg[u] = dg0;
-          }
-        } else if (lane == 0 && has_above) {
-          bout_up[u] = 0.0f;
-          bout_dg[u] = 0.0f;
         }
+        // lane 0's pushes into slot u (a column past N holds a stale value,
+        // never published), the other lanes' into scratch slots: no branch
+        bout_up[bsl + u] = up0;
+        bout_dg[bsl + u] = dg0;
         recv_dg = recv_dg_next;
       }
       __syncthreads();
