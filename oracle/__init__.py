@@ -1,5 +1,9 @@
 """FP64 CPU oracle for the WETSAND hot path -- TEST INFRASTRUCTURE ONLY.
 
+The hard-DTW programs (cost, DTW with its path, Sub-DTW) also run in float32
+from the same C source (``fp32=True``, ``dtw32``, ``cost32``): the reference
+of the float32-decision variant of the sweeps.
+
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product path
 (``paper_2404_12134_amd``) never imports, links or calls it, and the two share
@@ -46,10 +50,13 @@ def lib():
         P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
         L.wts_o_cost.restype = D
         L.wts_o_cost.argtypes = [P, P, I32, I32]
+        L.wts_o_cost32.restype = ctypes.c_float
+        L.wts_o_cost32.argtypes = [P, P, I32, I32]
         L.wts_o_dtw.argtypes = [P, I64, P, I64, I32, I32, P, P, P, P]
-        L.wts_o_dtw_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P]
-        L.wts_o_score_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P, P]
-        L.wts_o_dba_iterate.argtypes = [P, I64, P, P, I32, I32, P, P, P, P, P]
+        L.wts_o_dtw32.argtypes = [P, I64, P, I64, I32, I32, P, P, P, P]
+        L.wts_o_dtw_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P, I32]
+        L.wts_o_score_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P, P, I32]
+        L.wts_o_dba_iterate.argtypes = [P, I64, P, P, I32, I32, P, P, P, P, P, I32]
         L.wts_o_softdtw.argtypes = [P, I64, P, I64, I32, D, P, P]
         L.wts_o_softdtw_band.argtypes = [P, I64, P, I64, I32, D, D, P, P]
         L.wts_o_softdtw_grad_band.argtypes = [P, I64, P, I64, I32, D, D, P, P, P, P]
@@ -59,14 +66,15 @@ def lib():
         L.wts_o_band_cols.restype = None
         L.wts_o_softdtw_grad.argtypes = [P, I64, P, I64, I32, D, P, P, P, P]
         L.wts_o_softdtw_batch.argtypes = [P, I64, P, P, I32, I32, D, P, P, P, P]
-        L.wts_o_medoid.argtypes = [P, P, I32, I32, P, P]
+        L.wts_o_medoid.argtypes = [P, P, I32, I32, P, P, I32]
         L.wts_o_subdtw.argtypes = [P, I64, P, I64, I32, I32, P, P, P]
-        L.wts_o_subdtw_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P, P]
+        L.wts_o_subdtw32.argtypes = [P, I64, P, I64, I32, I32, P, P, P]
+        L.wts_o_subdtw_batch.argtypes = [P, I64, P, P, I32, I32, I32, P, P, P, I32]
         L.wts_o_resample.argtypes = [P, I64, I32, I64, P]
         L.wts_o_resample.restype = None
         L.wts_o_euclid_mean.argtypes = [P, P, I32, I32, I64, P]
         L.wts_o_nearest_init.argtypes = [P, P, I32, I32, I64, P]
-        for f in ("wts_o_dtw", "wts_o_dtw_batch", "wts_o_score_batch", "wts_o_dba_iterate",
+        for f in ("wts_o_dtw", "wts_o_dtw32", "wts_o_subdtw32", "wts_o_dtw_batch", "wts_o_score_batch", "wts_o_dba_iterate",
                   "wts_o_softdtw", "wts_o_softdtw_grad", "wts_o_softdtw_batch", "wts_o_medoid",
                   "wts_o_euclid_mean", "wts_o_nearest_init", "wts_o_num_threads",
                   "wts_o_subdtw", "wts_o_subdtw_batch", "wts_o_softdtw_band",
@@ -125,31 +133,60 @@ def dtw(X, Y, kind=SQEUCLID, with_path=True, with_codes=False):
     return float(dist[0]), k, (path[:k].copy() if with_path else None), codes
 
 
-def dtw_batch(X, cycles, kind=SQEUCLID):
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def cost32(x, y, kind=SQEUCLID) -> float:
+    """Def. 3 evaluated in float32 on float32 inputs (the float32 program)."""
+    x, y = _f32(x).ravel(), _f32(y).ravel()
+    return float(lib().wts_o_cost32(_p(x), _p(y), x.size, kind))
+
+
+def dtw32(X, Y, kind=SQEUCLID, with_path=True, with_codes=False):
+    """Eq. 1 run in float32 on the inputs rounded to float32 (the reference
+    of the float32-decision sweeps): returns (dist as float64, |pi|, path,
+    codes) like dtw()."""
+    X, Y = _f32(_series(X)), _f32(_series(Y))
+    M, N, d = X.shape[0], Y.shape[0], X.shape[1]
+    dist = np.zeros(1, dtype=np.float32)
+    plen = np.zeros(1, dtype=np.int64)
+    path = np.zeros((M + N - 1, 2), dtype=np.int32) if with_path else None
+    codes = np.zeros((M, N), dtype=np.uint8) if with_codes else None
+    _check(lib().wts_o_dtw32(_p(X), M, _p(Y), N, d, kind, _p(dist), _p(plen), _p(path),
+                             _p(codes)))
+    k = int(plen[0])
+    return float(dist[0]), k, (path[:k].copy() if with_path else None), codes
+
+
+def dtw_batch(X, cycles, kind=SQEUCLID, fp32=False):
+    """Eq. 1 for every cycle: (dist, |pi|); fp32: float32 decisions."""
     X = _series(X)
     Y, off = _packed(cycles)
     n = len(cycles)
     dist = np.zeros(n)
     plen = np.zeros(n, dtype=np.int64)
     _check(lib().wts_o_dtw_batch(_p(X), X.shape[0], _p(Y), _p(off), n, X.shape[1], kind,
-                                 _p(dist), _p(plen)))
+                                 _p(dist), _p(plen), int(bool(fp32))))
     return dist, plen
 
 
-def score_batch(B, cycles, kind=SQEUCLID):
-    """Eq. 8 for every cycle: returns (score, dist, |pi|)."""
+def score_batch(B, cycles, kind=SQEUCLID, fp32=False):
+    """Eq. 8 for every cycle: returns (score, dist, |pi|); fp32: float32
+    decisions."""
     B = _series(B)
     Y, off = _packed(cycles)
     n = len(cycles)
     score, dist = np.zeros(n), np.zeros(n)
     plen = np.zeros(n, dtype=np.int64)
     _check(lib().wts_o_score_batch(_p(B), B.shape[0], _p(Y), _p(off), n, B.shape[1], kind,
-                                   _p(score), _p(dist), _p(plen)))
+                                   _p(score), _p(dist), _p(plen), int(bool(fp32))))
     return score, dist, plen
 
 
-def dba_iterate(B, cycles, weights=None):
-    """One DBA iteration: returns (B', K counts, dist, |pi|)."""
+def dba_iterate(B, cycles, weights=None, fp32=False):
+    """One DBA iteration: returns (B', K counts, dist, |pi|); fp32: the paths
+    from float32 decisions (sums and division in float64)."""
     B = _series(B)
     Y, off = _packed(cycles)
     n, L, d = len(cycles), B.shape[0], B.shape[1]
@@ -159,7 +196,7 @@ def dba_iterate(B, cycles, weights=None):
     dist = np.zeros(n)
     plen = np.zeros(n, dtype=np.int64)
     _check(lib().wts_o_dba_iterate(_p(B), L, _p(Y), _p(off), n, d, _p(w), _p(Bout), _p(counts),
-                                   _p(dist), _p(plen)))
+                                   _p(dist), _p(plen), int(bool(fp32))))
     return Bout, counts, dist, plen
 
 
@@ -234,12 +271,12 @@ def softdtw_batch(X, cycles, gamma, weights=None, grad=True, band=0.0):
     return (vals, g, h) if grad else vals
 
 
-def medoid(cycles):
+def medoid(cycles, fp32=False):
     Y, off = _packed(cycles)
     n, d = len(cycles), Y.shape[1]
     D = np.zeros((n, n))
     k = np.zeros(1, dtype=np.int32)
-    _check(lib().wts_o_medoid(_p(Y), _p(off), n, d, _p(D), _p(k)))
+    _check(lib().wts_o_medoid(_p(Y), _p(off), n, d, _p(D), _p(k), int(bool(fp32))))
     return int(k[0]), D
 
 
@@ -264,19 +301,27 @@ def nearest_init(cycles, L):
     return int(k), out
 
 
-def subdtw(X, Y, kind=SQEUCLID):
-    """Sub-DTW (Sec. III-B, Eq. 2): (value, a*, b*), 0-based columns of Y."""
-    X, Y = _series(X), _series(Y)
-    v = np.zeros(1)
+def subdtw(X, Y, kind=SQEUCLID, fp32=False):
+    """Sub-DTW (Sec. III-B, Eq. 2): (value, a*, b*), 0-based columns of Y;
+    fp32: the same program in float32 on the inputs rounded to float32."""
     a = np.zeros(1, dtype=np.int64)
     b = np.zeros(1, dtype=np.int64)
-    _check(lib().wts_o_subdtw(_p(X), X.shape[0], _p(Y), Y.shape[0], X.shape[1], kind, _p(v),
-                              _p(a), _p(b)))
+    if fp32:
+        X, Y = _f32(_series(X)), _f32(_series(Y))
+        v = np.zeros(1, dtype=np.float32)
+        _check(lib().wts_o_subdtw32(_p(X), X.shape[0], _p(Y), Y.shape[0], X.shape[1], kind,
+                                    _p(v), _p(a), _p(b)))
+    else:
+        X, Y = _series(X), _series(Y)
+        v = np.zeros(1)
+        _check(lib().wts_o_subdtw(_p(X), X.shape[0], _p(Y), Y.shape[0], X.shape[1], kind,
+                                  _p(v), _p(a), _p(b)))
     return float(v[0]), int(a[0]), int(b[0])
 
 
-def subdtw_batch(X, windows, kind=SQEUCLID):
-    """Sub-DTW of X against every window: (values, a*, b*) arrays."""
+def subdtw_batch(X, windows, kind=SQEUCLID, fp32=False):
+    """Sub-DTW of X against every window: (values, a*, b*) arrays; fp32:
+    float32 decisions."""
     X = _series(X)
     Y, off = _packed(windows)
     n = len(windows)
@@ -284,7 +329,7 @@ def subdtw_batch(X, windows, kind=SQEUCLID):
     a = np.zeros(n, dtype=np.int64)
     b = np.zeros(n, dtype=np.int64)
     _check(lib().wts_o_subdtw_batch(_p(X), X.shape[0], _p(Y), _p(off), n, X.shape[1], kind,
-                                    _p(v), _p(a), _p(b)))
+                                    _p(v), _p(a), _p(b), int(bool(fp32))))
     return v, a, b
 
 

@@ -17,6 +17,12 @@ definitions directly:
 
 The number of complete paths of an M x N grid is the Delannoy number
 D(M-1, N-1) = sum_k C(M-1, k) C(N-1, k) 2^k.
+
+Float32 arithmetic (for the float32-decision program): every operation is
+evaluated exactly on rationals and rounded once to the nearest float32
+(ties to even), so a path's cost is its cost summed in float32 in path
+order.  Rounding to nearest is monotone, so the minimum over paths of these
+sums is what a float32 dynamic program computes.
 """
 
 from __future__ import annotations
@@ -189,3 +195,68 @@ def dba_iterate(B, cycles, weights=None):
                 S = S + w[p] * psum[p, l, c]
             out[l, c] = S / C
     return out, K
+
+
+# ------------------------------------------------------- float32 arithmetic
+
+def round_f32(q) -> float:
+    """The float32 nearest to the rational q (ties to even), as a float."""
+    q = Fraction(q)
+    if q == 0:
+        return 0.0
+    sign = -1 if q < 0 else 1
+    a = abs(q)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1                        # now 2^e <= a < 2^(e+1)
+    e = max(e, -126)                  # subnormals share the smallest exponent
+    ulp = Fraction(2) ** (e - 23)
+    m = a / ulp                       # 2^23 <= m < 2^24 for normal numbers
+    lo = m.numerator // m.denominator
+    rem = m - lo
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and lo % 2 == 1):
+        lo += 1
+    v = lo * ulp
+    if v >= Fraction(2) ** 128:
+        return sign * math.inf
+    return sign * float(v)            # exact: v has at most 24 significant bits
+
+
+def delta32(x, y):
+    """Def. 3 in float32, the oracle's operation order: e_c = x_c - y_c,
+    s = e_0 * e_0, s = fma(e_c, e_c, s), each rounded once to float32."""
+    x = [Fraction(float(v)) for v in np.asarray(x, dtype=np.float32).ravel()]
+    y = [Fraction(float(v)) for v in np.asarray(y, dtype=np.float32).ravel()]
+    e = Fraction(round_f32(x[0] - y[0]))
+    s = Fraction(round_f32(e * e))
+    for c in range(1, len(x)):
+        e = Fraction(round_f32(x[c] - y[c]))
+        s = Fraction(round_f32(e * e + s))
+    return float(s)
+
+
+def path_cost32(X, Y, path) -> float:
+    """The path's cost summed in float32 from (1,1): c = delta + c."""
+    c = Fraction(0)
+    for i, j in path:
+        c = Fraction(round_f32(Fraction(delta32(X[i], Y[j])) + c))
+    return float(c)
+
+
+def dtw32_value(X, Y) -> float:
+    """Eq. 1 in float32 arithmetic: the minimum over paths of path_cost32."""
+    X, Y = _series(X), _series(Y)
+    return min(path_cost32(X, Y, p) for p in all_paths(X.shape[0], Y.shape[0]))
+
+
+def subdtw32_value(X, Y) -> float:
+    """Sub-DTW in float32 arithmetic: the minimum over every subsequence
+    Y[a..b] and every path of X against it of path_cost32."""
+    X, Y = _series(X), _series(Y)
+    M, N = X.shape[0], Y.shape[0]
+    best = math.inf
+    for a in range(N):
+        for b in range(a, N):
+            for p in all_paths(M, b - a + 1):
+                best = min(best, path_cost32(X, Y, [(i, j + a) for i, j in p]))
+    return best

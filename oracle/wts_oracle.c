@@ -7,7 +7,9 @@
  *
  * Everything is the textbook dynamic program written out, in FP64, compiled
  * with -O2 -ffp-contract=off (no FMA contraction, no fast-math), one
- * single-threaded row-major DP per pair, OpenMP across pairs.  The notation
+ * single-threaded row-major DP per pair, OpenMP across pairs.  The hard-DTW
+ * programs also run in float32 (the same source, wts_oracle_dp.inc) as the
+ * reference of the float32-decision variant of the sweeps.  The notation
  * follows the paper (Sec. III):
  *   X in R^{d x M} (here: the barycenter B, M = L rows), Y in R^{d x N},
  *   delta_{ij} = delta(x_i, y_j)                              (Def. 3)
@@ -49,112 +51,102 @@
 #define CODE_UP 1
 #define CODE_LEFT 2
 
-/* Def. 3: delta(x, y).  Squared Euclidean in a fixed order:
- * e_c = x_c - y_c; s = e_0 * e_0; s = fma(e_c, e_c, s) for c = 1..d-1.
- * The l2 norm is sqrt(s) (correctly rounded). */
-double wts_o_cost(const double* x, const double* y, int d, int kind) {
-  double e = x[0] - y[0];
-  double s = e * e;
-  for (int c = 1; c < d; ++c) {
-    e = x[c] - y[c];
-    s = fma(e, e, s);
-  }
-  return kind == O_EUCLID ? sqrt(s) : s;
+/* The hard-DTW dynamic programs (Def. 3 cost, Eq. 1 with its optimal path,
+ * Sub-DTW of Eq. 2), written once in wts_oracle_dp.inc: in float64 here, and
+ * the same source in float32 for the float32-decision variant. */
+#define REAL double
+#define FMA_R fma
+#define SQRT_R sqrt
+#define DP_NAME(base) base
+#include "wts_oracle_dp.inc"
+#undef REAL
+#undef FMA_R
+#undef SQRT_R
+#undef DP_NAME
+#define REAL float
+#define FMA_R fmaf
+#define SQRT_R sqrtf
+#define DP_NAME(base) base##32
+#include "wts_oracle_dp.inc"
+#undef REAL
+#undef FMA_R
+#undef SQRT_R
+#undef DP_NAME
+
+/* Inputs rounded to float32 (to nearest); NULL on allocation failure. */
+static float* to_f32(const double* a, int64_t n) {
+  float* r = (float*)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+  if (r)
+    for (int64_t q = 0; q < n; ++q) r[q] = (float)a[q];
+  return r;
 }
 
-/* Eq. 1 / Eq. 5 with gamma = 0, plus the optimal path.
- *   dist  <- r_{M,N}
- *   plen  <- |pi|, the number of index pairs on the optimal path
- *   path  <- the path in forward order as (i, j) int32 pairs, or NULL
- *   codes <- M*N argmin codes (0 diag, 1 up, 2 left), or NULL
- * Returns 0, or -1 on allocation failure. */
-int wts_o_dtw(const double* X, int64_t M, const double* Y, int64_t N, int d, int kind,
-              double* dist, int64_t* plen, int32_t* path, uint8_t* codes_out) {
-  uint8_t* code = codes_out ? codes_out : (uint8_t*)malloc((size_t)(M * N));
-  double* prev = (double*)malloc(sizeof(double) * (size_t)(N + 1));
-  double* cur = (double*)malloc(sizeof(double) * (size_t)(N + 1));
-  if (!code || !prev || !cur) {
-    free(prev); free(cur);
-    if (!codes_out) free(code);
-    return -1;
-  }
-  /* row "0" of the paper: r_{0,0} = 0, r_{0,j} = inf.  prev[j+1] = r(i-1, j),
-   * prev[0] = r(i-1, -1). */
-  prev[0] = 0.0;
-  for (int64_t j = 0; j < N; ++j) prev[j + 1] = INFINITY;
-  for (int64_t i = 0; i < M; ++i) {
-    cur[0] = INFINITY;
-    for (int64_t j = 0; j < N; ++j) {
-      double dg = prev[j], up = prev[j + 1], lf = cur[j];
-      double m = dg;
-      uint8_t c = CODE_DIAG;
-      if (up < m) { m = up; c = CODE_UP; }
-      if (lf < m) { m = lf; c = CODE_LEFT; }
-      cur[j + 1] = wts_o_cost(X + i * d, Y + j * d, d, kind) + m;
-      code[i * N + j] = c;
-    }
-    double* t = prev; prev = cur; cur = t;
-    prev[0] = INFINITY;
-  }
-  *dist = prev[N];
-  /* backtrack from (M-1, N-1) to (0, 0) */
-  int64_t i = M - 1, j = N - 1, k = 0;
-  int64_t cap = M + N - 1;
-  int32_t* rev = path ? (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)cap) : NULL;
-  for (;;) {
-    if (rev) { rev[2 * k] = (int32_t)i; rev[2 * k + 1] = (int32_t)j; }
-    ++k;
-    if (i == 0 && j == 0) break;
-    uint8_t c = code[i * N + j];
-    if (c == CODE_DIAG) { --i; --j; }
-    else if (c == CODE_UP) { --i; }
-    else { --j; }
-  }
-  *plen = k;
-  if (rev) {
-    for (int64_t q = 0; q < k; ++q) {
-      path[2 * q] = rev[2 * (k - 1 - q)];
-      path[2 * q + 1] = rev[2 * (k - 1 - q) + 1];
-    }
-    free(rev);
-  }
-  free(prev); free(cur);
-  if (!codes_out) free(code);
-  return 0;
+/* Eq. 1 for one pair with float64 decisions (fp32 = 0), or the same program
+ * in float32 on the inputs rounded to float32 (fp32 = 1; the value is then
+ * widened exactly to float64). */
+static int dtw_pair(const double* X, int64_t M, const double* Y, int64_t N, int d, int kind,
+                    int fp32, double* dist, int64_t* plen, int32_t* path, uint8_t* codes) {
+  if (!fp32) return wts_o_dtw(X, M, Y, N, d, kind, dist, plen, path, codes);
+  float* xf = to_f32(X, M * d);
+  float* yf = to_f32(Y, N * d);
+  float v = 0.0f;
+  int rc = (xf && yf) ? wts_o_dtw32(xf, M, yf, N, d, kind, &v, plen, path, codes) : -1;
+  *dist = (double)v;
+  free(xf); free(yf);
+  return rc;
 }
 
-/* Eq. 1 for a whole batch against one X; OpenMP across cycles. */
+/* Sub-DTW of one pair, float64 or float32 decisions as dtw_pair. */
+static int subdtw_pair(const double* X, int64_t M, const double* Y, int64_t N, int d, int kind,
+                       int fp32, double* value, int64_t* a_star, int64_t* b_star) {
+  if (!fp32) return wts_o_subdtw(X, M, Y, N, d, kind, value, a_star, b_star);
+  float* xf = to_f32(X, M * d);
+  float* yf = to_f32(Y, N * d);
+  float v = 0.0f;
+  int rc = (xf && yf) ? wts_o_subdtw32(xf, M, yf, N, d, kind, &v, a_star, b_star) : -1;
+  *value = (double)v;
+  free(xf); free(yf);
+  return rc;
+}
+
+/* Eq. 1 for a whole batch against one X; OpenMP across cycles.  fp32 = 1:
+ * float32 decisions (dtw_pair). */
 int wts_o_dtw_batch(const double* X, int64_t M, const double* Yall, const int64_t* off, int n,
-                    int d, int kind, double* dist, int64_t* plen) {
+                    int d, int kind, double* dist, int64_t* plen, int fp32) {
   int err = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
   for (int p = 0; p < n; ++p) {
     int64_t len = 0;
-    err |= wts_o_dtw(X, M, Yall + off[p] * d, off[p + 1] - off[p], d, kind, &dist[p], &len, NULL,
-                     NULL);
+    err |= dtw_pair(X, M, Yall + off[p] * d, off[p + 1] - off[p], d, kind, fp32, &dist[p], &len,
+                    NULL, NULL);
     if (plen) plen[p] = len;
   }
   return err ? -1 : 0;
 }
 
-/* Eq. 8: d_score = DTW(B, C_k) / |pi| for every cycle. */
+/* Eq. 8: d_score = DTW(B, C_k) / |pi| for every cycle (fp32 as above; the
+ * division is float64 either way). */
 int wts_o_score_batch(const double* B, int64_t L, const double* Yall, const int64_t* off, int n,
-                      int d, int kind, double* score, double* dist, int64_t* plen) {
-  int err = wts_o_dtw_batch(B, L, Yall, off, n, d, kind, dist, plen);
+                      int d, int kind, double* score, double* dist, int64_t* plen, int fp32) {
+  int err = wts_o_dtw_batch(B, L, Yall, off, n, d, kind, dist, plen, fp32);
   for (int p = 0; p < n; ++p) score[p] = dist[p] / (double)plen[p];
   return err;
 }
 
 /* Per-pair part of one DBA iteration: backtrack the optimal path of (B, Y)
  * and, for every barycenter row l, sum the aligned samples y_j in the order
- * the backtrack visits them (descending j), starting from +0.0.
+ * the backtrack visits them (descending j), starting from +0.0 (in float64
+ * whichever precision decided the path).
  *   psum[l*d + c], pcnt[l] are overwritten. */
-static int dba_pair(const double* B, int64_t L, const double* Y, int64_t N, int d,
+static int dba_pair(const double* B, int64_t L, const double* Y, int64_t N, int d, int fp32,
                     double* psum, int64_t* pcnt, double* dist, int64_t* plen) {
   uint8_t* code = (uint8_t*)malloc((size_t)(L * N));
   if (!code) return -1;
   int64_t len = 0;
-  if (wts_o_dtw(B, L, Y, N, d, O_SQEUCLID, dist, &len, NULL, code)) { free(code); return -1; }
+  if (dtw_pair(B, L, Y, N, d, O_SQEUCLID, fp32, dist, &len, NULL, code)) {
+    free(code);
+    return -1;
+  }
   *plen = len;
   for (int64_t l = 0; l < L * d; ++l) psum[l] = 0.0;
   for (int64_t l = 0; l < L; ++l) pcnt[l] = 0;
@@ -179,10 +171,11 @@ static int dba_pair(const double* B, int64_t L, const double* Y, int64_t N, int 
  *   K_l = sum_i |run_i(l)|              (integer alignment counts)
  *   B'_l = S_l / C_l
  * w = NULL means every w_i = 1.  counts <- K, dist/plen <- per-cycle DTW
- * value and path length (either may be NULL). */
+ * value and path length (either may be NULL).  fp32 = 1: the paths come from
+ * float32 decisions (dtw_pair); the sums and the division stay float64. */
 int wts_o_dba_iterate(const double* B, int64_t L, const double* Yall, const int64_t* off, int n,
                       int d, const double* w, double* Bout, int64_t* counts, double* dist,
-                      int64_t* plen) {
+                      int64_t* plen, int fp32) {
   double* psum = (double*)malloc(sizeof(double) * (size_t)(n * L * d));
   int64_t* pcnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n * L));
   double* pd = (double*)malloc(sizeof(double) * (size_t)n);
@@ -191,8 +184,8 @@ int wts_o_dba_iterate(const double* B, int64_t L, const double* Yall, const int6
   int err = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
   for (int p = 0; p < n; ++p)
-    err |= dba_pair(B, L, Yall + off[p] * d, off[p + 1] - off[p], d, psum + (int64_t)p * L * d,
-                    pcnt + (int64_t)p * L, &pd[p], &pl[p]);
+    err |= dba_pair(B, L, Yall + off[p] * d, off[p + 1] - off[p], d, fp32,
+                    psum + (int64_t)p * L * d, pcnt + (int64_t)p * L, &pd[p], &pl[p]);
   if (!err) {
     for (int64_t l = 0; l < L; ++l) {
       double C = 0.0;
@@ -442,65 +435,15 @@ int wts_o_softdtw_grad_ckpt(const double* X, int64_t M, const double* Y, int64_t
   return 0;
 }
 
-/* Sub-DTW (Sec. III-B, Eq. 2): the minimum cost over subsequence alignment
- * paths, which run from row 1 to row M of X but may start and end at any
- * column of Y.  The dynamic program is Eq. 1's with a free start: the row
- * above the first one is 0 at every column (r_{0,j} = 0 in the paper's
- * 1-based cells), the column left of the first one +inf below row 0.  The
- * path is backtracked from (M-1, b*) with the DTW tie-break (diag, up,
- * left), where b* is the lowest column whose last-row cost is minimal; the
- * first cell it reaches in row 0 gives a*.  Outputs: value, a*, b* (0-based
- * columns of Y).  Needs M*N bytes for the argmin codes. */
-int wts_o_subdtw(const double* X, int64_t M, const double* Y, int64_t N, int d, int kind,
-                 double* value, int64_t* a_star, int64_t* b_star) {
-  uint8_t* code = (uint8_t*)malloc((size_t)(M * N));
-  double* prev = (double*)malloc(sizeof(double) * (size_t)(N + 1));
-  double* cur = (double*)malloc(sizeof(double) * (size_t)(N + 1));
-  if (!code || !prev || !cur) { free(code); free(prev); free(cur); return -1; }
-  /* prev[j+1] = r(i-1, j); row -1 is 0 everywhere (free start), prev[0] is
-   * the corner r(-1, -1) = 0 */
-  for (int64_t j = 0; j <= N; ++j) prev[j] = 0.0;
-  for (int64_t i = 0; i < M; ++i) {
-    cur[0] = INFINITY;
-    for (int64_t j = 0; j < N; ++j) {
-      double dg = prev[j], up = prev[j + 1], lf = cur[j];
-      double m = dg;
-      uint8_t c = CODE_DIAG;
-      if (up < m) { m = up; c = CODE_UP; }
-      if (lf < m) { m = lf; c = CODE_LEFT; }
-      cur[j + 1] = wts_o_cost(X + i * d, Y + j * d, d, kind) + m;
-      code[i * N + j] = c;
-    }
-    double* t = prev; prev = cur; cur = t;
-  }
-  /* last row: lowest column with the minimal cost */
-  int64_t b = 0;
-  for (int64_t j = 1; j < N; ++j)
-    if (prev[j + 1] < prev[b + 1]) b = j;
-  *value = prev[b + 1];
-  *b_star = b;
-  /* backtrack to row 0 */
-  int64_t i = M - 1, j = b;
-  while (i > 0) {
-    uint8_t c = code[i * N + j];
-    if (c == CODE_DIAG) { --i; --j; }
-    else if (c == CODE_UP) { --i; }
-    else { --j; }
-  }
-  /* in row 0 the diagonal predecessor (row -1, cost 0) is never worse than
-   * the left one, so the path enters row 0 at the column it reaches */
-  *a_star = j;
-  free(code); free(prev); free(cur);
-  return 0;
-}
-
-/* Sub-DTW of one X against many windows of Y (OpenMP across windows). */
+/* Sub-DTW of one X against many windows of Y (OpenMP across windows);
+ * fp32 = 1: float32 decisions (subdtw_pair). */
 int wts_o_subdtw_batch(const double* X, int64_t M, const double* Yall, const int64_t* off, int n,
-                       int d, int kind, double* value, int64_t* a_star, int64_t* b_star) {
+                       int d, int kind, double* value, int64_t* a_star, int64_t* b_star,
+                       int fp32) {
   int err = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
   for (int p = 0; p < n; ++p)
-    err |= wts_o_subdtw(X, M, Yall + off[p] * d, off[p + 1] - off[p], d, kind, &value[p],
+    err |= subdtw_pair(X, M, Yall + off[p] * d, off[p + 1] - off[p], d, kind, fp32, &value[p],
                         &a_star[p], &b_star[p]);
   return err ? -1 : 0;
 }
@@ -565,8 +508,10 @@ void wts_o_band_cols(int64_t M, int64_t N, double w, int64_t i, int64_t* jlo, in
 
 /* Medoid initialisation: D[k][i] = DTW(Y_k, Y_i) for all k != i (D[k][k] = 0),
  * total_k = sum_{i ascending} D[k][i], medoid = argmin_k total_k (lowest k on
- * ties).  Dm: n*n (may be NULL). */
-int wts_o_medoid(const double* Yall, const int64_t* off, int n, int d, double* Dm, int* medoid) {
+ * ties).  Dm: n*n (may be NULL).  fp32 = 1: each DTW with float32
+ * decisions (dtw_pair), the totals in float64. */
+int wts_o_medoid(const double* Yall, const int64_t* off, int n, int d, double* Dm, int* medoid,
+                 int fp32) {
   double* D = Dm ? Dm : (double*)malloc(sizeof(double) * (size_t)n * (size_t)n);
   if (!D) return -1;
   int err = 0;
@@ -575,9 +520,9 @@ int wts_o_medoid(const double* Yall, const int64_t* off, int n, int d, double* D
     for (int i = 0; i < n; ++i) {
       if (i == k) { D[(int64_t)k * n + i] = 0.0; continue; }
       int64_t len;
-      err |= wts_o_dtw(Yall + off[k] * d, off[k + 1] - off[k], Yall + off[i] * d,
-                       off[i + 1] - off[i], d, O_SQEUCLID, &D[(int64_t)k * n + i], &len, NULL,
-                       NULL);
+      err |= dtw_pair(Yall + off[k] * d, off[k + 1] - off[k], Yall + off[i] * d,
+                      off[i + 1] - off[i], d, O_SQEUCLID, fp32, &D[(int64_t)k * n + i], &len,
+                      NULL, NULL);
     }
   }
   int best = 0;

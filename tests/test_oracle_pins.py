@@ -1,4 +1,5 @@
-"""Pins for the FP64 oracle against facts the paper and the mathematics fix.
+"""Pins for the FP64 oracle (and its float32 program) against facts the paper
+and the mathematics fix.
 
 Each test checks the oracle against something other than itself: brute force
 over all alignment paths (Def. 1, Eq. 1, Eq. 4), a hand-worked example,
@@ -552,3 +553,118 @@ def test_softdtw_grad_checkpointed_is_bitwise_the_full_R(M, N, band):
         assert v == v2
         np.testing.assert_array_equal(g, g2)
         np.testing.assert_array_equal(h, h2)
+
+
+# ------------------------------------------- the float32 program (decision = 1)
+
+def _grid(r, shape, bits=12, hi=4.0):
+    """Values on the 2^-bits grid in [-hi, hi]: exact in float32; their
+    differences, squares and the float64 sums of a few of them are exact in
+    float64, while float32 must round the squares and the sums."""
+    return np.round(r.uniform(-hi, hi, shape) * 2 ** bits) / 2 ** bits
+
+
+def _is_path(path, M, N):
+    if path[0] != (0, 0) or path[-1] != (M - 1, N - 1):
+        return False
+    return all((i1 - i0, j1 - j0) in ((0, 1), (1, 0), (1, 1))
+               for (i0, j0), (i1, j1) in zip(path, path[1:]))
+
+
+def test_cost32_is_float32_rounding_of_each_operation():
+    r = rng(300)
+    for d in range(1, 9):
+        for _ in range(50):
+            x, y = r.standard_normal(d), r.standard_normal(d)
+            assert oracle.cost32(x, y) == brute.delta32(x, y)
+    # the same inputs give a different float64 cost: float32 rounding is real
+    x, y = np.float32([1.1, -0.3, 2.7]), np.float32([0.2, 0.9, -1.3])
+    assert oracle.cost32(x, y) != oracle.cost(x.astype(np.float64), y.astype(np.float64))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_dtw32_brute_value_and_an_optimal_path(d):
+    """The float32 program's value is the minimum over every alignment path
+    of the path's cost summed in float32; its path is a complete path whose
+    float32 cost is that value.  On the 2^-12 grid float64 is exact and
+    float32 rounds, so the two programs differ."""
+    r = rng(310 + d)
+    differ = 0
+    for M in range(1, 6):
+        for N in range(1, 6):
+            X, Y = _grid(r, (M, d)), _grid(r, (N, d))
+            v, plen, path, _ = oracle.dtw32(X, Y)
+            assert v == brute.dtw32_value(X, Y), (M, N)
+            p = [tuple(c) for c in path.tolist()]
+            assert _is_path(p, M, N) and plen == len(p)
+            assert brute.path_cost32(X, Y, p) == v
+            differ += v != oracle.dtw(X, Y)[0]
+    assert differ > 5
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_fp32_equals_fp64_on_exactly_representable_inputs(d):
+    """Small integers: every cost and sum is exact in float32, so the float32
+    program reproduces the float64 one bit for bit -- value, tie-broken path
+    and argmin codes (whose tie-break brute force pins) -- and so do the
+    batched DTW, score, DBA, medoid and Sub-DTW in float32 mode."""
+    r = rng(320 + d)
+    for _ in range(40):
+        M, N = int(r.integers(1, 9)), int(r.integers(1, 9))
+        X, Y = synth.integer_pair(r, M, N, d, hi=2)
+        a = oracle.dtw(X, Y, with_codes=True)
+        b = oracle.dtw32(X, Y, with_codes=True)
+        assert a[0] == b[0] and a[1] == b[1]
+        assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+        assert oracle.subdtw(X, Y) == oracle.subdtw(X, Y, fp32=True)
+    B = r.integers(-3, 4, (9, d)).astype(np.float64)
+    cyc = [r.integers(-3, 4, (int(N), d)).astype(np.float64) for N in (5, 9, 12, 1)]
+    for f in (oracle.dtw_batch, oracle.score_batch, oracle.dba_iterate, oracle.subdtw_batch):
+        for u, v in zip(f(B, cyc), f(B, cyc, fp32=True)):
+            assert np.array_equal(u, v), f.__name__
+    k64, D64 = oracle.medoid(cyc)
+    k32, D32 = oracle.medoid(cyc, fp32=True)
+    assert k64 == k32 and np.array_equal(D64, D32)
+
+
+def test_subdtw32_brute_value_and_window():
+    """Sub-DTW in float32: the minimum over every subsequence path of its
+    float32 cost, attained by the float32 DTW of X against Y[a*..b*]."""
+    r = rng(330)
+    for _ in range(20):
+        M, N = int(r.integers(1, 4)), int(r.integers(1, 6))
+        X, Y = _grid(r, (M, 2)), _grid(r, (N, 2))
+        v, a, b = oracle.subdtw(X, Y, fp32=True)
+        assert v == brute.subdtw32_value(X, Y)
+        assert 0 <= a <= b < N and oracle.dtw32(X, Y[a:b + 1])[0] == v
+
+
+def test_fp32_batch_functions_use_the_float32_program():
+    """Batched calls in float32 mode give, cycle by cycle, the float32 DTW of
+    the barycenter rounded to float32 (the DBA sums stay float64: the mean of
+    the cycle samples on the float32 paths)."""
+    r = rng(340)
+    B = r.standard_normal((14, 3))
+    cyc = [r.standard_normal((int(N), 3)).astype(np.float32).astype(np.float64)
+           for N in (10, 17, 3)]
+    dist, plen = oracle.dtw_batch(B, cyc, fp32=True)
+    score, dist2, plen2 = oracle.score_batch(B, cyc, fp32=True)
+    for k, c in enumerate(cyc):
+        v, n, path, _ = oracle.dtw32(B.astype(np.float32), c)
+        assert dist[k] == v == dist2[k] and plen[k] == n == plen2[k]
+        assert score[k] == v / n
+    Bo, cnt, _, _ = oracle.dba_iterate(B, cyc, fp32=True)
+    # per cycle: the samples aligned to each row summed in backtrack order;
+    # then the cycles folded in ascending order (the DBA update's order)
+    S = np.zeros_like(B)
+    C = np.zeros(B.shape[0])
+    for c in cyc:
+        _, _, path, _ = oracle.dtw32(B.astype(np.float32), c)
+        ps = np.zeros_like(B)
+        pc = np.zeros(B.shape[0])
+        for i, j in path[::-1]:
+            ps[i] = ps[i] + c[j]
+            pc[i] += 1
+        S = S + 1.0 * ps
+        C = C + 1.0 * pc
+    assert np.array_equal(cnt, C) and np.array_equal(Bo, S / C[:, None])
