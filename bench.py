@@ -45,6 +45,9 @@ sys.path.insert(0, ROOT)
 # gfx950 (MI355X): 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz; FP64 add/mul/fma/min
 # issue at one per lane per clock (78.6 TFLOP/s FP64 vector counts an FMA as 2).
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9          # 39.32e12 lane-ops/s
+# float32 and 32-bit integer VALU operations issue at twice that rate (157.3
+# TFLOP/s FP32 vector counts an FMA as 2): the peak of the float32-decision sweeps
+VALU_LANE_OPS_PEAK_F32 = 2 * VALU_LANE_OPS_PEAK  # 78.64e12 lane-ops/s
 HBM_PEAK_GBS = 8000.0
 
 
@@ -95,17 +98,17 @@ def c_soft_bwd(d: int, tau: float) -> float:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("wts_dtw.hip", "wts_soft.hip", "wts_device.h"):
+    for f in ("wts_sweep.h", "wts_dtw.hip", "wts_dtw32.hip", "wts_soft.hip", "wts_device.h"):
         with open(os.path.join(ROOT, "paper_2404_12134_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 KERNELS = {   # sweep -> rocprofv3 kernel name ({rho}: rows per lane of the plan)
-    "medoid": "void wts::(anonymous namespace)::dtw_fwd_kernel<float, float, 3, {rho}, 0, false>",
-    "dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, {rho}, 2, false>",
-    "score": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 3, {rho}, 1, false>",
-    "c5_dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, 6, {rho}, 2, false>",
+    "medoid": "void wts::(anonymous namespace)::dtw_fwd_kernel<float, float, double, 3, {rho}, 0, false>",
+    "dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, double, 3, {rho}, 2, false>",
+    "score": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, double, 3, {rho}, 1, false>",
+    "c5_dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, double, 6, {rho}, 2, false>",
     "c5_soft_fwd": "void wts::(anonymous namespace)::soft_fwd_kernel<float, 6, {rho}, false>",
     "c5_soft_bwd": "void wts::(anonymous namespace)::soft_bwd_kernel<float, 6, {rho}, false>",
 }
@@ -577,6 +580,8 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
     torch.cuda.synchronize()
     plan.check()
     t_score = e0.elapsed_time(e1) / 1e3
+    progress("headline: the DBA iteration with float32 decisions")
+    fp32 = fp32_dba_compare(wts, plan, off, d, dt, L, Y, it.A, arena, cells, sec, t_dba)
     speed = None
     if speedup:
         progress("headline: one-cycle-per-launch DBA comparison")
@@ -600,6 +605,7 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
         "roofline": roof,
         "autotune": it.tuned,
         "batched_vs_per_cycle": speed,
+        "fp32_decisions": fp32,
     }
     del graph, it, arena
     for _, _, gp in groups:
@@ -614,6 +620,70 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
 
 
 # ------------------------------------------------------------ extra sections
+
+def fp32_dba_compare(wts, plan, off, d, dt, L, Y, B, arena, cells, sec, t_dba):
+    """The DBA iteration of the headline workload with float32 decisions
+    (plan option decision = fp32; 4 and 5 rows per lane tried) against the
+    float64 one on the same barycenter: sweep and iteration times, the path
+    sweep's roofline against the float32 VALU peak, and how the results
+    differ (distances, path lengths, counts, the new barycenter).  Both plans
+    use the headline's arena as their DBA workspace, one after the other."""
+    import numpy as np
+    import torch
+    n = len(off) - 1
+    out64 = (torch.empty_like(B), torch.empty(L, dtype=torch.int64, device=B.device),
+             torch.empty(n, dtype=torch.float64, device=B.device))
+    out32 = tuple(torch.empty_like(t) for t in out64)
+    wts.dba_iterate(plan, B, Y, bary_out=out64[0], counts=out64[1], dist=out64[2])
+    sc64, d64, l64 = wts.anomaly_score(plan, B, Y)
+    best = None
+    tried = {}
+    for rho in (4, 5):
+        p32 = wts.Plan(off, d, dt, L, decision="fp32", rho=rho)
+        p32.set_workspace(wts.OP_DBA, arena)
+        wts.dba_iterate(p32, B, Y, bary_out=out32[0], counts=out32[1], dist=out32[2])
+        torch.cuda.synchronize()
+        p32.enable_timing(4)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        wts.dba_iterate(p32, B, Y, bary_out=out32[0], counts=out32[1], dist=out32[2])
+        e1.record()
+        torch.cuda.synchronize()
+        ms, nl = p32.sweep_ms(wts.OP_DBA)
+        p32.check()
+        tried[rho] = (ms / nl / 1e3, e0.elapsed_time(e1) / 1e3)
+        if best is None or tried[rho][1] < tried[best][1]:
+            best = rho
+        if rho == 4:
+            sc32, d32, l32 = wts.anomaly_score(p32, B, Y)
+        p32.close()
+    torch.cuda.synchronize()
+    sweep_s, iter_s = tried[best]
+    ops = cells * c_dba(d)
+    ach = ops / sweep_s / 1e12
+    peak = VALU_LANE_OPS_PEAK_F32 / 1e12
+    d64h, d32h = out64[2].cpu().numpy(), out32[2].cpu().numpy()
+    l64h, l32h = l64.cpu().numpy(), l32.cpu().numpy()
+    B64, B32 = out64[0].cpu().numpy(), out32[0].cpu().numpy()
+    return {
+        "rows_per_lane": best,
+        "candidates_s": {str(k): [round(v[0], 4), round(v[1], 4)] for k, v in tried.items()},
+        "dba_iteration_s": round(iter_s, 4), "dba_gcups": round(cells / iter_s / 1e9, 2),
+        "path_sweep": {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 3),
+                       "unit": "TOP/s", "frac": round(ach / peak, 4),
+                       "launch_ms": round(sweep_s * 1e3, 3), "ops_per_cell": c_dba(d)},
+        "fp64_dba_iteration_s": round(t_dba, 4),
+        "s_per_iteration_with_fp32_dba": round(sec - t_dba + iter_s, 4),
+        "vs_fp64": {
+            "max_rel_dist_diff": float(np.max(np.abs(d32h - d64h) / np.maximum(d64h, 1e-300))),
+            "cycles_with_other_path_length": int((l32h != l64h).sum()),
+            "rows_with_other_count": int((out32[1] != out64[1]).sum().item()),
+            "max_abs_bary_diff": float(np.max(np.abs(B32 - B64))),
+            "max_rel_score_diff": float(np.max(np.abs(sc32.cpu().numpy() - sc64.cpu().numpy())
+                                               / np.maximum(sc64.cpu().numpy(), 1e-300))),
+        },
+    }
+
 
 def dba_per_cycle_speedup(wts, plan, off, d, dt, L, Y, B, sequential=False):
     """Batched vs one-cycle-per-launch DBA iteration: the same kernels, run
@@ -1161,6 +1231,7 @@ def main():
         "autotune": head["autotune"],
         "cpu_baseline": head.get("cpu_baseline"),
         "batched_vs_per_cycle": head["batched_vs_per_cycle"],
+        "fp32_decisions": head.get("fp32_decisions"),
         "valu": valu,
         "extras": extras,
     }

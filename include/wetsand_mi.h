@@ -103,6 +103,8 @@ enum {
 
 enum { WTS_INIT_EUCLID_MEAN = 0, WTS_INIT_NEAREST = 1, WTS_INIT_COPY = 2 };
 
+enum { WTS_DECISION_FP64 = 0, WTS_DECISION_FP32 = 1 };
+
 typedef struct {
   int32_t cost;       /* WTS_COST_* for wts_dtw_align / wts_anomaly_score; DBA, Soft-DTW and
                          the medoid always use the squared cost                              */
@@ -113,6 +115,18 @@ typedef struct {
   int32_t grid;       /* workgroups of the persistent sweep (0 = tuned default)              */
   int32_t validate;   /* 1: every compute call first checks its inputs for NaN / infinity on
                          the device (see Conventions); 0: no check                           */
+  int32_t decision;   /* precision of the hard-DTW sweeps (wts_dtw_align, wts_dba_iterate,
+                         wts_anomaly_score[_noalloc], wts_medoid, wts_subdtw):
+                         WTS_DECISION_FP64 (0, default): cost, minima and argmins in
+                         float64, bit for bit the float64 definitions (Def. 3, Eq. 1, Eq. 2);
+                         WTS_DECISION_FP32 (1): the same operations in float32 on the
+                         float32 cycles and the barycenter rounded to float32 -- about
+                         twice the arithmetic rate, with values, paths and codes bit for
+                         bit those of the float32 evaluation of the same definitions
+                         (near-ties may resolve differently from float64).  Needs
+                         WTS_F32 cycles and the squared cost (else WTS_E_UNSUPPORTED).
+                         Path sums, DBA means and scores stay float64; the Soft-DTW
+                         calls do not read this field                                   */
   double band;        /* Soft-DTW only: Sakoe-Chiba bandwidth as a fraction w of the longer
                          length (Table I: 0.6); 0 = no band.  Cell (i, j) of an M x N pair
                          is kept iff |i (N-1) - j (M-1)| <= R min(M-1, N-1) with

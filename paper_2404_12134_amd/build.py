@@ -22,8 +22,8 @@ OBJDIR = os.path.join(HERE, "_build")
 # -fno-honor-nans lets min() map to a bare v_min_f64.
 # The Soft-DTW kernels never subtract two infinities: every computed cell has
 # at least one finite predecessor, so the same holds there.
-SOURCES = {"wts_dtw.hip": ["-fno-honor-nans"], "wts_soft.hip": ["-fno-honor-nans"],
-           "wts_abi.hip": [], "wts_aux.hip": []}
+SOURCES = {"wts_dtw.hip": ["-fno-honor-nans"], "wts_dtw32.hip": ["-fno-honor-nans"],
+           "wts_soft.hip": ["-fno-honor-nans"], "wts_abi.hip": [], "wts_aux.hip": []}
 ARCH = os.environ.get("WTS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

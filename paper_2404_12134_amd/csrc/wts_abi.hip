@@ -370,8 +370,8 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
   const int tk = timing_begin(p, x_is_cycle ? WTS_OP_MEDOID
                                  : mode == wts::MODE_PATH ? WTS_OP_DBA
                                  : mode == wts::MODE_SUB ? WTS_OP_SUBDTW : WTS_OP_SCORE, st);
-  HIP_TRY(wts::launch_fwd(p->d, ps.rho, mode, euc, x_is_cycle, p->dtype, a,
-                          default_grid(p, ps), st));
+  HIP_TRY(wts::launch_fwd(p->d, ps.rho, mode, euc, x_is_cycle, p->dtype,
+                          p->opts.decision == WTS_DECISION_FP32, a, default_grid(p, ps), st));
   timing_end(p, tk, st);
   return WTS_OK;
 }
@@ -432,6 +432,10 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
     return fail(WTS_E_UNSUPPORTED, "opts.rho = %d: 2, 4 or 5 supported", o.rho);
   if (o.grid < 0) return fail(WTS_E_ARG, "opts.grid = %d", o.grid);
   if (o.validate != 0 && o.validate != 1) return fail(WTS_E_ARG, "opts.validate = %d: 0 or 1", o.validate);
+  if (o.decision != WTS_DECISION_FP64 && o.decision != WTS_DECISION_FP32)
+    return fail(WTS_E_ARG, "opts.decision = %d: 0 or 1", o.decision);
+  if (o.decision == WTS_DECISION_FP32 && (dtype != WTS_F32 || o.cost != WTS_COST_SQEUCLID))
+    return fail(WTS_E_UNSUPPORTED, "float32 decisions need float32 cycles and the squared cost");
   if (!(o.band >= 0.0) || !std::isfinite(o.band)) return fail(WTS_E_ARG, "opts.band must be finite and >= 0");
   int ndev = 0;
   HIP_TRY(hipGetDeviceCount(&ndev));

@@ -24,8 +24,11 @@ struct WalkArgs {
   const int* skip;          // validation flag of the call (or null)
 };
 
-hipError_t launch_fwd(int d, int rho, int mode, bool euc, bool x_is_cycle, int ydtype,
+// fp32: the float32-decision instances (float32 cycles, squared cost only).
+hipError_t launch_fwd(int d, int rho, int mode, bool euc, bool x_is_cycle, int ydtype, bool fp32,
                       const FwdArgs& a, int grid, hipStream_t st);
+hipError_t launch_fwd32(int d, int rho, int mode, bool euc, bool x_is_cycle, int ydtype,
+                        const FwdArgs& a, int grid, hipStream_t st);
 hipError_t launch_walk(int d, int rho, int ydtype, bool emit, const WalkArgs& a, int n_items,
                        hipStream_t st);
 hipError_t launch_chain(const PairDesc* pairs, int n_pairs, const int* bnd_aux,

@@ -23,6 +23,7 @@ COST_SQ, COST_EUCLID = 0, 1
 (OP_ALIGN, OP_ALIGN_PATHS, OP_DBA, OP_SCORE, OP_SOFT_FWD, OP_SOFT_BWD, OP_MEDOID, OP_SUBDTW,
  OP_SOFT_GRAD_C) = range(9)
 INIT_EUCLID_MEAN, INIT_NEAREST, INIT_COPY = 0, 1, 2
+DECISION_FP64, DECISION_FP32 = 0, 1
 
 _lib = None
 
@@ -40,7 +41,8 @@ class WtsError(RuntimeError):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("cost", ctypes.c_int32), ("rho", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("validate", ctypes.c_int32), ("band", ctypes.c_double)]
+                ("validate", ctypes.c_int32), ("decision", ctypes.c_int32),
+                ("band", ctypes.c_double)]
 
 
 def load():
@@ -161,7 +163,8 @@ class Plan:
     the longer length (Table I)."""
 
     def __init__(self, offsets, d: int, dtype: str, L: int, device: int = 0, cost: str = "sq",
-                 rho: int = 0, grid: int = 0, band: float = 0.0, validate: bool = False):
+                 rho: int = 0, grid: int = 0, band: float = 0.0, validate: bool = False,
+                 decision: str = "fp64"):
         lib = load()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         self.offsets = off
@@ -172,8 +175,12 @@ class Plan:
         self.device = int(device)
         if dtype not in ("f32", "f64"):
             raise ValueError("dtype must be 'f32' or 'f64'")
+        if decision not in ("fp64", "fp32"):
+            raise ValueError("decision must be 'fp64' or 'fp32'")
+        self.decision = decision
         opts = _Opts(COST_EUCLID if cost == "euclid" else COST_SQ, int(rho), int(grid),
-                     1 if validate else 0, float(band))
+                     1 if validate else 0, DECISION_FP32 if decision == "fp32" else DECISION_FP64,
+                     float(band))
         h = ctypes.c_void_p()
         _check(lib.wts_plan_create(ctypes.byref(h), self.device, self.n, self.d,
                                    F32 if dtype == "f32" else F64,

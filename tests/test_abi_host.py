@@ -78,9 +78,14 @@ def test_plan_create_rejects_bad_shapes_before_any_gpu_call(lib):
         assert _create(lib, opts=ctypes.byref(_Opts(0, rho, 0, 0)))[0] == WTS_E_UNSUPPORTED
     assert _create(lib, opts=ctypes.byref(_Opts(0, 4, -1, 0)))[0] == WTS_E_ARG
     for band in (-0.5, float("nan"), float("inf")):   # Sakoe-Chiba bandwidth
-        assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 0, band)))[0] == WTS_E_ARG
+        assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 0, band=band)))[0] == WTS_E_ARG
     assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 7)))[0] == WTS_E_ARG   # validate: 0 or 1
     assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, -1)))[0] == WTS_E_ARG
+    # decision: 0 (float64) or 1 (float32), the latter on float32 cycles with the squared cost
+    for dec in (-1, 2):
+        assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 0, dec)))[0] == WTS_E_ARG
+    assert _create(lib, dtype=1, opts=ctypes.byref(_Opts(0, 4, 0, 0, 1)))[0] == WTS_E_UNSUPPORTED
+    assert _create(lib, opts=ctypes.byref(_Opts(1, 4, 0, 0, 1)))[0] == WTS_E_UNSUPPORTED
 
 
 def test_null_plan_is_rejected(lib):
@@ -162,3 +167,14 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(wetsand, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         wetsand.load()
+
+
+def test_binding_options_struct_matches_the_header():
+    """The ctypes mirror of wts_opts lists the header's fields in order."""
+    import re
+    from paper_2404_12134_amd.wetsand import _Opts
+    body = open(HEADER).read()
+    struct = body[body.index("typedef struct {", body.index("WTS_DECISION_FP64")):]
+    struct = struct[:struct.index("} wts_opts;")]
+    fields = re.findall(r"^\s*(?:int32_t|double)\s+(\w+);", struct, re.M)
+    assert fields == [f for f, _ in _Opts._fields_]

@@ -1,0 +1,205 @@
+"""GPU parity of the float32-decision sweeps (plan decision "fp32") against
+the oracle's float32 program, through the C ABI.
+
+With decision = fp32 the sweeps evaluate the cost, the minima and the argmin
+codes in float32 on the float32 cycles and the barycenter rounded to float32
+(one rounding, to nearest), in the same operation order as the oracle's
+float32 program (the same C source as its float64 one).  Distances, path
+lengths, paths, DBA barycenters (whose sums stay float64), counts, scores,
+medoid matrices and Sub-DTW (value, a*, b*) must match it BIT FOR BIT.
+Against the float64 decisions the values are gated by a float32 rounding
+bound, and the paths that differ (near-ties that float32 resolves the other
+way) are counted and reported.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_12134_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def as64(cycles):
+    return [np.asarray(c, dtype=np.float64) for c in cycles]
+
+
+def plan_of(wts, cycles, d, L, **kw):
+    Y, off, dt = wts.pack_cycles(cycles, dtype="f32")
+    return wts.Plan(off, d, dt, L, decision="fp32", **kw), Y
+
+
+SHAPES = [  # (L, lengths): ragged tails, one and several strips, one-sample series
+    (1, [1, 5, 64]),
+    (63, [17, 200]),
+    (65, [300, 1]),
+    (257, [513, 40]),
+    (700, [1, 1000, 333, 64]),
+]
+
+
+@pytest.mark.parametrize("rho", [2, 4, 5])
+@pytest.mark.parametrize("d", [1, 3, 6, 8])
+@pytest.mark.parametrize("L,lens", SHAPES)
+def test_fp32_align_paths_bitwise(wts, d, rho, L, lens):
+    import torch
+    r = rng(L * 17 + d * 3 + rho)
+    B = r.standard_normal((L, d))
+    cyc = [r.standard_normal((N, d)).astype(np.float32) for N in lens]
+    plan, Y = plan_of(wts, cyc, d, L, rho=rho)
+    say("case fp32 align d=%d rho=%d L=%d lens=%s" % (d, rho, L, lens))
+    dist, plen, pth = wts.dtw_align(plan, torch.from_numpy(B).cuda(), Y, paths=True)
+    torch.cuda.synchronize()
+    assert plan.status() == wts.OK
+    dist, plen = dist.cpu().numpy(), plen.cpu().numpy()
+    for k, c in enumerate(cyc):
+        od, ol, op, _ = oracle.dtw32(B, c)
+        assert dist[k] == od and plen[k] == ol, (k, dist[k], od)
+        np.testing.assert_array_equal(wts.path_of(plan, pth, torch.from_numpy(plen), k), op)
+
+
+@pytest.mark.parametrize("rho", [2, 4, 5])
+def test_fp32_dba_and_scores_bitwise(wts, rho):
+    import torch
+    w = synth.make(3, n=9, len_range=(60, 1500), L=700)
+    cyc = [np.asarray(c, np.float32) for c in w.cycles]
+    _, B0 = oracle.nearest_init(as64(cyc), 700)
+    plan, Y = plan_of(wts, cyc, w.d, 700, rho=rho)
+    wt = np.linspace(0.5, 2.0, w.n)
+    Bg = torch.from_numpy(B0).cuda()
+    Bo = B0
+    for it, weights in enumerate((None, wt, None)):
+        say("case fp32 dba rho=%d iteration %d" % (rho, it))
+        Wt = None if weights is None else torch.from_numpy(weights).cuda()
+        Bg, counts, dist = wts.dba_iterate(plan, Bg, Y, Wt)
+        Bn, K, od, _ = oracle.dba_iterate(Bo, as64(cyc), weights, fp32=True)
+        np.testing.assert_array_equal(Bg.cpu().numpy(), Bn)
+        np.testing.assert_array_equal(counts.cpu().numpy(), K)
+        np.testing.assert_array_equal(dist.cpu().numpy(), od)
+        Bo, Bg = Bn, Bg.clone()
+    say("case fp32 scores rho=%d" % rho)
+    score, dist, plen = wts.anomaly_score(plan, torch.from_numpy(Bo).cuda(), Y)
+    os_, od, ol = oracle.score_batch(Bo, as64(cyc), fp32=True)
+    np.testing.assert_array_equal(score.cpu().numpy(), os_)
+    np.testing.assert_array_equal(dist.cpu().numpy(), od)
+    np.testing.assert_array_equal(plen.cpu().numpy(), ol)
+    assert plan.status() == wts.OK
+
+
+@pytest.mark.parametrize("rho", [0, 2, 5])
+def test_fp32_medoid_bitwise(wts, rho):
+    w = synth.make(2, n=9, len_range=(200, 700))
+    cyc = [np.asarray(c, np.float32) for c in w.cycles]
+    plan, Y = plan_of(wts, cyc, 3, 0, rho=rho)
+    say("case fp32 medoid rho", rho)
+    k, Dm, tot = wts.medoid(plan, Y)
+    ko, Do = oracle.medoid(as64(cyc), fp32=True)
+    np.testing.assert_array_equal(Dm.cpu().numpy(), Do)
+    assert int(k.item()) == ko
+
+
+@pytest.mark.parametrize("d", [1, 3, 6, 8])
+def test_fp32_subdtw_bitwise(wts, d):
+    import torch
+    r = rng(60 + d)
+    for M, lens in [(5, [1, 2, 40, 65]), (200, [400, 399, 1, 64]), (257, [514, 600])]:
+        X = r.standard_normal((M, d))
+        wins = [r.standard_normal((N, d)).astype(np.float32) for N in lens]
+        plan, Y = plan_of(wts, wins, d, M)
+        say("case fp32 subdtw d=%d M=%d" % (d, M))
+        v, a, b = wts.subdtw(plan, torch.from_numpy(X).cuda(), Y)
+        torch.cuda.synchronize()
+        ov, oa, ob = oracle.subdtw_batch(X, as64(wins), fp32=True)
+        np.testing.assert_array_equal(v.cpu().numpy(), ov)
+        np.testing.assert_array_equal(a.cpu().numpy(), oa)
+        np.testing.assert_array_equal(b.cpu().numpy(), ob)
+
+
+def test_fp32_ties_equal_fp64_on_exact_inputs(wts):
+    """Small integers (every cost and sum exact in float32, many tied paths):
+    the float32 sweeps reproduce the float64 ones bit for bit."""
+    import torch
+    r = rng(71)
+    for L, lens in [(9, [7, 13, 1]), (300, [290, 310, 64, 600])]:
+        B = r.integers(0, 3, (L, 2)).astype(np.float64)
+        cyc = [r.integers(0, 3, (N, 2)).astype(np.float32) for N in lens]
+        Y, off, dt = wts.pack_cycles(cyc, dtype="f32")
+        out = []
+        for dec in ("fp64", "fp32"):
+            plan = wts.Plan(off, 2, dt, L, decision=dec)
+            dist, plen, pth = wts.dtw_align(plan, torch.from_numpy(B).cuda(), Y, paths=True)
+            Bo, K, _ = wts.dba_iterate(plan, torch.from_numpy(B).cuda(), Y)
+            torch.cuda.synchronize()
+            paths = [wts.path_of(plan, pth, plen, k) for k in range(len(cyc))]
+            out.append((dist.cpu().numpy(), plen.cpu().numpy(), Bo.cpu().numpy(),
+                        K.cpu().numpy()) + tuple(paths))
+        say("case fp32 = fp64 on exact inputs L=%d" % L)
+        for u, v in zip(*out):
+            np.testing.assert_array_equal(u, v)
+
+
+def test_fp32_against_fp64_rounding_bound_and_path_flips(wts):
+    """Against float64 decisions: each value is within the float32 rounding
+    of the float64 one -- a path sum of |pi| cells, each cost of d channels,
+    carries at most (|pi| + 2d + 2) float32 roundings of at most 2^-24 of the
+    running magnitude -- and the share of paths that float32 resolves
+    differently is reported (not gated)."""
+    import torch
+    w = synth.make(2, n=64, len_range=(800, 1200))
+    cyc = [np.asarray(c, np.float32) for c in w.cycles]
+    r = rng(72)
+    B = oracle.resample(np.asarray(cyc[0], np.float64), 1000) + 0.01 * r.standard_normal((1000, 3))
+    Y, off, dt = wts.pack_cycles(cyc, dtype="f32")
+    res = {}
+    for dec in ("fp64", "fp32"):
+        plan = wts.Plan(off, 3, dt, 1000, decision=dec)
+        dist, plen, pth = wts.dtw_align(plan, torch.from_numpy(B).cuda(), Y, paths=True)
+        torch.cuda.synchronize()
+        res[dec] = (dist.cpu().numpy(), plen.cpu().numpy(),
+                    [wts.path_of(plan, pth, plen, k) for k in range(len(cyc))])
+    d64, l64, p64 = res["fp64"]
+    d32, l32, p32 = res["fp32"]
+    bound = (np.maximum(l64, l32) + 2 * 3 + 2) * 2.0 ** -24 * d64
+    assert (np.abs(d32 - d64) <= bound).all(), np.max(np.abs(d32 - d64) / np.maximum(d64, 1e-30))
+    flips = sum(not np.array_equal(a, b) for a, b in zip(p64, p32))
+    say("fp32 vs fp64: max rel diff %.3g, paths that differ %d of %d"
+        % (np.max(np.abs(d32 - d64) / d64), flips, len(cyc)))
+
+
+def test_fp32_sampled_at_the_512_cycle_size(wts):
+    """The 512-cycle workload (log-uniform 1k..20k samples, L = 10000): one
+    float32-decision DBA iteration; three cycles, the longest included,
+    checked against the oracle's float32 program (distance, path length, and
+    the rows' sums through the scores), the rest by properties."""
+    import torch
+    w = synth.make(3)
+    cyc = [np.asarray(c, np.float32) for c in w.cycles]
+    k0, B0 = oracle.nearest_init(as64(cyc), w.L)
+    plan, Y = plan_of(wts, cyc, w.d, w.L)
+    say("case fp32 512-cycle dba")
+    Bg, counts, dist = wts.dba_iterate(plan, torch.from_numpy(B0).cuda(), Y)
+    score, d2, plen = wts.anomaly_score(plan, torch.from_numpy(B0).cuda(), Y)
+    torch.cuda.synchronize()
+    assert plan.status() == wts.OK
+    dist, d2, plen = dist.cpu().numpy(), d2.cpu().numpy(), plen.cpu().numpy()
+    np.testing.assert_array_equal(dist, d2)
+    longest = int(np.argmax(w.lengths))
+    for k in sorted({0, 257, longest}):
+        say("  cycle", k, "N =", int(w.lengths[k]))
+        od, ol = oracle.dtw_batch(B0, [cyc[k].astype(np.float64)], fp32=True)
+        assert dist[k] == od[0] and plen[k] == ol[0]
+    K = counts.cpu().numpy()
+    assert (K >= w.n).all() and K.sum() == plen.sum()
+    assert np.isfinite(Bg.cpu().numpy()).all()
