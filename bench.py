@@ -992,8 +992,9 @@ def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
     rec["grad_cycles"] = {"ms": round(1e3 * tg, 2),
                           "gcups_fwd_bwd": round(2 * cells / tg / 1e9, 2)}
     del Y64
-    # the Table I band (0.6), gamma 0.1
-    bplan = wts.Plan(off, d, dt, L, band=0.6, grid=tuned["grid"])
+    # the Table I band (0.6), gamma 0.1, its own tuned grid
+    bplan, btuned = autotune.tuned_plan(off, d, dt, L, op="soft", cycles=Y, bary=B0, reps=1,
+                                        cache_path=None, band=0.6)
     bcells = band_cells(L, w.lengths, 0.6)
     sdb = wts.SoftDescent([(0, w.n, bplan)], Y, off, L, d, 0.1, gv, 0.5)
     B = B0.clone()
@@ -1012,7 +1013,8 @@ def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
     rec["band_0.6"] = {"cells_in_band_per_pass": bcells,
                        "band_fraction": round(bcells / cells, 4), "s_per_step": round(sec, 4),
                        "gcups_fwd_bwd_in_band": round(2 * bcells / sec / 1e9, 2),
-                       "forward_ms": round(tf / nf, 2), "backward_ms": round(tb / nb, 2)}
+                       "forward_ms": round(tf / nf, 2), "backward_ms": round(tb / nb, 2),
+                       "autotune": {k: btuned[k] for k in ("rho", "grid", "table")}}
     del sdb
     bplan.close()
     if lbfgs:

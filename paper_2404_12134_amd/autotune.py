@@ -10,7 +10,8 @@ issue rate dominate, with many pairs the per-cell instruction count does.
 `tune` times every candidate shape on the batch (the caller's cycles, or
 seeded random values of the same lengths) and keeps the fastest; results are
 cached in a JSON file keyed by (GPU architecture, compute units, operation,
-d, dtype, L, n, length buckets).
+d, dtype, L, n, length buckets, and the Sakoe-Chiba band and decision
+precision when they are set).
 
 Every shape computes bit-identical results (each pair's dynamic program runs
 the same operations whatever the strip-to-wave assignment), so the choice
@@ -103,7 +104,8 @@ def _run_op(wts, plan, op: str, bary, Y, outs):
 
 def tune(offsets, d: int, dtype: str, L: int, op: str = "dba", cycles=None, bary=None,
          reps: int = 3, device: int = 0, cache_path: Optional[str] = DEFAULT_CACHE,
-         refresh: bool = False, shapes=None, workspace=None) -> dict:
+         refresh: bool = False, shapes=None, workspace=None, band: float = 0.0,
+         decision: str = "fp64") -> dict:
     """Times every candidate shape for `op` on this batch and returns
     {"rho": .., "grid": .., "ms": .., "table": [[rho, grid, ms], ...], "key": ..}.
 
@@ -113,7 +115,9 @@ def tune(offsets, d: int, dtype: str, L: int, op: str = "dba", cycles=None, bary
     rows.  L = 0 with op = "medoid".  shapes: the (rho, grid) candidates
     (default `candidates(op, cus)`); workspace: a caller-owned 256-byte
     aligned uint8 buffer used as the DBA workspace or the Soft-DTW
-    checkpoints of every candidate (for batches whose buffers are large)."""
+    checkpoints of every candidate (for batches whose buffers are large);
+    band, decision: plan options of the candidates (a banded Soft-DTW sweep
+    and the float32-decision DTW sweeps have shapes of their own)."""
     import torch
     from . import wetsand as wts
 
@@ -129,6 +133,10 @@ def tune(offsets, d: int, dtype: str, L: int, op: str = "dba", cycles=None, bary
     cus = int(props.multi_processor_count)
     shapes = list(candidates(op, cus) if shapes is None else shapes)
     key = cache_key("%s-%dcu" % (arch, cus), op, d, dtype, L, lengths)
+    if band:
+        key += "|band%g" % band
+    if decision != "fp64":
+        key += "|" + decision
     if cache_path and not refresh:
         hit = load_cache(cache_path).get(key)
         if hit:
@@ -152,7 +160,8 @@ def tune(offsets, d: int, dtype: str, L: int, op: str = "dba", cycles=None, bary
 
     table = []
     for rho, grid in shapes:
-        plan = wts.Plan(off, d, dtype, L, device=device, rho=rho, grid=grid)
+        plan = wts.Plan(off, d, dtype, L, device=device, rho=rho, grid=grid, band=band,
+                        decision=decision)
         if workspace is not None and op == "dba":
             plan.set_workspace(wts.OP_DBA, workspace)
         _run_op(wts, plan, op, B, Y, outs)            # warm-up: workspace, code paths
@@ -179,4 +188,5 @@ def tuned_plan(offsets, d: int, dtype: str, L: int, op: str = "dba", **kw):
     from . import wetsand as wts
     t = tune(offsets, d, dtype, L, op=op, **kw)
     return wts.Plan(offsets, d, dtype, L, device=kw.get("device", 0), rho=t["rho"],
-                    grid=t["grid"]), t
+                    grid=t["grid"], band=kw.get("band", 0.0),
+                    decision=kw.get("decision", "fp64")), t
