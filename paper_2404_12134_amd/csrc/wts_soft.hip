@@ -4,8 +4,11 @@
 // k = log2(e) / gamma, so the soft-min of Eq. 3 becomes
 //   min'(a, b, c) = m - log2(2^(m-a) + 2^(m-b) + 2^(m-c)),  m = min(a, b, c),
 // evaluated with float64 differences and the hardware base-2 exponential and
-// logarithm (v_exp_f32 / v_log_f32); every cost delta enters as delta * k.
-// The Soft-DTW value is r'(M-1, N-1) / k.
+// logarithm (v_exp_f32 / v_log_f32).  Every cost delta enters as delta * k:
+// the kernels take the series multiplied by sqrt(k) when they load them, so
+// the squared differences come out scaled with no multiply per cell (the
+// gradient's sums are scaled back once per row).  The Soft-DTW value is
+// r'(M-1, N-1) / k.
 //
 // Forward.  Same skewed wavefront sweep as the DTW kernels (one wave per strip
 // of 64*RHO rows, strips of a pair chained through device memory).  It keeps
@@ -159,6 +162,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const double INF = inf_d();
   const double k = a.kscale;
+  const double sk = __builtin_sqrt(k);   // x and y enter as sqrt(k) x, sqrt(k) y
   if (skipped(a.skip)) return;   // every workgroup: no strip waits for another
 
   for (;;) {
@@ -190,7 +194,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     for (int r = 0; r < RHO; ++r)
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        xr[r][c] = (ib + r < M) ? a.x[(pd.x_off + ib + r) * D + c] : 0.0;
+        xr[r][c] = (ib + r < M) ? a.x[(pd.x_off + ib + r) * D + c] * sk : 0.0;
     double left[RHO];
 #pragma unroll
     for (int r = 0; r < RHO; ++r) left[r] = INF;
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     {
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        yv[c] = lane < N ? static_cast<double>(Y[(pd.y_off + lane) * D + c]) : 0.0;
+        yv[c] = lane < N ? static_cast<double>(Y[(pd.y_off + lane) * D + c]) * sk : 0.0;
 #pragma unroll
       for (int c = 0; c < D; ++c) ring_put(ys[c], lane, yv[c]);
     }
@@ -295,10 +299,10 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
               if constexpr (BAND) {
                 const bool inb = __builtin_fabs(bd0 + (double)r * (double)(N - 1)) <= band_b;
                 const SoftMin sm = softmin3_band(dg, up, lf, inb);
-                rv = inb ? sq_cost<D>(xr[r], y) * k + sm.v : INF;
+                rv = inb ? sq_cost<D>(xr[r], y) + sm.v : INF;
               } else {
                 const SoftMin sm = softmin3(dg, up, lf);
-                rv = sq_cost<D>(xr[r], y) * k + sm.v;
+                rv = sq_cost<D>(xr[r], y) + sm.v;
               }
               dg = lf;
               up = rv;
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
         const int j = t0 + kChunk + lane;
 #pragma unroll
         for (int c = 0; c < D; ++c)
-          ring_put(ys[c], j & (kRing - 1), j < N ? static_cast<double>(yraw[c]) : 0.0);
+          ring_put(ys[c], j & (kRing - 1), j < N ? static_cast<double>(yraw[c]) * sk : 0.0);
       }
       __syncthreads();
     }
@@ -396,6 +400,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const double INF = inf_d();
   const double k = a.kscale;
+  const double sk = __builtin_sqrt(k);   // x and y enter as sqrt(k) x, sqrt(k) y
   if (skipped(a.skip)) return;   // every workgroup: no strip waits for another
 
   for (;;) {
@@ -451,7 +456,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
     for (int r = 0; r < RHO; ++r)
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        xr[r][c] = (ib + r < M) ? a.x[(pd.x_off + ib + r) * D + c] : 0.0;
+        xr[r][c] = (ib + r < M) ? a.x[(pd.x_off + ib + r) * D + c] * sk : 0.0;
 
     double acc_e[RHO], acc_ey[RHO][D];        // float64 row accumulators
     float pl[RHO], pdg[RHO];                  // pending left / diagonal pushes into each row
@@ -493,7 +498,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
 #pragma unroll
         for (int c = 0; c < D; ++c)
           ring_put(ys[c], j & (kRing - 1),
-                   (j >= 0 && j < N) ? static_cast<double>(Y[(pd.y_off + j) * D + c]) : 0.0);
+                   (j >= 0 && j < N) ? static_cast<double>(Y[(pd.y_off + j) * D + c]) * sk : 0.0);
       }
     }
 
@@ -593,7 +598,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
               // receives and passes on exactly nothing
               const bool inb = __builtin_fabs(bd0 + (double)r * (double)(N - 1)) <= band_b;
               const SoftMin sm = softmin3_band(dg, up, lf, inb);
-              const double rv = inb ? sq_cost<D>(xr[r], y) * k + sm.v : INF;
+              const double rv = inb ? sq_cost<D>(xr[r], y) + sm.v : INF;
               const float rs = __builtin_amdgcn_rcpf(inb ? sm.s : 1.0f);
               wu[u][r] = inb ? sm.eu * rs : 0.0f;
               wl[u][r] = inb ? sm.el * rs : 0.0f;
@@ -602,7 +607,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
               left[r] = rv;
             } else {
               const SoftMin sm = softmin3(dg, up, lf);
-              const double rv = sq_cost<D>(xr[r], y) * k + sm.v;
+              const double rv = sq_cost<D>(xr[r], y) + sm.v;
               const float rs = __builtin_amdgcn_rcpf(sm.s);   // s >= 1: the minimum's term is 1
               wu[u][r] = sm.eu * rs;
               wl[u][r] = sm.el * rs;
@@ -701,7 +706,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
         const bool in = jn >= 0 && jn < N;
 #pragma unroll
         for (int c = 0; c < D; ++c)
-          ring_put(ys[c], jn & (kRing - 1), in ? static_cast<double>(yraw[c]) : 0.0);
+          ring_put(ys[c], jn & (kRing - 1), in ? static_cast<double>(yraw[c]) * sk : 0.0);
       }
       __syncthreads();
     }
@@ -744,7 +749,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
         const int64_t o = grow + i;
 #pragma unroll
         for (int c = 0; c < D; ++c)
-          a.gsum[o * D + c] = 2.0 * (xr[r][c] * acc_e[r] - acc_ey[r][c]);
+          a.gsum[o * D + c] = 2.0 * (xr[r][c] * acc_e[r] - acc_ey[r][c]) / sk;
         a.hsum[o] = acc_e[r];
       }
     }
