@@ -452,7 +452,8 @@ class BarycenterIteration:
                 self.ev[1].elapsed_time(self.ev[2]) / 1e3)
 
 
-def c5_setup(wts, dev, gamma: float = 0.1, max_group_gib: float = 215.0, tune: bool = False):
+def c5_setup(wts, dev, gamma: float = 0.1, max_group_gib: float = 215.0, tune: bool = False,
+             tune_cache=None):
     """The headline's plans, arena and iteration.  tune=True first times the
     sweep shapes on the workload itself (DBA: 4 or 5 rows per lane x grid
     candidates; Soft-DTW: grid candidates on the first checkpoint group),
@@ -472,11 +473,11 @@ def c5_setup(wts, dev, gamma: float = 0.1, max_group_gib: float = 215.0, tune: b
         cus = torch.cuda.get_device_properties(dev).multi_processor_count
         shapes = [(r, g) for r in (4, 5) for g in autotune.grid_candidates("dba", cus)]
         td = autotune.tune(off, w.d, dt, w.L, op="dba", cycles=Y, bary=B0, reps=1,
-                           cache_path=None, shapes=shapes, workspace=arena)
+                           cache_path=tune_cache, shapes=shapes, workspace=arena)
         a, b, _ = groups[0]
         ts = autotune.tune(off[a:b + 1] - off[a], w.d, dt, w.L, op="soft",
-                           cycles=Y[int(off[a]):int(off[b])], bary=B0, reps=1, cache_path=None,
-                           workspace=arena)
+                           cycles=Y[int(off[a]):int(off[b])], bary=B0, reps=1,
+                           cache_path=tune_cache, workspace=arena)
         for _, _, gp in groups:
             gp.close()
         plan.close()
@@ -513,10 +514,11 @@ def c5_kernel_times(wts, it, groups):
 
 
 def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.1,
-                speedup: bool = True, cpu: bool = True):
+                speedup: bool = True, cpu: bool = True, tune_cache=None, fp32: bool = True):
     import torch
     progress("headline: generating the 256-cycle workload, tuning the sweep shapes")
-    w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, gamma, tune=True)
+    w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, gamma, tune=True,
+                                                      tune_cache=tune_cache)
     L, d = w.L, w.d
     cells = L * int(w.lengths.sum())
     progress("headline: %d Soft-DTW groups, arena %.1f GiB; capturing the iteration"
@@ -580,8 +582,10 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
     torch.cuda.synchronize()
     plan.check()
     t_score = e0.elapsed_time(e1) / 1e3
-    progress("headline: the DBA iteration with float32 decisions")
-    fp32 = fp32_dba_compare(wts, plan, off, d, dt, L, Y, it.A, arena, cells, sec, t_dba)
+    fp32_rec = None
+    if fp32:
+        progress("headline: the DBA iteration with float32 decisions")
+        fp32_rec = fp32_dba_compare(wts, plan, off, d, dt, L, Y, it.A, arena, cells, sec, t_dba)
     speed = None
     if speedup:
         progress("headline: one-cycle-per-launch DBA comparison")
@@ -605,7 +609,7 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
         "roofline": roof,
         "autotune": it.tuned,
         "batched_vs_per_cycle": speed,
-        "fp32_decisions": fp32,
+        "fp32_decisions": fp32_rec,
     }
     del graph, it, arena
     for _, _, gp in groups:
@@ -1115,7 +1119,8 @@ def only_phase(args, wts, dev):
                           "valu": valu_rates()}))
         return
     if args.only == "c5":
-        w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, tune=True)
+        w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, tune=True,
+                                                          tune_cache=args.tune_cache)
         for _ in range(args.steps):
             it.run()
         torch.cuda.synchronize()
@@ -1172,6 +1177,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the float32-decision DBA comparison of the headline")
+    ap.add_argument("--tune-cache", metavar="JSON", default=None,
+                    help="keep the headline's tuned sweep shapes in this file: a later run "
+                         "with the same file (e.g. under a profiler) reuses them untimed")
     ap.add_argument("--no-speedup", action="store_true",
                     help="skip the batched vs one-cycle-per-launch comparisons")
     ap.add_argument("--no-extras", action="store_true",
@@ -1204,7 +1214,8 @@ def main():
     tau = valu["tau"]
     progress("valu rates measured (tau %s)" % tau)
     head = c5_headline(wts, dev, args.steps, args.warmup, tau, speedup=not args.no_speedup,
-                       cpu=not args.no_cpu_baseline)
+                       cpu=not args.no_cpu_baseline, tune_cache=args.tune_cache,
+                       fp32=not args.no_fp32)
     progress("headline done: %.1f GCUPS" % head["value"])
     extras = {}
     if not args.no_extras:
