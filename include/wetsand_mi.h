@@ -75,11 +75,11 @@ typedef enum {
   WTS_E_SHAPE = -2,        /* n, d, L or a cycle length out of range */
   WTS_E_DTYPE = -3,        /* dtype is not WTS_F32 / WTS_F64 */
   WTS_E_WORKSPACE = -4,    /* ws_bytes (or ckpt_bytes) smaller than required */
-  WTS_E_CAPACITY = -5,     /* a size beyond a fixed limit of this build: L or a cycle longer
+  WTS_E_CAPACITY = -5,     /* a size beyond a fixed limit of this library: L or a cycle longer
                               than 2^24 samples, more than 2^30 sweep items (pairs x strips) */
   WTS_E_HIP = -6,          /* a HIP runtime call failed */
   WTS_E_NONFINITE = -7,    /* (wts_plan_status) a validated call found a NaN or an infinity */
-  WTS_E_UNSUPPORTED = -8,  /* valid request this build does not implement */
+  WTS_E_UNSUPPORTED = -8,  /* valid request this library does not implement */
   WTS_E_DEVICE = -9        /* (wts_plan_status) a kernel reported an inconsistency: a strip
                               gave up waiting for its neighbour (about a second), or path
                               recovery met inconsistent tags; results are undefined        */

@@ -130,7 +130,7 @@ def subdtw(X, Y, kind="sq"):
 
 
 def in_band(i: int, j: int, M: int, N: int, w: float) -> bool:
-    """Sakoe-Chiba band of Table I, as this build reads it: a band of radius
+    """Sakoe-Chiba band of Table I, as the oracle reads it: a band of radius
     R = ceil(w max(M, N)) around the diagonal from (0, 0) to (M-1, N-1),
     measured along the longer side (R at least ceil(max(M-1, N-1) /
     min(M-1, N-1))); w <= 0 is no band."""
