@@ -338,13 +338,14 @@ def segment_alpha(M: int) -> int:
     return int(0.15 * M)
 
 
-def segment(X, Y, kind=SQEUCLID):
+def segment(X, Y, kind=SQEUCLID, fp32=False):
     """The segmentation loop of Sec. III-B, 0-based and half-open windows:
     ws = 0; repeat: window Y[ws : min(ws + 2M, N)], (a*, b*) of its Sub-DTW
     made absolute, cycle Y[a* .. b*] kept, ws <- b* - alpha, while ws < N.
     Where b* - alpha would not move the window forward (the paper does not
     say what then), it restarts just past the match: ws <- b* + 1.
-    Returns [(a*, b*, value)] in order."""
+    Returns [(a*, b*, value)] in order.  fp32: each Sub-DTW with float32
+    decisions."""
     X, Y = _series(X), _series(Y)
     M, N = X.shape[0], Y.shape[0]
     alpha = segment_alpha(M)
@@ -352,7 +353,7 @@ def segment(X, Y, kind=SQEUCLID):
     ws = 0
     while ws < N:
         we = min(ws + 2 * M, N)
-        v, a, b = subdtw(X, Y[ws:we], kind)
+        v, a, b = subdtw(X, Y[ws:we], kind, fp32=fp32)
         out.append((ws + a, ws + b, v))
         ws = ws + b - alpha if b - alpha > 0 else ws + b + 1
     return out

@@ -733,7 +733,7 @@ def segment_alpha(M: int) -> int:
 
 
 def segment(x: torch.Tensor, streams: Sequence[torch.Tensor], dtype: str,
-            alpha: Optional[int] = None, device: int = 0):
+            alpha: Optional[int] = None, device: int = 0, decision: str = "fp64"):
     """The segmentation of Sec. III-B for several streams at once.
 
     Each stream s keeps a window start ws_s (0 at first).  Every round runs
@@ -746,7 +746,8 @@ def segment(x: torch.Tensor, streams: Sequence[torch.Tensor], dtype: str,
     stream, the list of (a*, b*, value) with absolute sample indices.
 
     Plans are cached by window lengths, so rounds in which every window is
-    2M long reuse one plan."""
+    2M long reuse one plan.  decision: the plans' decision precision ("fp32"
+    needs float32 streams)."""
     M, d = int(x.shape[0]), int(x.shape[1])
     if x.dtype != torch.float64 or not x.is_contiguous():
         raise ValueError("x must be a contiguous float64 [M][d] tensor")
@@ -771,7 +772,7 @@ def segment(x: torch.Tensor, streams: Sequence[torch.Tensor], dtype: str,
             if plan is None:
                 off = np.zeros(len(lens) + 1, dtype=np.int64)
                 off[1:] = np.cumsum(lens)
-                plan = plans[lens] = Plan(off, d, dtype, M, device=device)
+                plan = plans[lens] = Plan(off, d, dtype, M, device=device, decision=decision)
             win = torch.cat([streams[k][ws[k]:e] for k, e in zip(live, ends)]).contiguous()
             v, a, b = subdtw(plan, x, win)
             v, a, b = v.cpu().numpy(), a.cpu().numpy(), b.cpu().numpy()

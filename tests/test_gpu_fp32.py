@@ -203,3 +203,20 @@ def test_fp32_sampled_at_the_512_cycle_size(wts):
     K = counts.cpu().numpy()
     assert (K >= w.n).all() and K.sum() == plen.sum()
     assert np.isfinite(Bg.cpu().numpy()).all()
+
+
+def test_fp32_segmentation_matches_the_float32_oracle_loop(wts):
+    """The segmentation loop of Sec. III-B with float32-decision plans: the
+    same cycles, in the same order, with the same costs as the oracle's loop
+    run with its float32 Sub-DTW on each stream alone."""
+    import torch
+    X, _, _ = synth.make_stream(11, 1, (190, 210), 3, dtype="f32", template_seed=7)
+    Xd = X.astype(np.float64)
+    streams = [synth.make_stream(seed, n, (190, 210), 3, dtype="f32", template_seed=7)[1]
+               for seed, n in ((31, 8), (32, 11))]
+    say("case fp32 segmentation")
+    dev = [torch.from_numpy(np.ascontiguousarray(Y)).cuda() for Y in streams]
+    got = wts.segment(torch.from_numpy(Xd).cuda(), dev, "f32", decision="fp32")
+    for Y, g in zip(streams, got):
+        assert g == oracle.segment(Xd, Y.astype(np.float64), fp32=True)
+        assert len(g) >= 3

@@ -668,3 +668,16 @@ def test_fp32_batch_functions_use_the_float32_program():
         S = S + 1.0 * ps
         C = C + 1.0 * pc
     assert np.array_equal(cnt, C) and np.array_equal(Bo, S / C[:, None])
+
+
+def test_fp32_segmentation_of_exact_copies():
+    """The segmentation loop with float32 Sub-DTW on a stream of exact copies
+    of the reference separated by idle stretches: every copy found at cost 0
+    (costs of identical samples are exact in any precision)."""
+    r = rng(350)
+    X = synth.dyadic(r, (12, 2)).astype(np.float32).astype(np.float64)
+    gap = np.repeat(X[-1:], 5, axis=0) + 3.0
+    Y = np.concatenate([X, gap, X, gap, X])
+    segs = oracle.segment(X, Y, fp32=True)
+    found = [(a, b) for a, b, v in segs if v == 0.0]
+    assert found == [(0, 11), (17, 28), (34, 45)]
