@@ -299,7 +299,7 @@ def valu_rates(reps: int = 5):
 
 # ------------------------------------------------------------ CPU baselines
 
-def cpu_baseline_c5(w, B, gamma: float, n_sample: int = 16, rows: int = 2048, seed: int = 5):
+def cpu_baseline_c5(w, B, gamma: float, n_sample: int = 16, rows: int = 3072, seed: int = 5):
     """The FP64 oracle (as it stands) on a bounded sample of the headline
     workload: n_sample seeded cycles (full length) against the first `rows`
     rows of the barycenter, one DBA iteration and one Soft-DTW forward +
