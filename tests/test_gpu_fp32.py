@@ -220,3 +220,39 @@ def test_fp32_segmentation_matches_the_float32_oracle_loop(wts):
     for Y, g in zip(streams, got):
         assert g == oracle.segment(Xd, Y.astype(np.float64), fp32=True)
         assert len(g) >= 3
+
+
+@pytest.mark.timeout(900)
+def test_fp32_dba_at_the_256_cycle_size_sampled(wts):
+    """The 256-cycle workload (40k..50k samples, 1 % gaps, L = max N) in the
+    launch configuration the bench times for float32 decisions (4 rows per
+    lane): one DBA iteration weighted onto two cycles (the shortest and the
+    longest), bit for bit the oracle's float32 program on those two; the
+    unweighted counts match the float32 path lengths of all cycles."""
+    import torch
+    w = synth.make(5)
+    cyc = [np.asarray(c, np.float32) for c in w.cycles]
+    lens = w.lengths
+    pick = sorted({int(np.argmin(lens)), int(np.argmax(lens))})
+    plan, Y = plan_of(wts, cyc, w.d, w.L, rho=4)
+    B0, kn = wts.init_barycenter(plan, Y, wts.INIT_NEAREST)
+    wv = np.zeros(w.n)
+    wv[pick] = [1.0, 0.5][:len(pick)]
+    say("case fp32 256-cycle DBA, workspace %.1f GiB" % (plan.workspace_bytes(wts.OP_DBA) / 2 ** 30))
+    B1, counts, dist = wts.dba_iterate(plan, B0, Y, torch.from_numpy(wv).cuda())
+    score, d2, plen = wts.anomaly_score(plan, B0, Y)
+    torch.cuda.synchronize()
+    assert plan.status() == wts.OK
+    B1, counts, dist = B1.cpu().numpy(), counts.cpu().numpy(), dist.cpu().numpy()
+    plen = plen.cpu().numpy()
+    np.testing.assert_array_equal(dist, d2.cpu().numpy())
+    assert int(counts.sum()) == int(plen.sum()) and (counts >= w.n).all()
+    plan.close()
+    torch.cuda.empty_cache()
+    ko, Bo = oracle.nearest_init(as64(cyc), w.L)
+    assert kn == ko
+    say("case fp32 256-cycle DBA: oracle on cycles", pick)
+    Bn, _, od, ol = oracle.dba_iterate(Bo, [as64(cyc)[q] for q in pick], wv[pick], fp32=True)
+    np.testing.assert_array_equal(B1, Bn)
+    np.testing.assert_array_equal(dist[pick], od)
+    np.testing.assert_array_equal(plen[pick], ol)
