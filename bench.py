@@ -627,7 +627,8 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
 
 def fp32_dba_compare(wts, plan, off, d, dt, L, Y, B, arena, cells, sec, t_dba):
     """The DBA iteration of the headline workload with float32 decisions
-    (plan option decision = fp32; 4 and 5 rows per lane tried) against the
+    (plan option decision = fp32; 4 and 5 rows per lane at three grids tried)
+    against the
     float64 one on the same barycenter: sweep and iteration times, the path
     sweep's roofline against the float32 VALU peak, and how the results
     differ (distances, path lengths, counts, the new barycenter).  Both plans
@@ -640,10 +641,12 @@ def fp32_dba_compare(wts, plan, off, d, dt, L, Y, B, arena, cells, sec, t_dba):
     out32 = tuple(torch.empty_like(t) for t in out64)
     wts.dba_iterate(plan, B, Y, bary_out=out64[0], counts=out64[1], dist=out64[2])
     sc64, d64, l64 = wts.anomaly_score(plan, B, Y)
+    from paper_2404_12134_amd import autotune
+    cus = torch.cuda.get_device_properties(B.device).multi_processor_count
     best = None
     tried = {}
-    for rho in (4, 5):
-        p32 = wts.Plan(off, d, dt, L, decision="fp32", rho=rho)
+    for rho, grid in [(r, g) for r in (4, 5) for g in autotune.grid_candidates("dba", cus)]:
+        p32 = wts.Plan(off, d, dt, L, decision="fp32", rho=rho, grid=grid)
         p32.set_workspace(wts.OP_DBA, arena)
         wts.dba_iterate(p32, B, Y, bary_out=out32[0], counts=out32[1], dist=out32[2])
         torch.cuda.synchronize()
@@ -655,10 +658,10 @@ def fp32_dba_compare(wts, plan, off, d, dt, L, Y, B, arena, cells, sec, t_dba):
         torch.cuda.synchronize()
         ms, nl = p32.sweep_ms(wts.OP_DBA)
         p32.check()
-        tried[rho] = (ms / nl / 1e3, e0.elapsed_time(e1) / 1e3)
-        if best is None or tried[rho][1] < tried[best][1]:
-            best = rho
-        if rho == 4:
+        tried[(rho, grid)] = (ms / nl / 1e3, e0.elapsed_time(e1) / 1e3)
+        if best is None or tried[(rho, grid)][1] < tried[best][1]:
+            best = (rho, grid)
+        if best == (rho, grid):
             sc32, d32, l32 = wts.anomaly_score(p32, B, Y)
         p32.close()
     torch.cuda.synchronize()
@@ -670,8 +673,8 @@ def fp32_dba_compare(wts, plan, off, d, dt, L, Y, B, arena, cells, sec, t_dba):
     l64h, l32h = l64.cpu().numpy(), l32.cpu().numpy()
     B64, B32 = out64[0].cpu().numpy(), out32[0].cpu().numpy()
     return {
-        "rows_per_lane": best,
-        "candidates_s": {str(k): [round(v[0], 4), round(v[1], 4)] for k, v in tried.items()},
+        "rows_per_lane": best[0], "grid": best[1],
+        "candidates_s": [[k[0], k[1], round(v[0], 4), round(v[1], 4)] for k, v in tried.items()],
         "dba_iteration_s": round(iter_s, 4), "dba_gcups": round(cells / iter_s / 1e9, 2),
         "path_sweep": {"bound": "alu", "achieved": round(ach, 3), "peak": round(peak, 3),
                        "unit": "TOP/s", "frac": round(ach / peak, 4),
