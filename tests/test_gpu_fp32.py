@@ -256,3 +256,58 @@ def test_fp32_dba_at_the_256_cycle_size_sampled(wts):
     np.testing.assert_array_equal(B1, Bn)
     np.testing.assert_array_equal(dist[pick], od)
     np.testing.assert_array_equal(plen[pick], ol)
+
+
+def test_fp32_graph_replay_noalloc_and_validation(wts):
+    """The float32-decision sweeps under the other call forms: a DBA
+    iteration and the scores captured in one HIP graph and replayed three
+    times between eager calls (bit for bit), the scratch-buffer score entry
+    point against the allocating one, and a validated plan that refuses a
+    NaN sample before any sweep."""
+    import torch
+    r = rng(80)
+    B = r.standard_normal((300, 3))
+    cyc = [r.standard_normal((N, 3)).astype(np.float32) for N in (257, 129, 400, 1)]
+    plan, Y = plan_of(wts, cyc, 3, 300)
+    Bt = torch.from_numpy(B).cuda()
+    Bo = torch.empty_like(Bt)
+    K = torch.empty(300, dtype=torch.int64, device="cuda")
+    dd = torch.empty(4, dtype=torch.float64, device="cuda")
+
+    def calls():
+        wts.dba_iterate(plan, Bt, Y, bary_out=Bo, counts=K, dist=dd)
+        return wts.anomaly_score(plan, Bt, Y)
+
+    say("case fp32 graph: eager")
+    ref = [t.clone() for t in (Bo, K, dd) + tuple(calls())]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        outs = calls()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        say("case fp32 graph: replay", rep)
+        calls()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((Bo, K, dd) + tuple(outs), ref):
+            assert torch.equal(a, b)
+    Bn, Kn, od, _ = oracle.dba_iterate(B, as64(cyc), fp32=True)
+    np.testing.assert_array_equal(Bo.cpu().numpy(), Bn)
+    say("case fp32 noalloc")
+    s1, d1, l1 = wts.anomaly_score(plan, Bt, Y)
+    s2, d2, l2 = wts.anomaly_score_noalloc(plan, Bt, Y, dist=torch.empty_like(d1),
+                                           path_len=torch.empty_like(l1))
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2) and torch.equal(d1, d2) and torch.equal(l1, l2)
+    say("case fp32 validate")
+    bad = [c.copy() for c in cyc]
+    bad[2][17, 1] = np.nan
+    vplan, Yb = plan_of(wts, bad, 3, 300, validate=True)
+    wts.anomaly_score(vplan, Bt, Yb)
+    torch.cuda.synchronize()
+    assert vplan.status() == wts.E_NONFINITE
+    assert vplan.status() == wts.OK          # the status word is cleared by the read
