@@ -14,6 +14,7 @@
 
 #include "../../include/wetsand_mi.h"
 #include "wts_kernels.h"
+#include "wts_order.h"
 
 using wts::PairDesc;
 
@@ -64,8 +65,6 @@ struct Job {
   int32_t M, N, out;
 };
 
-constexpr size_t kSweepBlock = 1024;   // pairs per block of the sweep pop order
-
 void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
   const int H = wts::kWave * rho;
   ps.rho = rho;
@@ -103,24 +102,16 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
     ps.pairs.push_back(d);
     ps.max_rows = std::max<int64_t>(ps.max_rows, jb.M);
   }
-  // Sweep pop order: blocks of kSweepBlock pairs (largest first), strip-major
-  // inside a block.  A strip is popped a block's worth of items after the
-  // strip it waits on, which by then has usually moved ahead, instead of
-  // right after it.  Every strip still follows its predecessor in the list,
-  // so a wait is always on an item some running workgroup already holds.
+  std::vector<int64_t> cols(ps.pairs.size());
+  std::vector<int> strips(ps.pairs.size());
+  for (size_t q = 0; q < ps.pairs.size(); ++q) {
+    cols[q] = (int64_t)ps.pairs[q].N + wts::kWave;
+    strips[q] = ps.pairs[q].S;
+  }
   ps.sweep_items.clear();
   ps.items_rev.clear();
-  for (size_t b0 = 0; b0 < ps.pairs.size(); b0 += kSweepBlock) {
-    const size_t b1 = std::min(ps.pairs.size(), b0 + kSweepBlock);
-    int smax = 0;
-    for (size_t q = b0; q < b1; ++q) smax = std::max(smax, ps.pairs[q].S);
-    for (int s = 0; s < smax; ++s)
-      for (size_t q = b0; q < b1; ++q)
-        if (s < ps.pairs[q].S) ps.sweep_items.push_back(make_int2((int)q, s));
-    for (int s = smax - 1; s >= 0; --s)
-      for (size_t q = b0; q < b1; ++q)
-        if (s < ps.pairs[q].S) ps.items_rev.push_back(make_int2((int)q, s));
-  }
+  wts::pop_order(cols, strips, false, [&](int q, int s) { ps.sweep_items.push_back(make_int2(q, s)); });
+  wts::pop_order(cols, strips, true, [&](int q, int s) { ps.items_rev.push_back(make_int2(q, s)); });
   ps.n_pairs = (int)ps.pairs.size();
   ps.n_items = (int)ps.items.size();
   ps.n_flags = flags;
