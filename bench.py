@@ -501,16 +501,19 @@ def c5_kernel_times(wts, it, groups):
     it.plan.enable_timing(4)
     for _, _, gp in groups:
         gp.enable_timing(4)
+        gp.bwd_tiles()   # forget the counts of earlier iterations
     it.run(mark=True)
     torch.cuda.synchronize()
     dba_ms, _ = it.plan.sweep_ms(wts.OP_DBA)
     fwd = [gp.sweep_ms(wts.OP_SOFT_FWD)[0] / 1e3 for _, _, gp in groups]
     bwd = [gp.sweep_ms(wts.OP_SOFT_BWD)[0] / 1e3 for _, _, gp in groups]
+    tiles = [gp.bwd_tiles() for _, _, gp in groups]
     it.plan.enable_timing(0)
     for _, _, gp in groups:
         gp.enable_timing(0)
     t_dba, t_soft = it.halves_s()
-    return dba_ms / 1e3, fwd, bwd, t_dba, t_soft
+    swept = sum(t[0] for t in tiles) / max(1, sum(t[1] for t in tiles))
+    return dba_ms / 1e3, fwd, bwd, t_dba, t_soft, swept
 
 
 def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.1,
@@ -551,12 +554,14 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
     value = counted / sec / 1e9
 
     # per-kernel launch times: one eager iteration with HIP events per sweep
-    dba_s, fwd, bwd, t_dba, t_soft = c5_kernel_times(wts, it, groups)
+    dba_s, fwd, bwd, t_dba, t_soft, swept = c5_kernel_times(wts, it, groups)
     plan.check()
+    # the backward sweeps only the tiles whose E entries are not all zero:
+    # its algorithmic work is that of the swept share of the cells
     kern = {   # name: (seconds per step, launches, cells, floor, KERNELS key, rho)
         "dba_path_sweep": (dba_s, 1, cells, c_dba(d), "c5_dba", plan.rho(wts.OP_DBA)),
         "soft_fwd": (sum(fwd), len(groups), cells, c_soft_fwd(d, tau), "c5_soft_fwd", 2),
-        "soft_bwd": (sum(bwd), len(groups), cells, c_soft_bwd(d, tau), "c5_soft_bwd", 2),
+        "soft_bwd": (sum(bwd), len(groups), cells * swept, c_soft_bwd(d, tau), "c5_soft_bwd", 2),
     }
     dom = max(kern, key=lambda k: kern[k][0])
     ksec, kl, kcells, kc, kkey, krho = kern[dom]
@@ -571,6 +576,8 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
                                   VALU_LANE_OPS_PEAK, 4)
     roof["soft_group_launch_ms"] = {"fwd": [round(x * 1e3, 2) for x in fwd],
                                     "bwd": [round(x * 1e3, 2) for x in bwd]}
+    progress("headline: the Soft-DTW backward with every tile swept (dense_e)")
+    skip_rec = dense_e_compare(wts, it, groups, off, d, dt, L, Y, gamma, swept)
 
     # the anomaly scores of all cycles (after the iterations)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -610,6 +617,7 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
         "autotune": it.tuned,
         "batched_vs_per_cycle": speed,
         "fp32_decisions": fp32_rec,
+        "soft_bwd_zero_tiles": skip_rec,
     }
     del graph, it, arena
     for _, _, gp in groups:
@@ -621,6 +629,42 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
         progress("headline: oracle on the CPU")
         rec["cpu_baseline"] = cpu_baseline_c5(w, Bhost, gamma)
     return rec
+
+
+def dense_e_compare(wts, it, groups, off, d, dt, L, Y, gamma, swept):
+    """The Soft-DTW backward of the first checkpoint group with the zero
+    tiles skipped (the headline's plans) and with every tile swept (a plan
+    with dense_e), on the same checkpoints: launch times and whether the
+    gradients and row masses agree bit for bit."""
+    import torch
+    gp, Yg, gv, a, b = it.soft.parts[0]
+    offs = off[a:b + 1] - off[a]
+    B = it.A
+    ck = it.soft.ckpt[:gp.workspace_bytes(wts.OP_SOFT_FWD)]
+    wts.softdtw_forward(gp, B, Yg, gamma, ckpt=ck)
+    grid = it.tuned["soft"]["grid"] if it.tuned else 0
+    pdense = wts.Plan(offs, d, dt, L, grid=grid, dense_e=True)
+    out = {}
+    for lab, pl in (("skipped", gp), ("dense", pdense)):
+        pl.enable_timing(4)
+        pl.bwd_tiles()
+        g_, m_ = wts.softdtw_backward(pl, B, Yg, gamma, ck, gv, with_mass=True)
+        torch.cuda.synchronize()
+        ms, nl = pl.sweep_ms(wts.OP_SOFT_BWD)
+        sw, tot = pl.bwd_tiles()
+        pl.enable_timing(0)
+        pl.check()
+        out[lab] = (g_.clone(), m_.clone(), ms / max(nl, 1), sw / max(tot, 1))
+    pdense.close()
+    same = bool(torch.equal(out["skipped"][0], out["dense"][0])
+                and torch.equal(out["skipped"][1], out["dense"][1]))
+    return {"tiles_swept_frac_step": round(swept, 5),
+            "group_cycles": int(b - a),
+            "launch_ms_skipped": round(out["skipped"][2], 2),
+            "launch_ms_dense": round(out["dense"][2], 2),
+            "tiles_swept_frac_group": round(out["skipped"][3], 5),
+            "speedup": round(out["dense"][2] / out["skipped"][2], 2),
+            "bitwise_equal_grad_and_mass": same}
 
 
 # ------------------------------------------------------------ extra sections
@@ -956,6 +1000,7 @@ def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
         torch.cuda.synchronize()
         B.copy_(B0)
         plan.enable_timing(2 * steps)
+        plan.bwd_tiles()
         t0 = time.perf_counter()
         for s in range(steps):
             sd.step(B)
@@ -964,11 +1009,16 @@ def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
         sec = (time.perf_counter() - t0) / steps
         tf, nf = plan.sweep_ms(wts.OP_SOFT_FWD)
         tb, nb = plan.sweep_ms(wts.OP_SOFT_BWD)
+        sw, tot = plan.bwd_tiles()
+        swept = sw / max(tot, 1)
         plan.enable_timing(0)
         plan.check()
         tr = traj.cpu().numpy()
+        # the backward's algorithmic work: the cells of the tiles it swept
         fwd = roofline("c5_soft_fwd", 2, cells * cf * nf, tf / 1e3, nf, cells * nf, cf)
-        bwd = roofline("c5_soft_bwd", 2, cells * cb * nb, tb / 1e3, nb, cells * nb, cb)
+        bwd = roofline("c5_soft_bwd", 2, cells * swept * cb * nb, tb / 1e3, nb,
+                       cells * swept * nb, cb)
+        bwd["tiles_swept_frac"] = round(swept, 5)
         for rf in (fwd, bwd):
             rf["traffic"] = None   # the committed counters are those of the headline workload
             rf.pop("issued_valu_per_cell", None)
@@ -982,7 +1032,8 @@ def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
             "objective_non_increasing": bool(np.all(np.diff(tr) <= 1e-12 * np.abs(tr[:-1]))),
             "fd_check_step0": fd,
             "forward": fwd, "backward": bwd,
-            "alu_frac_fwd_bwd": round(cells * (cf + cb) / pair_s / VALU_LANE_OPS_PEAK, 4),
+            "alu_frac_fwd_bwd": round(cells * (cf + swept * cb) / pair_s / VALU_LANE_OPS_PEAK,
+                                      4),
         }
         del sd
     # the gradient with respect to the cycles (gamma 0.1)
@@ -1008,6 +1059,7 @@ def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
     sdb.step(B)
     torch.cuda.synchronize()
     bplan.enable_timing(8)
+    bplan.bwd_tiles()
     t0 = time.perf_counter()
     for _ in range(3):
         sdb.step(B)
@@ -1015,12 +1067,14 @@ def c4_section(wts, dev, tau: float, steps: int = 50, lbfgs: bool = True):
     sec = (time.perf_counter() - t0) / 3
     tf, nf = bplan.sweep_ms(wts.OP_SOFT_FWD)
     tb, nb = bplan.sweep_ms(wts.OP_SOFT_BWD)
+    bsw, btot = bplan.bwd_tiles()
     bplan.enable_timing(0)
     bplan.check()
     rec["band_0.6"] = {"cells_in_band_per_pass": bcells,
                        "band_fraction": round(bcells / cells, 4), "s_per_step": round(sec, 4),
                        "gcups_fwd_bwd_in_band": round(2 * bcells / sec / 1e9, 2),
                        "forward_ms": round(tf / nf, 2), "backward_ms": round(tb / nb, 2),
+                       "backward_tiles_swept_frac_of_band": round(bsw / max(btot, 1), 5),
                        "autotune": {k: btuned[k] for k in ("rho", "grid", "table")}}
     del sdb
     bplan.close()

@@ -135,6 +135,14 @@ typedef struct {
                          gradients are those over the paths inside the band.  Must be
                          finite and >= 0; a band needs L and every cycle length below
                          2^26                                                            */
+  int32_t dense_e;    /* Soft-DTW backward (Eq. 6): 0 (default) skips every 16-column tile
+                         of a strip whose E entries are exactly zero in the float32 e
+                         arithmetic: e reaches a cell only through its successors'
+                         pushes, so a tile with no push entering it is zero throughout.
+                         Gradients and row masses are bit for bit those of a sweep over
+                         every tile; only the time changes (E is non-zero in a band
+                         around the soft alignment, a few hundred columns wide on long
+                         similar series).  1: sweep every tile                            */
 } wts_opts;
 
 /* Create a plan for a batch of n cycles of d channels (1 <= d <= 8) stored as
@@ -172,6 +180,15 @@ size_t wts_workspace_bytes(const wts_plan* plan, int op);
  * forgets them. */
 wts_status wts_plan_timing(wts_plan* plan, int32_t max_launches);
 wts_status wts_plan_sweep_ms(wts_plan* plan, int op, double* total_ms, int32_t* launches);
+
+/* Tiles of the Soft-DTW backward, for profiling: *swept receives the 16-column
+ * strip tiles the backward kernels of this plan (wts_softdtw_backward,
+ * wts_softdtw_grad_cycles) swept since the plan was created or last read, and
+ * *in_range the tiles their strips spanned (inside the band, if any); the
+ * difference is the tiles skipped as exactly zero (opts.dense_e = 0).  Waits
+ * for the device, then resets both counts.  WTS_E_ARG for null arguments,
+ * WTS_E_HIP if a HIP call fails.  Not for use under graph capture. */
+wts_status wts_plan_bwd_tiles(wts_plan* plan, int64_t* swept, int64_t* in_range);
 
 /* Rows per lane (rho) of the wavefront sweeps that operation `op` runs on this
  * plan, as chosen at plan creation (opts.rho, or the automatic choice); it

@@ -192,6 +192,7 @@ struct wts_plan {
   // device words: [0] sticky status bits (wts_plan_status reads and clears
   // them), [1] the current call's validation flag, [2] read-out slot
   int* d_status = nullptr;
+  unsigned long long* d_tiles = nullptr;   // Soft-DTW backward: tiles swept, tiles in range
   // optional sweep timing: pool of (start, stop) event pairs, one per sweep launch
   std::vector<hipEvent_t> ev;
   size_t ev_next = 0;
@@ -423,6 +424,7 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
     return fail(WTS_E_UNSUPPORTED, "opts.rho = %d: 2, 4 or 5 supported", o.rho);
   if (o.grid < 0) return fail(WTS_E_ARG, "opts.grid = %d", o.grid);
   if (o.validate != 0 && o.validate != 1) return fail(WTS_E_ARG, "opts.validate = %d: 0 or 1", o.validate);
+  if (o.dense_e != 0 && o.dense_e != 1) return fail(WTS_E_ARG, "opts.dense_e = %d: 0 or 1", o.dense_e);
   if (o.decision != WTS_DECISION_FP64 && o.decision != WTS_DECISION_FP32)
     return fail(WTS_E_ARG, "opts.decision = %d: 0 or 1", o.decision);
   if (o.decision == WTS_DECISION_FP32 && (dtype != WTS_F32 || o.cost != WTS_COST_SQEUCLID))
@@ -519,6 +521,10 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   hipError_t e;
   if ((e = hipMalloc(&p->d_status, 4 * sizeof(int))) != hipSuccess) return cleanup_fail(e, "hipMalloc");
   if ((e = hipMemset(p->d_status, 0, 4 * sizeof(int))) != hipSuccess) return cleanup_fail(e, "hipMemset");
+  if ((e = hipMalloc(&p->d_tiles, 2 * sizeof(unsigned long long))) != hipSuccess)
+    return cleanup_fail(e, "hipMalloc");
+  if ((e = hipMemset(p->d_tiles, 0, 2 * sizeof(unsigned long long))) != hipSuccess)
+    return cleanup_fail(e, "hipMemset");
   if ((e = hipMalloc(&p->d_off, sizeof(int64_t) * (n + 1))) != hipSuccess) return cleanup_fail(e, "hipMalloc");
   if ((e = hipMemcpy(p->d_off, p->off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup_fail(e, "hipMemcpy");
@@ -540,6 +546,18 @@ wts_status wts_plan_timing(wts_plan* p, int32_t max_launches) {
     p->ev.push_back(e);
   }
   p->ev_op.assign(max_launches, -1);
+  return WTS_OK;
+}
+
+wts_status wts_plan_bwd_tiles(wts_plan* p, int64_t* swept, int64_t* in_range) {
+  if (!p || !swept || !in_range) return fail(WTS_E_ARG, "null argument");
+  DeviceGuard g(p->device);
+  unsigned long long t[2] = {0, 0};
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(t, p->d_tiles, sizeof(t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(p->d_tiles, 0, sizeof(t)));
+  *swept = (int64_t)t[0];
+  *in_range = (int64_t)t[1];
   return WTS_OK;
 }
 
@@ -597,6 +615,7 @@ void wts_plan_destroy(wts_plan* p) {
   }
   if (p->d_off) (void)hipFree(p->d_off);
   if (p->d_status) (void)hipFree(p->d_status);
+  if (p->d_tiles) (void)hipFree(p->d_tiles);
   if (p->d_path_base) (void)hipFree(p->d_path_base);
   if (p->d_med_ab) (void)hipFree(p->d_med_ab);
   delete p;
@@ -826,6 +845,8 @@ wts_status wts_softdtw_backward(const wts_plan* p, const double* bary, const voi
   a.gsum = at<double>(ws, l.gsum);
   a.hsum = at<double>(ws, l.hsum);
   a.L = p->L;
+  a.zero_skip = p->opts.dense_e ? 0 : 1;
+  a.tiles = p->d_tiles;
   const int tk = timing_begin(p, WTS_OP_SOFT_BWD, st);
   HIP_TRY(wts::launch_soft(p->d, p->dtype, true, a, default_grid(p, ps), st));
   timing_end(p, tk, st);
@@ -877,6 +898,8 @@ wts_status wts_softdtw_grad_cycles(const wts_plan* p, const double* bary, const 
   HIP_TRY(wts::launch_zero(a.queue, 2, st));
   HIP_TRY(wts::launch_zero(a.progress, ps.n_flags, st));
   a.items = ps.d_items_rev;
+  a.zero_skip = p->opts.dense_e ? 0 : 1;
+  a.tiles = p->d_tiles;
   HIP_TRY(wts::launch_soft(p->d, WTS_F64, true, a, default_grid(p, ps), st));
   HIP_TRY(wts::launch_soft_rows_scale(a.gsum, p->d_off, p->n, p->off[p->n], p->d, grad_value,
                                       grad_cycles, st));

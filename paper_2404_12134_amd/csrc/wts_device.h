@@ -101,6 +101,8 @@ struct FwdArgs {
   int cost_kind;         // 0 squared, 1 Euclidean (sqrt)
   int relaxed_wait;      // 1: far more items than resident wavefronts; wait with long sleeps
   const int* skip;       // non-zero flag: the call's inputs failed validation, do nothing (or null)
+  int zero_skip;         // backward: 1 = tiles whose e is exactly zero are not swept
+  unsigned long long* tiles;   // backward: += tiles swept, tiles of the strips' ranges (or null)
 };
 
 struct SoftArgs {
@@ -125,6 +127,8 @@ struct SoftArgs {
   double band;           // Sakoe-Chiba bandwidth as a fraction of the longer length (0: none)
   int rows_packed;       // 0: gsum/hsum rows at out * L + i; 1: at x_off + i (X rows packed)
   const int* skip;       // non-zero flag: the call's inputs failed validation, do nothing (or null)
+  int zero_skip;         // backward: 1 = tiles whose e is exactly zero are not swept
+  unsigned long long* tiles;   // backward: += tiles swept, tiles of the strips' ranges (or null)
 };
 
 __device__ __forceinline__ double inf_d() { return __builtin_huge_val(); }

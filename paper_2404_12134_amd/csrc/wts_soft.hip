@@ -488,11 +488,9 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       rf_n = __builtin_bit_cast(
           double, __builtin_amdgcn_raw_buffer_load_b64(rf_in, lane < kTile && j < N ? j * 8 : kDrop, 0, 0));
     };
-    load_tile_inputs(g_hi);
-
-    // Y columns of the first tile swept
-    {
-      const int jlo = 16 * g_hi - (kWave - 1);
+    // the Y columns of tile gg (63 + 16 of them, through the ring)
+    auto fill_ring = [&](int gg) {
+      const int jlo = 16 * gg - (kWave - 1);
       for (int q = lane; q < 16 + kWave - 1; q += kWave) {
         const int j = jlo + q;
 #pragma unroll
@@ -500,9 +498,117 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
           ring_put(ys[c], j & (kRing - 1),
                    (j >= 0 && j < N) ? static_cast<double>(Y[(pd.y_off + j) * D + c]) * sk : 0.0);
       }
-    }
+    };
+    // any push still travelling inside the strip (wave-uniform)
+    auto pending = [&]() {
+      bool p = up0 != 0.0f || dg0 != 0.0f || recv_dg != 0.0f;
+#pragma unroll
+      for (int r = 0; r < RHO; ++r) p = p || pl[r] != 0.0f || pdg[r] != 0.0f;
+      return __builtin_amdgcn_ballot_w64(p) != 0;
+    };
+    // waits until the strip below has published every column >= jlo
+    auto wait_below = [&](int jlo) {
+      const int need = N - max(0, jlo);
+      if (need > seen_below && !gave_up) {
+        int got = 0, quit = 0;
+        if (lane == 0) {
+          int polls = 0;
+          got = ld_dev(prog_below);
+          while (got < need) {
+            poll_backoff(polls, a.relaxed_wait);
+            if (++polls > kSpinLimit) {
+              atomicOr(a.status, kStatusSpinTimeout);
+              quit = 1;
+              break;
+            }
+            got = ld_dev(prog_below);
+          }
+        }
+        seen_below = __builtin_amdgcn_readfirstlane(got);
+        gave_up = __builtin_amdgcn_readfirstlane(quit) != 0;
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    };
 
+    load_tile_inputs(g_hi);
+    fill_ring(g_hi);
+
+    // Zero tiles.  e reaches a cell only through the pushes of its
+    // successors, so a tile entered with no push travelling inside the strip
+    // and no non-zero push from the strip below has e = 0 in every cell and
+    // pushes nothing on.  With zero_skip such tiles are not swept; the strip
+    // checks the pushes from below for up to 16 tiles at a time (as far as
+    // the strip below has published) and moves on.  The result is the same
+    // bit for bit: a swept zero tile only adds +0 to the row sums and pushes
+    // 0 * w = 0.  Its top-row pushes are zero: they are stored unless the
+    // shared push row is known to hold zero there already, which is the case
+    // for every column this strip read as zero while skipping (the strip
+    // below left a zero there; the bottom strip, which reads nothing, stores
+    // them all).
+    bool idle = a.zero_skip && !pending();
+    int n_swept = 0;
     for (int g = g_hi; g >= g_lo; --g) {
+      if (idle) {
+        // columns at or below clean_hi read as zero from below in this run of skips
+        const int clean_hi = has_below ? 16 * g - (kWave - 1) + 15 : -1;
+        int hit = -1;   // first tile (from the right) fed a non-zero push from below
+        for (;;) {
+          int ge = max(g_lo, g - 15);   // this round: tiles g .. ge
+          if (has_below) {
+            wait_below(16 * g - (kWave - 1));   // tile g's inputs, at least
+            if (!gave_up && seen_below < N - max(0, 16 * ge - (kWave - 1))) {
+              int got = 0;   // one more read of the counter, without waiting
+              if (lane == 0) got = ld_dev(prog_below);
+              seen_below = max(seen_below, __builtin_amdgcn_readfirstlane(got));
+            }
+            // tile t takes columns >= 16 t - 63, all published once
+            // 16 t - 63 >= N - seen_below (any t once every column is)
+            if (!gave_up && seen_below < N) ge = max(ge, (N - seen_below + (kWave - 1) + 15) >> 4);
+            // the pushes tiles g .. ge take in: columns 16 ge - 63 .. 16 g - 48
+            const int jlo = 16 * ge - (kWave - 1);
+            const int cnt = 16 * (g - ge + 1);
+            float u[4], v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int q = lane + kWave * k;
+              const int c = jlo + q;
+              const int off = q < cnt && c >= 0 && c < N ? c * 4 : kDrop;
+              u[k] = ld_dev_f32(pu_in, off);
+              v[k] = ld_dev_f32(pd_in, off);
+            }
+#pragma unroll
+            for (int k = 3; k >= 0; --k) {
+              const unsigned long long m = __builtin_amdgcn_ballot_w64(u[k] != 0.0f || v[k] != 0.0f);
+              if (hit < 0 && m != 0) hit = ge + ((kWave * k + 63 - __builtin_clzll(m)) >> 4);
+            }
+          }
+          const int gz = hit >= 0 ? hit + 1 : ge;   // tiles g .. gz are zero
+          if (has_above && gz <= g) {
+            // their top-row pushes: columns 16 gz .. 16 g + 15, announced
+            // once every older store is complete
+            const int cnt = 16 * (g - gz + 1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int q = lane + kWave * k;
+              const int c = 16 * gz + q;
+              if (q < cnt && c < N && c > clean_hi) {
+                st_dev(pu_out, c * 4, 0.0f);
+                st_dev(pd_out, c * 4, 0.0f);
+              }
+            }
+            mem_drain();
+            if (lane == 0) st_dev(prog_self, N - min(N, 16 * gz));
+          }
+          g = gz - 1;
+          if (hit >= 0 || g < g_lo) break;
+        }
+        if (g < g_lo) break;
+        // sweep tile g: its replay inputs and Y columns were not kept up
+        idle = false;
+        load_tile_inputs(g);
+        fill_ring(g);
+      }
+      ++n_swept;
       const int tg = 16 * g;
       const int yb = (tg - lane) & (kRing - 1);   // ring slot of step 0's column
       // next tile's 16 new Y columns, stored after this tile
@@ -518,32 +624,11 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       // lane 0's upper input for the replay (bottom row of the strip above),
       // loaded during the previous tile
       if (lane < kTile) bin_fwd[lane] = has_above ? rf_n : INF;
-      // lane 63's inputs: pushes of the strip below's top row at columns tg-63 ..
-      if (has_below) {
-        const int jlo = max(0, tg - (kWave - 1));
-        const int need = N - jlo;            // columns >= jlo published
-        // the strip below usually runs far ahead: one read of its counter
-        // covers many tiles, and only a counter short of `need` is read again
-        if (need > seen_below && !gave_up) {
-          int got = 0, quit = 0;
-          if (lane == 0) {
-            int polls = 0;
-            got = ld_dev(prog_below);
-            while (got < need) {
-              poll_backoff(polls, a.relaxed_wait);
-              if (++polls > kSpinLimit) {
-                atomicOr(a.status, kStatusSpinTimeout);
-                quit = 1;
-                break;
-              }
-              got = ld_dev(prog_below);
-            }
-          }
-          seen_below = __builtin_amdgcn_readfirstlane(got);
-          gave_up = __builtin_amdgcn_readfirstlane(quit) != 0;
-        }
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      }
+      // lane 63's inputs: pushes of the strip below's top row at columns
+      // tg-63 ..  The strip below usually runs far ahead: one read of its
+      // counter covers many tiles, and only a counter short of what this
+      // tile needs is read again.
+      if (has_below) wait_below(tg - (kWave - 1));
       // the pushes are only needed by the backward half: loaded now (one
       // unconditional load each, zero outside the row or without a strip
       // below) and written to LDS after the replay
@@ -689,6 +774,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
         bout_dg[bsl + u] = dg0;
         recv_dg = recv_dg_next;
       }
+      idle = a.zero_skip && !pending();
       __syncthreads();
       if (has_above) {
         // publish the top row's pushes for columns tg .. tg+15 (two stores,
@@ -740,6 +826,10 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       }
       mem_drain();
       if (lane == 0) st_dev(prog_self, N);
+    }
+    if (a.tiles != nullptr && lane == 0) {
+      atomicAdd(a.tiles, (unsigned long long)n_swept);
+      atomicAdd(a.tiles + 1, (unsigned long long)(g_hi - g_lo + 1));
     }
     // per-row sums of this cycle: gradient 2 (b sum_j e - sum_j e y_j) and mass
 #pragma unroll

@@ -42,7 +42,7 @@ class WtsError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("cost", ctypes.c_int32), ("rho", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("decision", ctypes.c_int32),
-                ("band", ctypes.c_double)]
+                ("band", ctypes.c_double), ("dense_e", ctypes.c_int32)]
 
 
 def load():
@@ -69,6 +69,7 @@ def load():
         "wts_precond_step": [P, P, P, I64, I32, D, P],
         "wts_plan_timing": [P, I32],
         "wts_plan_sweep_ms": [P, ctypes.c_int, P, P],
+        "wts_plan_bwd_tiles": [P, P, P],
         "wts_plan_rho": [P, ctypes.c_int],
         "wts_subdtw": [P, P, P, P, P, P, P, SZ, P],
         "wts_softdtw_grad_cycles": [P, P, P, D, P, P, P, SZ, P],
@@ -96,7 +97,7 @@ def exported_symbols():
             "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step",
             "wts_plan_timing", "wts_plan_sweep_ms", "wts_plan_rho", "wts_subdtw",
             "wts_softdtw_grad_cycles", "wts_plan_status", "wts_barycenter_objective",
-            "wts_anomaly_score_noalloc"]
+            "wts_anomaly_score_noalloc", "wts_plan_bwd_tiles"]
 
 
 def _check(rc: int):
@@ -160,11 +161,13 @@ class Plan:
     """A plan binds the cycle lengths, the channel count, the storage dtype and
     the barycenter length L (L = 0: a plan for the medoid only).  band > 0
     restricts the Soft-DTW calls to a Sakoe-Chiba band of that fraction of
-    the longer length (Table I)."""
+    the longer length (Table I).  dense_e=True makes the Soft-DTW backward
+    sweep every tile, also those whose E entries are exactly zero (same
+    results, more time)."""
 
     def __init__(self, offsets, d: int, dtype: str, L: int, device: int = 0, cost: str = "sq",
                  rho: int = 0, grid: int = 0, band: float = 0.0, validate: bool = False,
-                 decision: str = "fp64"):
+                 decision: str = "fp64", dense_e: bool = False):
         lib = load()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         self.offsets = off
@@ -180,7 +183,7 @@ class Plan:
         self.decision = decision
         opts = _Opts(COST_EUCLID if cost == "euclid" else COST_SQ, int(rho), int(grid),
                      1 if validate else 0, DECISION_FP32 if decision == "fp32" else DECISION_FP64,
-                     float(band))
+                     float(band), 1 if dense_e else 0)
         h = ctypes.c_void_p()
         _check(lib.wts_plan_create(ctypes.byref(h), self.device, self.n, self.d,
                                    F32 if dtype == "f32" else F64,
@@ -228,6 +231,14 @@ class Plan:
         cnt = ctypes.c_int32(0)
         _check(load().wts_plan_sweep_ms(self._h, int(op), ctypes.byref(tot), ctypes.byref(cnt)))
         return tot.value, cnt.value
+
+    def bwd_tiles(self):
+        """(tiles swept, tiles in range) of the Soft-DTW backward kernels of this
+        plan since the last query (waits for the device; eager use only)."""
+        sw = ctypes.c_int64(0)
+        tot = ctypes.c_int64(0)
+        _check(load().wts_plan_bwd_tiles(self._h, ctypes.byref(sw), ctypes.byref(tot)))
+        return sw.value, tot.value
 
     def rho(self, op: int) -> int:
         """Rows per lane of the sweeps `op` runs on this plan (names the kernel instance)."""
