@@ -216,11 +216,15 @@ def ingest_traffic(root: str):
     # instructions: x 64 lanes / cells), from a pass over one iteration of
     # the headline ('c5' phase, --steps 1): the launches of one kernel cover
     # one DP pass together
+    # the backward sweeps only its non-zero tiles: its cells are the swept share
     cells = {}
+    swept = 1.0
     for f in glob.glob(os.path.join(root, "**", "*.out"), recursive=True):
         for line in open(f, errors="replace"):
             if line.startswith("{") and '"phase": "c5"' in line:
-                cells["c5"] = json.loads(line)["cells_per_pass"]
+                rec = json.loads(line)
+                cells["c5"] = rec["cells_per_pass"]
+                swept = rec.get("bwd_tiles_swept_frac", swept)
     per_cell = {}
     if "c5" in cells:
         tot = {}
@@ -233,11 +237,14 @@ def ingest_traffic(root: str):
             pre, post = pattern.split("{rho}")
             for kn, v in tot.items():
                 if kn.startswith(pre) and kn.endswith(post):
+                    c = cells["c5"] * (swept if key == "c5_soft_bwd" else 1.0)
                     per_cell[key] = {"kernel": kn.replace("void ", ""),
-                                     "per_cell": round(v * 64 / cells["c5"], 2)}
+                                     "per_cell": round(v * 64 / c, 2)}
     if per_cell:
         rec = {"source_hash": kernel_source_hash(), "per_cell": per_cell,
-               "note": "SQ_INSTS_VALU x 64 / cells of one pass, headline workload"}
+               "bwd_tiles_swept_frac": swept,
+               "note": "SQ_INSTS_VALU x 64 / cells of one pass, headline workload (the "
+                       "backward: the cells of the tiles it swept)"}
         with open(os.path.join(ROOT, "profiles", "valu_issued.json"), "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
@@ -1231,15 +1238,20 @@ def only_phase(args, wts, dev):
     if args.only == "c5":
         w, Y, off, dt, plan, groups, arena, it = c5_setup(wts, dev, tune=True,
                                                           tune_cache=args.tune_cache)
+        for _, _, gp in groups:
+            gp.bwd_tiles()
         for _ in range(args.steps):
             it.run()
         torch.cuda.synchronize()
         plan.check()
+        tiles = [gp.bwd_tiles() for _, _, gp in groups]
+        swept = sum(t[0] for t in tiles) / max(1, sum(t[1] for t in tiles))
         print(json.dumps({"phase": "c5", "source_hash": kernel_source_hash(),
                           "kernels": {"c5_dba": KERNELS["c5_dba"].format(rho=plan.rho(wts.OP_DBA)),
                                       "c5_soft_fwd": KERNELS["c5_soft_fwd"].format(rho=2),
                                       "c5_soft_bwd": KERNELS["c5_soft_bwd"].format(rho=2)},
                           "cells_per_pass": w.L * int(w.lengths.sum()),
+                          "bwd_tiles_swept_frac": swept,
                           "soft_groups": [[a, b] for a, b, _ in groups],
                           "last_dispatches": {"c5_dba": args.steps,
                                               "c5_soft_fwd": args.steps * len(groups),
@@ -1357,6 +1369,7 @@ def main():
         "cpu_baseline": head.get("cpu_baseline"),
         "batched_vs_per_cycle": head["batched_vs_per_cycle"],
         "fp32_decisions": head.get("fp32_decisions"),
+        "soft_bwd_zero_tiles": head.get("soft_bwd_zero_tiles"),
         "valu": valu,
         "extras": extras,
     }
