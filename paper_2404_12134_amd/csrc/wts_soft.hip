@@ -42,17 +42,6 @@ namespace wts {
 
 namespace {
 
-template <int D>
-__device__ __forceinline__ double sq_cost(const double (&x)[D], const double (&y)[D]) {
-  double e = x[0] - y[0];
-  double s = e * e;
-#pragma unroll
-  for (int c = 1; c < D; ++c) {
-    e = x[c] - y[c];
-    s = __builtin_fma(e, e, s);
-  }
-  return s;
-}
 
 __device__ __forceinline__ double shl1_f64(double v, double old) {
   // DPP wave_shl:1 -- lane k receives v from lane k+1; lane 63 receives `old`.
@@ -77,6 +66,36 @@ __device__ __forceinline__ void ring_put(double* row, int slot, double v) {
   if (slot < 16) row[slot + kRing] = v;
 }
 constexpr int kTile = 16;    // sweep steps per checkpoint / replay tile
+
+// Def. 3's squared cost in the scaled units of these kernels, k |x - y|^2,
+// in d + 1 operations per cell: the rows carry x' = sk (x - mu) and
+// |x'|^2, the columns y' = sk (y - mu) as -2 y' and |y'|^2, and
+// k |x - y|^2 = |x'|^2 + |y'|^2 + x' . (-2 y').  mu, the first row of the
+// pair's row series, keeps the three terms of the order of the series'
+// spread, so cancellation costs no more than a few roundings of that size.
+template <int D>
+__device__ __forceinline__ double sq_cost(const double (&x)[D], double xx, const double (&ym2)[D],
+                                          double yy) {
+  double s = xx + yy;
+#pragma unroll
+  for (int c = 0; c < D; ++c) s = __builtin_fma(x[c], ym2[c], s);
+  return s;
+}
+template <int D>
+__device__ __forceinline__ double sq_norm(const double (&v)[D]) {
+  double q = v[0] * v[0];
+#pragma unroll
+  for (int c = 1; c < D; ++c) q = __builtin_fma(v[c], v[c], q);
+  return q;
+}
+// One column into the Y ring: -2 y' per channel and |y'|^2.
+template <int D>
+__device__ __forceinline__ void ring_col(double (*ys)[kRing + 16], double* yq, int slot,
+                                         const double (&yc)[D]) {
+#pragma unroll
+  for (int c = 0; c < D; ++c) ring_put(ys[c], slot, -2.0 * yc[c]);
+  ring_put(yq, slot, sq_norm<D>(yc));
+}
 
 // Soft-min of the three predecessors in scaled units.  Returns the soft-min
 // value and the three (unnormalised) base-2 exponentials.
@@ -154,7 +173,8 @@ template <typename TY, int D, int RHO, bool BAND>
 __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
   constexpr int H = kWave * RHO;
   constexpr int kChunk = 64;
-  __shared__ double ys[D][kRing + 16];
+  __shared__ double ys[D][kRing + 16];   // -2 y' of the columns (see sq_cost)
+  __shared__ double yq[kRing + 16];      // |y'|^2
   __shared__ double binr[kChunk];       // the strip above's bottom row (+inf for the top strip)
   __shared__ double bor[kRing];
   __shared__ int s_item;
@@ -162,7 +182,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const double INF = inf_d();
   const double k = a.kscale;
-  const double sk = __builtin_sqrt(k);   // x and y enter as sqrt(k) x, sqrt(k) y
+  const double sk = __builtin_sqrt(k);   // x and y enter as sqrt(k) (x - mu), sqrt(k) (y - mu)
   if (skipped(a.skip)) return;   // every workgroup: no strip waits for another
 
   for (;;) {
@@ -175,6 +195,9 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     const PairDesc pd = uniform(a.pairs[uni(it.x)]);
     const int s = uni(it.y);
     const int M = pd.M, N = pd.N;
+    double mu[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) mu[c] = a.x[pd.x_off * D + c];
     const int i0 = s * H;
     const int ib = i0 + lane * RHO;
     const double band_b = BAND ? band_halfwidth(M, N, a.band) : 0.0;
@@ -189,12 +212,14 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     int* prog_in = a.progress + pd.flag_base + s - 1;
     int* prog_out = a.progress + pd.flag_base + s;
 
-    double xr[RHO][D];
+    double xr[RHO][D], xx[RHO];
 #pragma unroll
-    for (int r = 0; r < RHO; ++r)
+    for (int r = 0; r < RHO; ++r) {
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        xr[r][c] = (ib + r < M) ? a.x[(pd.x_off + ib + r) * D + c] * sk : 0.0;
+        xr[r][c] = (ib + r < M) ? (a.x[(pd.x_off + ib + r) * D + c] - mu[c]) * sk : 0.0;
+      xx[r] = sq_norm<D>(xr[r]);
+    }
     double left[RHO];
 #pragma unroll
     for (int r = 0; r < RHO; ++r) left[r] = INF;
@@ -206,13 +231,12 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     double pr_next = INF;
     const __amdgpu_buffer_rsrc_t ro = rsrc(row_out, has_next ? N * 8 : 0);
 
-    double yv[D];
     {
+      double yc[D];
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        yv[c] = lane < N ? static_cast<double>(Y[(pd.y_off + lane) * D + c]) * sk : 0.0;
-#pragma unroll
-      for (int c = 0; c < D; ++c) ring_put(ys[c], lane, yv[c]);
+        yc[c] = lane < N ? (static_cast<double>(Y[(pd.y_off + lane) * D + c]) - mu[c]) * sk : 0.0;
+      ring_col<D>(ys, yq, lane, yc);
     }
     __syncthreads();
 
@@ -289,6 +313,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
             double y[D];
 #pragma unroll
             for (int c = 0; c < D; ++c) y[c] = ys[c][yb + u];
+            const double yy = yq[yb + u];
             double dg = dg0, up = upin;
             // band coordinate of row ib at column j (exact in float64)
             const double bd0 = (double)ib * (double)(N - 1) - (double)j * (double)(M - 1);
@@ -299,10 +324,10 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
               if constexpr (BAND) {
                 const bool inb = __builtin_fabs(bd0 + (double)r * (double)(N - 1)) <= band_b;
                 const SoftMin sm = softmin3_band(dg, up, lf, inb);
-                rv = inb ? sq_cost<D>(xr[r], y) + sm.v : INF;
+                rv = inb ? sq_cost<D>(xr[r], xx[r], y, yy) + sm.v : INF;
               } else {
                 const SoftMin sm = softmin3(dg, up, lf);
-                rv = sq_cost<D>(xr[r], y) + sm.v;
+                rv = sq_cost<D>(xr[r], xx[r], y, yy) + sm.v;
               }
               dg = lf;
               up = rv;
@@ -355,9 +380,10 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
       }
       if (more) {
         const int j = t0 + kChunk + lane;
+        double yc[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c)
-          ring_put(ys[c], j & (kRing - 1), j < N ? static_cast<double>(yraw[c]) * sk : 0.0);
+        for (int c = 0; c < D; ++c) yc[c] = j < N ? (static_cast<double>(yraw[c]) - mu[c]) * sk : 0.0;
+        ring_col<D>(ys, yq, j & (kRing - 1), yc);
       }
       __syncthreads();
     }
@@ -384,9 +410,10 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
 // two waves without spills; the band test needs more registers, so the
 // banded instance is held to two.
 template <typename TY, int D, int RHO, bool BAND>
-__global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs a) {
+__global__ __launch_bounds__(kWave, 2) void soft_bwd_kernel(SoftArgs a) {
   constexpr int H = kWave * RHO;
-  __shared__ double ys[D][kRing + 16];
+  __shared__ double ys[D][kRing + 16];     // -2 y' of the columns (see sq_cost)
+  __shared__ double yq[kRing + 16];        // |y'|^2
   __shared__ double bin_fwd[kTile];        // lane 0's upper input for the replay
   __shared__ float bin_up[kTile];          // lane 63's pushes from the strip below
   __shared__ float bin_dg[kTile];
@@ -400,7 +427,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
   const TY* __restrict__ Y = static_cast<const TY*>(a.y);
   const double INF = inf_d();
   const double k = a.kscale;
-  const double sk = __builtin_sqrt(k);   // x and y enter as sqrt(k) x, sqrt(k) y
+  const double sk = __builtin_sqrt(k);   // x and y enter as sqrt(k) (x - mu), sqrt(k) (y - mu)
   if (skipped(a.skip)) return;   // every workgroup: no strip waits for another
 
   for (;;) {
@@ -411,6 +438,9 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
     if (item >= a.n_items) break;
     const int2 it = a.items[item];
     const PairDesc pd = uniform(a.pairs[uni(it.x)]);
+    double mu[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) mu[c] = a.x[pd.x_off * D + c];
     // first gradient row of this pair (per-cycle blocks of L rows, or the packed X rows)
     const int64_t grow = uni(a.rows_packed ? pd.x_off : (int64_t)pd.out * a.L);
     const int s = uni(it.y);
@@ -451,14 +481,17 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
     const int k_last = (M - 1 - i0) / RHO;
     const int r_last = (M - 1 - i0) - k_last * RHO;
 
-    double xr[RHO][D];
+    double xr[RHO][D], xx[RHO];
 #pragma unroll
-    for (int r = 0; r < RHO; ++r)
+    for (int r = 0; r < RHO; ++r) {
 #pragma unroll
       for (int c = 0; c < D; ++c)
-        xr[r][c] = (ib + r < M) ? a.x[(pd.x_off + ib + r) * D + c] * sk : 0.0;
+        xr[r][c] = (ib + r < M) ? (a.x[(pd.x_off + ib + r) * D + c] - mu[c]) * sk : 0.0;
+      xx[r] = sq_norm<D>(xr[r]);
+    }
 
-    double acc_e[RHO], acc_ey[RHO][D];        // float64 row accumulators
+    // float64 row accumulators: sum_j e and sum_j e (-2 y'_j)
+    double acc_e[RHO], acc_ey[RHO][D];
     float pl[RHO], pdg[RHO];                  // pending left / diagonal pushes into each row
 #pragma unroll
     for (int r = 0; r < RHO; ++r) {
@@ -493,10 +526,12 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       const int jlo = 16 * gg - (kWave - 1);
       for (int q = lane; q < 16 + kWave - 1; q += kWave) {
         const int j = jlo + q;
+        double yc[D];
 #pragma unroll
         for (int c = 0; c < D; ++c)
-          ring_put(ys[c], j & (kRing - 1),
-                   (j >= 0 && j < N) ? static_cast<double>(Y[(pd.y_off + j) * D + c]) * sk : 0.0);
+          yc[c] = (j >= 0 && j < N) ? (static_cast<double>(Y[(pd.y_off + j) * D + c]) - mu[c]) * sk
+                                    : 0.0;
+        ring_col<D>(ys, yq, j & (kRing - 1), yc);
       }
     };
     // any push still travelling inside the strip (wave-uniform)
@@ -673,6 +708,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
           double y[D];
 #pragma unroll
           for (int c = 0; c < D; ++c) y[c] = ys[c][yb + u];
+          const double yy = yq[yb + u];
           double dg = dgi, up = upin;
           const double bd0 = (double)ib * (double)(N - 1) - (double)j * (double)(M - 1);
 #pragma unroll
@@ -683,7 +719,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
               // receives and passes on exactly nothing
               const bool inb = __builtin_fabs(bd0 + (double)r * (double)(N - 1)) <= band_b;
               const SoftMin sm = softmin3_band(dg, up, lf, inb);
-              const double rv = inb ? sq_cost<D>(xr[r], y) + sm.v : INF;
+              const double rv = inb ? sq_cost<D>(xr[r], xx[r], y, yy) + sm.v : INF;
               const float rs = __builtin_amdgcn_rcpf(inb ? sm.s : 1.0f);
               wu[u][r] = inb ? sm.eu * rs : 0.0f;
               wl[u][r] = inb ? sm.el * rs : 0.0f;
@@ -692,7 +728,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
               left[r] = rv;
             } else {
               const SoftMin sm = softmin3(dg, up, lf);
-              const double rv = sq_cost<D>(xr[r], y) + sm.v;
+              const double rv = sq_cost<D>(xr[r], xx[r], y, yy) + sm.v;
               const float rs = __builtin_amdgcn_rcpf(sm.s);   // s >= 1: the minimum's term is 1
               wu[u][r] = sm.eu * rs;
               wl[u][r] = sm.el * rs;
@@ -790,9 +826,10 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       }
       if (g > 0 && lane < 16) {
         const bool in = jn >= 0 && jn < N;
+        double yc[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c)
-          ring_put(ys[c], jn & (kRing - 1), in ? static_cast<double>(yraw[c]) * sk : 0.0);
+        for (int c = 0; c < D; ++c) yc[c] = in ? (static_cast<double>(yraw[c]) - mu[c]) * sk : 0.0;
+        ring_col<D>(ys, yq, jn & (kRing - 1), yc);
       }
       __syncthreads();
     }
@@ -831,7 +868,8 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
       atomicAdd(a.tiles, (unsigned long long)n_swept);
       atomicAdd(a.tiles + 1, (unsigned long long)(g_hi - g_lo + 1));
     }
-    // per-row sums of this cycle: gradient 2 (b sum_j e - sum_j e y_j) and mass
+    // per-row sums of this cycle: gradient 2 (b sum_j e - sum_j e y_j), which
+    // is (2 x' sum_j e + sum_j e (-2 y'_j)) / sk, and mass
 #pragma unroll
     for (int r = 0; r < RHO; ++r) {
       const int i = ib + r;
@@ -839,7 +877,7 @@ __global__ __launch_bounds__(kWave, BAND ? 2 : 3) void soft_bwd_kernel(SoftArgs 
         const int64_t o = grow + i;
 #pragma unroll
         for (int c = 0; c < D; ++c)
-          a.gsum[o * D + c] = 2.0 * (xr[r][c] * acc_e[r] - acc_ey[r][c]) / sk;
+          a.gsum[o * D + c] = (2.0 * xr[r][c] * acc_e[r] + acc_ey[r][c]) / sk;
         a.hsum[o] = acc_e[r];
       }
     }
