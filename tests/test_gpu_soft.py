@@ -236,3 +236,25 @@ def test_soft_wide_band_is_bitwise_unbanded(wts):
         outs.append((v.cpu().numpy(), g.cpu().numpy(), h.cpu().numpy()))
     for a, b in zip(*outs):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("offset", [1e3, 1e6])
+def test_soft_large_offset_matches_oracle(wts, offset):
+    """Series far from the origin: the kernels form the cost as an expanded
+    square around the pair's first row, so a common offset of 1e6 (where
+    |x|^2 would be 1e12 times the costs) still meets the 1e-4 bar."""
+    import torch
+    r = rng(int(offset) % 1000 + 3)
+    B = offset + r.standard_normal((200, 3))
+    cyc = [offset + r.standard_normal((N, 3)) for N in (180, 233)]
+    wv = np.array([1.0, 0.5])
+    say("soft offset %g" % offset)
+    plan, Bt, Y = setup(wts, B, cyc, dtype="f64")
+    val, ck = wts.softdtw_forward(plan, Bt, Y, 0.5)
+    g, h = wts.softdtw_backward(plan, Bt, Y, 0.5, ck, torch.from_numpy(wv).cuda(), with_mass=True)
+    torch.cuda.synchronize()
+    assert plan.status() == wts.OK
+    ov, og, oh = oracle.softdtw_batch(B, cyc, 0.5, wv)
+    check_vec(val.cpu().numpy(), ov)
+    check_vec(g.cpu().numpy(), og)
+    check_vec(h.cpu().numpy(), oh)
