@@ -104,11 +104,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-KERNELS = {   # sweep -> rocprofv3 kernel name ({rho}: rows per lane of the plan)
+KERNELS = {   # sweep -> rocprofv3 kernel name ({rho}: rows per lane of the plan;
+              # {mode}: the path sweep's mode, 2 without entry tags, 4 with them)
     "medoid": "void wts::(anonymous namespace)::dtw_fwd_kernel<float, float, double, 3, {rho}, 0, false>",
-    "dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, double, 3, {rho}, 2, false>",
+    "dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, double, 3, {rho}, {mode}, false>",
     "score": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, double, 3, {rho}, 1, false>",
-    "c5_dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, double, 6, {rho}, 2, false>",
+    "c5_dba": "void wts::(anonymous namespace)::dtw_fwd_kernel<double, float, double, 6, {rho}, {mode}, false>",
     "c5_soft_fwd": "void wts::(anonymous namespace)::soft_fwd_kernel<float, 6, {rho}, false>",
     "c5_soft_bwd": "void wts::(anonymous namespace)::soft_bwd_kernel<float, 6, {rho}, false>",
 }
@@ -194,10 +195,10 @@ def ingest_traffic(root: str):
                             "fetch_scale": f_scale, "write_scale": w_scale}}
     for key, pattern in KERNELS.items():
         phase = "c5" if key.startswith("c5") else key
-        pre, post = pattern.split("{rho}")
+        pre = _pattern_re(pattern)
         inst = {}
         for (ph, kn, cname), v in avg.items():
-            if ph != phase or not (kn.startswith(pre) and kn.endswith(post)):
+            if ph != phase or not pre.match(kn):
                 continue
             if cname not in ("FETCH_SIZE", "WRITE_SIZE"):
                 continue
@@ -234,9 +235,9 @@ def ingest_traffic(root: str):
         for key, pattern in KERNELS.items():
             if not key.startswith("c5"):
                 continue
-            pre, post = pattern.split("{rho}")
+            pre = _pattern_re(pattern)
             for kn, v in tot.items():
-                if kn.startswith(pre) and kn.endswith(post):
+                if pre.match(kn):
                     c = cells["c5"] * (swept if key == "c5_soft_bwd" else 1.0)
                     per_cell[key] = {"kernel": kn.replace("void ", ""),
                                      "per_cell": round(v * 64 / c, 2)}
@@ -380,8 +381,20 @@ def band_cells(L: int, lengths, w: float) -> int:
     return tot
 
 
-def kname(key: str, rho: int) -> str:
-    return KERNELS[key].format(rho=rho).replace("void ", "")
+def kname(key: str, rho: int, mode: int = 2) -> str:
+    return KERNELS[key].format(rho=rho, mode=mode).replace("void ", "")
+
+
+def path_mode(plan) -> int:
+    """The sweep mode of a barycenter plan's path sweep: 2 (codes only) when
+    it recovers paths pair by pair, 4 (with entry tags) strip by strip."""
+    return 2 if plan.walk() == "pairs" else 4
+
+
+def _pattern_re(pattern: str):
+    import re
+    return re.compile(re.escape(pattern).replace(r"\{rho\}", r"\d+").replace(r"\{mode\}", r"\d+")
+                      + "$")
 
 
 def issued_per_cell(key: str, name: str):
@@ -565,19 +578,22 @@ def c5_headline(wts, dev, steps: int, warmup: int, tau: float, gamma: float = 0.
     plan.check()
     # the backward sweeps only the tiles whose E entries are not all zero:
     # its algorithmic work is that of the swept share of the cells
-    kern = {   # name: (seconds per step, launches, cells, floor, KERNELS key, rho)
-        "dba_path_sweep": (dba_s, 1, cells, c_dba(d), "c5_dba", plan.rho(wts.OP_DBA)),
-        "soft_fwd": (sum(fwd), len(groups), cells, c_soft_fwd(d, tau), "c5_soft_fwd", 2),
-        "soft_bwd": (sum(bwd), len(groups), cells * swept, c_soft_bwd(d, tau), "c5_soft_bwd", 2),
+    kern = {   # name: (seconds per step, launches, cells, floor, KERNELS key, rho, mode)
+        "dba_path_sweep": (dba_s, 1, cells, c_dba(d), "c5_dba", plan.rho(wts.OP_DBA),
+                           path_mode(plan)),
+        "soft_fwd": (sum(fwd), len(groups), cells, c_soft_fwd(d, tau), "c5_soft_fwd", 2, 0),
+        "soft_bwd": (sum(bwd), len(groups), cells * swept, c_soft_bwd(d, tau), "c5_soft_bwd", 2,
+                     0),
     }
     dom = max(kern, key=lambda k: kern[k][0])
-    ksec, kl, kcells, kc, kkey, krho = kern[dom]
-    roof = roofline(kkey, krho, kcells * kc, ksec, kl, kcells, kc)
+    ksec, kl, kcells, kc, kkey, krho, kmode = kern[dom]
+    roof = roofline(kkey, krho, kcells * kc, ksec, kl, kcells, kc, name=kname(kkey, krho, kmode))
     roof["per_kernel_ms_per_step"] = {k: round(v[0] * 1e3, 2) for k, v in kern.items()}
     roof["per_kernel_alu_frac"] = {k: round(v[2] * v[3] / v[0] / VALU_LANE_OPS_PEAK, 4)
                                    for k, v in kern.items()}
-    roof["per_kernel_issued_valu_per_cell"] = {k: issued_per_cell(v[4], kname(v[4], v[5]))
+    roof["per_kernel_issued_valu_per_cell"] = {k: issued_per_cell(v[4], kname(v[4], v[5], v[6]))
                                                for k, v in kern.items()}
+    roof["dba_path_recovery"] = plan.walk()
     roof["ops_per_cell_floors"] = {k: v[3] for k, v in kern.items()}
     roof["step_alu_frac"] = round(sum(v[2] * v[3] for v in kern.values()) / sec /
                                   VALU_LANE_OPS_PEAK, 4)
@@ -869,7 +885,8 @@ def c2_section(wts, dev, steps: int = 3, speedup: bool = True):
     per = {}
     for key, (pl, op, cells, cm) in sweeps.items():
         tot, cnt = pl.sweep_ms(op)
-        per[key] = roofline(key, pl.rho(op), cells * cm * cnt, tot / 1e3, cnt, cells * cnt, cm)
+        per[key] = roofline(key, pl.rho(op), cells * cm * cnt, tot / 1e3, cnt, cells * cnt, cm,
+                            name=kname(key, pl.rho(op), path_mode(pl) if key == "dba" else 2))
         per[key]["ms_per_step"] = round(tot / steps, 3)
     mplan.enable_timing(0)
     plan.enable_timing(0)
@@ -937,7 +954,9 @@ def c3_section(wts, dev, iters: int = 10, speedup: bool = True):
     speed = dba_per_cycle_speedup(wts, plan, off, w.d, dt, w.L, Y, B0) if speedup else None
     cm = c_dba(w.d)
     rho = plan.rho(wts.OP_DBA)
-    rf = roofline("c5_dba", rho, cells * cm * cnt, tot / 1e3, cnt, cells * cnt, cm)
+    rf = roofline("c5_dba", rho, cells * cm * cnt, tot / 1e3, cnt, cells * cnt, cm,
+                  name=kname("c5_dba", rho, path_mode(plan)))
+    rf["path_recovery"] = plan.walk()
     rf["traffic"] = None          # the committed counters are those of the headline workload
     rf.pop("issued_valu_per_cell", None)
     return {"workload": w.name + ": %d DBA iterations replayed from a hipGraph, nearest-length "
@@ -1247,7 +1266,8 @@ def only_phase(args, wts, dev):
         tiles = [gp.bwd_tiles() for _, _, gp in groups]
         swept = sum(t[0] for t in tiles) / max(1, sum(t[1] for t in tiles))
         print(json.dumps({"phase": "c5", "source_hash": kernel_source_hash(),
-                          "kernels": {"c5_dba": KERNELS["c5_dba"].format(rho=plan.rho(wts.OP_DBA)),
+                          "kernels": {"c5_dba": KERNELS["c5_dba"].format(rho=plan.rho(wts.OP_DBA),
+                                                                         mode=path_mode(plan)),
                                       "c5_soft_fwd": KERNELS["c5_soft_fwd"].format(rho=2),
                                       "c5_soft_bwd": KERNELS["c5_soft_bwd"].format(rho=2)},
                           "cells_per_pass": w.L * int(w.lengths.sum()),
@@ -1291,7 +1311,8 @@ def only_phase(args, wts, dev):
     used = {"medoid": mplan.rho(wts.OP_MEDOID), "dba": plan.rho(wts.OP_DBA),
             "score": plan.rho(wts.OP_SCORE)}[args.only]
     print(json.dumps({"phase": args.only, "L": L, "source_hash": kernel_source_hash(),
-                      "kernels": {args.only: KERNELS[args.only].format(rho=used)}}))
+                      "kernels": {args.only: KERNELS[args.only].format(rho=used,
+                                                                       mode=path_mode(plan))}}))
 
 
 def main():

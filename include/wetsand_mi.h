@@ -104,6 +104,7 @@ enum {
 enum { WTS_INIT_EUCLID_MEAN = 0, WTS_INIT_NEAREST = 1, WTS_INIT_COPY = 2 };
 
 enum { WTS_DECISION_FP64 = 0, WTS_DECISION_FP32 = 1 };
+enum { WTS_WALK_AUTO = 0, WTS_WALK_STRIPS = 1, WTS_WALK_PAIRS = 2 };
 
 typedef struct {
   int32_t cost;       /* WTS_COST_* for wts_dtw_align / wts_anomaly_score; DBA, Soft-DTW and
@@ -143,6 +144,14 @@ typedef struct {
                          every tile; only the time changes (E is non-zero in a band
                          around the soft alignment, a few hundred columns wide on long
                          similar series).  1: sweep every tile                            */
+  int32_t walk;       /* path recovery of wts_dba_iterate / wts_dtw_align with paths:
+                         WTS_WALK_STRIPS (1): the path sweep tags every cell with the cell
+                         through which its path enters the strip, and all strips are then
+                         walked at once; WTS_WALK_PAIRS (2): the sweep keeps only the argmin
+                         codes (about a tenth faster) and each pair walks its strips in turn;
+                         WTS_WALK_AUTO (0, default): pairs when the batch's cells outweigh
+                         its longest pair's walk (large batches), else strips.  Paths,
+                         counts and sums are the same bits either way                      */
 } wts_opts;
 
 /* Create a plan for a batch of n cycles of d channels (1 <= d <= 8) stored as
@@ -180,6 +189,11 @@ size_t wts_workspace_bytes(const wts_plan* plan, int op);
  * forgets them. */
 wts_status wts_plan_timing(wts_plan* plan, int32_t max_launches);
 wts_status wts_plan_sweep_ms(wts_plan* plan, int op, double* total_ms, int32_t* launches);
+
+/* The path recovery this plan's barycenter operations use (opts.walk, or the
+ * automatic choice): WTS_WALK_STRIPS or WTS_WALK_PAIRS; WTS_E_ARG for a null
+ * plan or a medoid plan (L = 0). */
+int32_t wts_plan_walk(const wts_plan* plan);
 
 /* Tiles of the Soft-DTW backward, for profiling: *swept receives the 16-column
  * strip tiles the backward kernels of this plan (wts_softdtw_backward,

@@ -58,6 +58,7 @@ struct PairSet {
   int64_t code_words = 0, bnd_elems = 0, aux_strip_elems = 0, state_elems = 0, row_elems = 0;
   int64_t max_rows = 0;
   int rho = 4;   // barycenter rows per lane of this set's sweeps
+  bool walk_pairs = false;   // path recovery one pair at a time (PATH sweep, no entry tags)
 };
 
 struct Job {
@@ -125,7 +126,7 @@ void build_set(PairSet& ps, std::vector<Job> jobs, int rho) {
 // Workspace: every region 256-byte aligned, in this order.
 struct Layout {
   size_t queue = 0, progress = 0, bnd_r = 0, bnd_aux = 0, codes = 0, out_dist = 0, out_aux = 0;
-  size_t seg = 0, seg_len = 0, seg_off = 0, psum = 0, pcnt = 0, dm = 0, totals = 0;
+  size_t seg = 0, seg_len = 0, seg_off = 0, runs = 0, psum = 0, pcnt = 0, dm = 0, totals = 0;
   size_t rows = 0, states = 0, push_up = 0, push_dg = 0, gsum = 0, hsum = 0, out_end = 0;
   size_t total = 0;
 };
@@ -251,6 +252,7 @@ Layout layout(const wts_plan* p, int op) {
     l.seg_off = take(sizeof(int) * (size_t)ps.n_items);
   }
   if (op == WTS_OP_DBA) {
+    if (ps.walk_pairs) l.runs = take(sizeof(int2) * (size_t)p->n * (size_t)p->L);
     l.psum = take(sizeof(double) * (size_t)p->n * (size_t)p->L * (size_t)p->d);
     l.pcnt = take(sizeof(int) * (size_t)p->n * (size_t)p->L);
   }
@@ -264,6 +266,22 @@ Layout layout(const wts_plan* p, int op) {
 
 template <typename T>
 T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+// Path recovery.  Tagging every cell with its strip entry (PATHT) costs the
+// sweep about a tenth of its time (two selects of about 22 operations per
+// cell) and lets all strips be walked at once; without the tags (PATH) each
+// pair walks its strips in turn, about 85 us per strip on gfx950.  The pair
+// walk pays when the tags' tenth, about 1e-13 s per cell on 256 CUs, exceeds
+// the longest pair's walk.
+bool walk_pairs_pays(const PairSet& ps) {
+  double cells = 0.0;
+  int smax = 0;
+  for (const PairDesc& d : ps.pairs) {
+    cells += (double)d.M * (double)d.N;
+    smax = std::max(smax, d.S);
+  }
+  return cells * 1e-13 > smax * 85e-6;
+}
 
 int default_grid(const wts_plan* p, const PairSet& ps) {
   // 24 one-wave workgroups per CU: enough resident waves for the value sweep
@@ -341,7 +359,9 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
                      hipStream_t st) {
   HIP_TRY(wts::launch_zero(at<int>(ws, l.queue), 2, st));
   HIP_TRY(wts::launch_fill_sentinels(at<double>(ws, l.bnd_r), ps.row_elems, at<int>(ws, l.bnd_aux),
-                                     mode == wts::MODE_DIST ? 0 : ps.row_elems, st));
+                                     mode == wts::MODE_DIST_LEN || mode == wts::MODE_SUB ||
+                                             mode == wts::MODE_PATHT
+                                         ? ps.row_elems : 0, st));
   wts::FwdArgs a{};
   a.pairs = ps.d_pairs;
   a.items = ps.d_sweep_items;
@@ -353,14 +373,14 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
   a.y = y;
   a.bnd_r = at<double>(ws, l.bnd_r);
   a.bnd_aux = at<int>(ws, l.bnd_aux);
-  a.codes = mode == wts::MODE_PATH ? at<uint32_t>(ws, l.codes) : nullptr;
+  a.codes = mode == wts::MODE_PATH || mode == wts::MODE_PATHT ? at<uint32_t>(ws, l.codes) : nullptr;
   a.out_dist = out_dist ? out_dist : at<double>(ws, l.out_dist);
   a.out_aux = at<int>(ws, l.out_aux);
   a.out_end = mode == wts::MODE_SUB ? at<int>(ws, l.out_end) : nullptr;
   a.cost_kind = euc ? 1 : 0;
   a.relaxed_wait = ps.n_items > 16 * p->cus ? 1 : 0;   // > 4 items per SIMD
   const int tk = timing_begin(p, x_is_cycle ? WTS_OP_MEDOID
-                                 : mode == wts::MODE_PATH ? WTS_OP_DBA
+                                 : mode == wts::MODE_PATH || mode == wts::MODE_PATHT ? WTS_OP_DBA
                                  : mode == wts::MODE_SUB ? WTS_OP_SUBDTW : WTS_OP_SCORE, st);
   HIP_TRY(wts::launch_fwd(p->d, ps.rho, mode, euc, x_is_cycle, p->dtype,
                           p->opts.decision == WTS_DECISION_FP32, a, default_grid(p, ps), st));
@@ -368,28 +388,40 @@ wts_status run_sweep(const wts_plan* p, const PairSet& ps, int mode, bool euc, b
   return WTS_OK;
 }
 
-// PATH sweep, strip chain and the first walk (row runs, segment lengths,
-// DBA partial sums when psum != nullptr).
+// The path sweep, then path recovery: segments, segment lengths and, with
+// psum, the DBA partial sums.  Pair walks: a PATH sweep, one walk per pair
+// (row runs), the row sums in parallel.  Strip walks: a PATHT sweep, the
+// strip chain from the entry tags, one walk per strip (row runs and sums).
 wts_status run_paths(const wts_plan* p, const double* bary, const void* cycles, void* ws,
                      const Layout& l, double* out_dist, double* psum, int* pcnt, hipStream_t st) {
   const PairSet& ps = p->bary;
-  wts_status rc = run_sweep(p, ps, wts::MODE_PATH, false, false, bary, cycles, ws, l, out_dist, st);
+  const int mode = ps.walk_pairs ? wts::MODE_PATH : wts::MODE_PATHT;
+  wts_status rc = run_sweep(p, ps, mode, false, false, bary, cycles, ws, l, out_dist, st);
   if (rc != WTS_OK) return rc;
-  HIP_TRY(wts::launch_chain(ps.d_pairs, ps.n_pairs, at<int>(ws, l.bnd_aux),
-                            at<int>(ws, l.out_aux), at<int2>(ws, l.seg), p->d_status,
-                            skip_of(p), st));
   wts::WalkArgs w{};
   w.pairs = ps.d_pairs;
   w.items = ps.d_items;
-  w.seg = at<int2>(ws, l.seg);
   w.codes = at<uint32_t>(ws, l.codes);
   w.y = cycles;
-  w.psum = psum;
-  w.pcnt = pcnt;
   w.L = p->L;
   w.seg_len = at<int>(ws, l.seg_len);
   w.status = p->d_status;
   w.skip = skip_of(p);
+  if (ps.walk_pairs) {
+    w.seg_out = at<int2>(ws, l.seg);
+    w.runs = psum ? at<int2>(ws, l.runs) : nullptr;
+    HIP_TRY(wts::launch_path_walk(ps.rho, w, ps.n_pairs, st));
+    if (psum)
+      HIP_TRY(wts::launch_run_sum(p->d, p->dtype, w.runs, p->d_off, cycles, p->n, p->L, psum,
+                                  pcnt, skip_of(p), st));
+    return WTS_OK;
+  }
+  HIP_TRY(wts::launch_chain(ps.d_pairs, ps.n_pairs, at<int>(ws, l.bnd_aux),
+                            at<int>(ws, l.out_aux), at<int2>(ws, l.seg), p->d_status,
+                            skip_of(p), st));
+  w.seg = at<int2>(ws, l.seg);
+  w.psum = psum;
+  w.pcnt = pcnt;
   HIP_TRY(wts::launch_walk(p->d, ps.rho, p->dtype, false, w, ps.n_items, st));
   return WTS_OK;
 }
@@ -425,6 +457,8 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
   if (o.grid < 0) return fail(WTS_E_ARG, "opts.grid = %d", o.grid);
   if (o.validate != 0 && o.validate != 1) return fail(WTS_E_ARG, "opts.validate = %d: 0 or 1", o.validate);
   if (o.dense_e != 0 && o.dense_e != 1) return fail(WTS_E_ARG, "opts.dense_e = %d: 0 or 1", o.dense_e);
+  if (o.walk != WTS_WALK_AUTO && o.walk != WTS_WALK_STRIPS && o.walk != WTS_WALK_PAIRS)
+    return fail(WTS_E_ARG, "opts.walk = %d: 0, 1 or 2", o.walk);
   if (o.decision != WTS_DECISION_FP64 && o.decision != WTS_DECISION_FP32)
     return fail(WTS_E_ARG, "opts.decision = %d: 0 or 1", o.decision);
   if (o.decision == WTS_DECISION_FP32 && (dtype != WTS_F32 || o.cost != WTS_COST_SQEUCLID))
@@ -467,6 +501,8 @@ wts_status wts_plan_create(wts_plan** out, int device, int32_t n, int32_t d, int
     for (int k = 0; k < n; ++k)
       jobs.push_back(Job{0, p->off[k], (int32_t)L, (int32_t)(p->off[k + 1] - p->off[k]), k});
     build_set(p->bary, jobs, o.rho ? o.rho : bary_rho(L, n, p->cus));
+    p->bary.walk_pairs = o.walk == WTS_WALK_PAIRS ||
+                         (o.walk == WTS_WALK_AUTO && walk_pairs_pays(p->bary));
     build_set(p->soft, jobs, wts::kSoftRho);
     std::vector<Job> tjobs;
     for (int k = 0; k < n; ++k)
@@ -547,6 +583,12 @@ wts_status wts_plan_timing(wts_plan* p, int32_t max_launches) {
   }
   p->ev_op.assign(max_launches, -1);
   return WTS_OK;
+}
+
+int32_t wts_plan_walk(const wts_plan* p) {
+  if (!p) return fail(WTS_E_ARG, "plan is null");
+  if (p->L == 0) return fail(WTS_E_ARG, "a medoid plan recovers no paths");
+  return p->bary.walk_pairs ? WTS_WALK_PAIRS : WTS_WALK_STRIPS;
 }
 
 wts_status wts_plan_bwd_tiles(wts_plan* p, int64_t* swept, int64_t* in_range) {

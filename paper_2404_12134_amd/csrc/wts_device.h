@@ -82,7 +82,10 @@ constexpr int kSoftRho = 2;
 // DIST: value only; DIST_LEN: value and path length; PATH: value and argmin
 // codes; SUB: Sub-DTW (free start; lowest-column minimum of the last row and
 // the start column of its path).
-enum Mode { MODE_DIST = 0, MODE_DIST_LEN = 1, MODE_PATH = 2, MODE_SUB = 3 };
+// MODE_PATH keeps the argmin codes only (the path is then walked pair by
+// pair); MODE_PATHT also tags every cell with the top-row cell through which
+// its path enters the strip, so that all strips can be walked at once.
+enum Mode { MODE_DIST = 0, MODE_DIST_LEN = 1, MODE_PATH = 2, MODE_SUB = 3, MODE_PATHT = 4 };
 
 struct FwdArgs {
   const PairDesc* pairs;

@@ -7,8 +7,8 @@ namespace wts {
 
 namespace {
 
-// Strip-level path recovery.  The forward sweep tagged every cell with the
-// top-row cell through which its optimal path enters the strip (code 2j for
+// Strip-level path recovery after a PATHT sweep.  That sweep tagged every
+// cell with the top-row cell through which its optimal path enters the strip (code 2j for
 // "from (i0-1, j)", 2j+1 for "from (i0-1, j-1)"), and kept that tag for the
 // bottom row of every strip.  Walking the tags from (M-1, N-1) gives, per
 // strip, where the path crosses its bottom row and its top row.
@@ -159,6 +159,134 @@ __global__ __launch_bounds__(kWave) void walk_kernel(WalkArgs a) {
       a.psum[o * D + c] = acc;
     }
     a.pcnt[o] = h - lo + 1;
+  }
+}
+
+// Path recovery, one pair per workgroup.  From (M-1, N-1) the walk follows
+// the argmin codes strip by strip, the bottom strip first: in each strip
+// from the column where the path crosses the strip's bottom row up to the
+// cell of its top row whose code leaves the strip (an up or diagonal move
+// out of row i0), which gives the column where the path crosses the bottom
+// row of the strip above.  Per strip it records the segment (bottom-row
+// column, top-row column) and its length, for the path list, and per row
+// the run of columns [lo, hi] the path occupies (for the DBA sums, which
+// run_sum_kernel forms in parallel).  All 64 lanes walk in lockstep
+// (identical state): the code-word staging is cooperative, and the words
+// read back from LDS are moved to scalar registers, so the walk itself runs
+// on the scalar unit.  A walk that leaves its strip marks the status word,
+// and every strip from there up gets empty runs.
+template <int RHO>
+__global__ __launch_bounds__(kWave) void path_walk_kernel(WalkArgs a) {
+  constexpr int H = kWave * RHO;
+  __shared__ uint32_t blk[kWalkWords][RHO][kWave];
+  const int lane = threadIdx.x;
+  if (skipped(a.skip)) return;
+  const PairDesc pd = a.pairs[blockIdx.x];
+  int2* runs = a.runs ? a.runs + (int64_t)pd.out * a.L : nullptr;   // null: no DBA sums wanted
+  bool bad = false;
+  int jx = pd.N - 1;   // where the path crosses the current strip's bottom row
+  for (int s = pd.S - 1; s >= 0; --s) {
+    const int item = pd.item_base + s;
+    const int i0 = s * H;
+    const int iend = min(pd.M, i0 + H) - 1;
+    const uint32_t* codes = a.codes + pd.code_base + (int64_t)s * pd.WT * RHO * kWave;
+    if (jx < 0 || jx >= pd.N) bad = true;
+    int i = iend, j = jx, hi = jx, jtop = -1, jnext = -1, cnt = 0;
+    int k = (iend - i0) / RHO, r = (iend - i0) - k * RHO;   // lane and row of row i
+    int wlo = 1 << 30, whi = -1;
+    uint32_t cw[RHO];
+    int ck = -1, cwk = -1;
+    while (!bad) {
+      if (j < 0) {   // walked out of the strip: inconsistent codes
+        bad = true;
+        break;
+      }
+      ++cnt;
+      const int t = j + k;
+      const int w = t >> 4;
+      if (k != ck || w != cwk) {   // the RHO words of (lane k, word w) into registers
+        if (w < wlo || w > whi) {
+          __syncthreads();
+          wlo = max(0, w - kWalkWords + 1);
+          whi = w;
+          for (int ww = wlo; ww <= whi; ++ww)
+#pragma unroll
+            for (int rr = 0; rr < RHO; ++rr)
+              blk[ww - wlo][rr][lane] = codes[((int64_t)ww * RHO + rr) * kWave + lane];
+          __syncthreads();
+        }
+        // the same words in every lane: scalar registers, so the walk's
+        // arithmetic and branches below stay on the scalar unit
+#pragma unroll
+        for (int rr = 0; rr < RHO; ++rr) cw[rr] = __builtin_amdgcn_readfirstlane(blk[w - wlo][rr][k]);
+        ck = k;
+        cwk = w;
+      }
+      uint32_t word = cw[0];
+#pragma unroll
+      for (int rr = 1; rr < RHO; ++rr) word = r == rr ? cw[rr] : word;
+      // step u of a word: bit 31-2u = diagonal chosen, bit 30-2u = up chosen
+      const int u = t & 15;
+      const uint32_t code = (word >> (30 - 2 * u)) & 3u;
+      if (code == 0u) {   // left
+        --j;
+        if (u > 0) {
+          // the cells (i, j), (i, j-1), ... of this word that are left moves
+          // too: their fields (steps u-1, u-2, ...) sit above this one
+          const uint32_t rest = word >> (32 - 2 * u);
+          const int more = rest == 0u ? u : (int)(__builtin_ctz(rest) >> 1);
+          j -= more;
+          cnt += more;
+        }
+      } else {
+        if (runs && lane == 0) runs[i] = make_int2(j, hi);
+        if (i == i0) {   // the move out of the strip
+          jtop = j;
+          jnext = j - ((code & 2u) ? 1 : 0);
+          break;
+        }
+        --i;
+        if (--r < 0) {
+          r = RHO - 1;
+          --k;
+        }
+        if (code & 2u) --j;   // diagonal
+        hi = j;
+      }
+    }
+    if (bad) {
+      if (lane == 0) atomicOr(a.status, kStatusBadPath);
+      if (runs)
+        for (int q = i0 + lane; q <= iend; q += kWave) runs[q] = make_int2(0, -1);
+    }
+    if (lane == 0) {
+      a.seg_out[item] = bad ? make_int2(-1, -1) : make_int2(jx, jtop);
+      a.seg_len[item] = bad ? 0 : cnt;
+    }
+    if (s > 0 && !bad && jnext < 0) bad = true;   // the path left row 0 before strip 0
+    jx = jnext;
+  }
+}
+
+// Per (cycle, barycenter row): the sum of the cycle's samples over the run
+// [lo, hi] of the row's path, in descending column order, and its length.
+template <typename TY, int D>
+__global__ void run_sum_kernel(const int2* __restrict__ runs, const int64_t* __restrict__ off,
+                               const void* y, int n, int64_t L, double* __restrict__ psum,
+                               int* __restrict__ pcnt, const int* skip) {
+  if (skipped(skip)) return;
+  const TY* __restrict__ Y = static_cast<const TY*>(y);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < (int64_t)n * L; o += stride) {
+    const int2 rn = runs[o];
+    const int64_t base = off[o / L];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      double acc = 0.0;
+      for (int jj = rn.y; jj >= rn.x; --jj) acc = acc + static_cast<double>(Y[(base + jj) * D + c]);
+      psum[o * D + c] = acc;
+    }
+    pcnt[o] = rn.y - rn.x + 1;
   }
 }
 
@@ -329,6 +457,37 @@ hipError_t launch_chain(const PairDesc* pairs, int n_pairs, const int* bnd_aux,
   hipLaunchKernelGGL(chain_kernel, dim3((n_pairs + 63) / 64), dim3(64), 0, st, pairs, n_pairs,
                      bnd_aux, out_aux, seg, status, skip);
   return hipGetLastError();
+}
+
+hipError_t launch_path_walk(int rho, const WalkArgs& a, int n_pairs, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  if (rho == 4) hipLaunchKernelGGL(path_walk_kernel<4>, dim3(n_pairs), dim3(kWave), 0, st, a);
+  else if (rho == 2) hipLaunchKernelGGL(path_walk_kernel<2>, dim3(n_pairs), dim3(kWave), 0, st, a);
+  else if (rho == 5) hipLaunchKernelGGL(path_walk_kernel<5>, dim3(n_pairs), dim3(kWave), 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename TY, int D>
+static hipError_t launch_run_sum_t(const int2* runs, const int64_t* off, const void* y, int n,
+                                   int64_t L, double* psum, int* pcnt, const int* skip,
+                                   hipStream_t st) {
+  const int64_t rows = (int64_t)n * L;
+  const unsigned blocks = (unsigned)std::min<int64_t>((rows + 255) / 256, 65536);
+  hipLaunchKernelGGL((run_sum_kernel<TY, D>), dim3(blocks), dim3(256), 0, st, runs, off, y, n, L,
+                     psum, pcnt, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_run_sum(int d, int ydtype, const int2* runs, const int64_t* off, const void* y,
+                          int n, int64_t L, double* psum, int* pcnt, const int* skip,
+                          hipStream_t st) {
+  if ((int64_t)n * L <= 0) return hipSuccess;
+#define CALLS(D, R) (ydtype == 0 ? launch_run_sum_t<float, D>(runs, off, y, n, L, psum, pcnt, skip, st) \
+                                 : launch_run_sum_t<double, D>(runs, off, y, n, L, psum, pcnt, skip, st))
+  WTS_D_SWITCH(d, 0, CALLS)
+#undef CALLS
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_zero(int* p, int64_t n, hipStream_t st) {

@@ -11,6 +11,8 @@ struct WalkArgs {
   const PairDesc* pairs;
   const int2* items;
   const int2* seg;          // per item: (bottom-row column, top-row column) of the path
+  int2* seg_out;            // the same, written by the path walk
+  int2* runs;               // [out][L]: the columns [lo, hi] of each row's path run
   const uint32_t* codes;
   const void* y;
   double* psum;             // [out][L][d] per-cycle row sums, or nullptr
@@ -29,11 +31,21 @@ hipError_t launch_fwd(int d, int rho, int mode, bool euc, bool x_is_cycle, int y
                       const FwdArgs& a, int grid, hipStream_t st);
 hipError_t launch_fwd32(int d, int rho, int mode, bool euc, bool x_is_cycle, int ydtype,
                         const FwdArgs& a, int grid, hipStream_t st);
+// Path recovery after a PATHT sweep: the strip chain (segments from the
+// entry tags), then walks of all strips at once (emit = false: row runs,
+// segment lengths and DBA partial sums; emit = true: the path list).
 hipError_t launch_walk(int d, int rho, int ydtype, bool emit, const WalkArgs& a, int n_items,
                        hipStream_t st);
 hipError_t launch_chain(const PairDesc* pairs, int n_pairs, const int* bnd_aux,
                         const int* out_aux, int2* seg, int* status, const int* skip,
                         hipStream_t st);
+// Path recovery after a PATH sweep: one workgroup per pair walks its strips
+// in turn (segments, their lengths, the row runs).
+hipError_t launch_path_walk(int rho, const WalkArgs& a, int n_pairs, hipStream_t st);
+// DBA partial sums per (cycle, barycenter row) from the pair walk's runs.
+hipError_t launch_run_sum(int d, int ydtype, const int2* runs, const int64_t* off, const void* y,
+                          int n, int64_t L, double* psum, int* pcnt, const int* skip,
+                          hipStream_t st);
 hipError_t launch_zero(int* p, int64_t n, hipStream_t st);
 hipError_t launch_fill_sentinels(double* r, int64_t nr, int* x, int64_t nx, hipStream_t st);
 hipError_t launch_seg_prefix(const PairDesc* pairs, int n_pairs, const int* seg_len,

@@ -109,7 +109,10 @@ template <typename TX, typename TY, typename TC, int D, int RHO, int MODE, bool 
 __global__ __launch_bounds__(kWave * kSweepWaves, MODE == MODE_DIST && D <= 4 ? 5 : 1)
 void dtw_fwd_kernel(FwdArgs a) {
   constexpr int H = kWave * RHO;
-  constexpr bool kAux = MODE != MODE_DIST;
+  // tags carried along the argmin: the path length (DIST_LEN), the start
+  // column (SUB) or the strip entry (PATHT); PATH keeps only its codes
+  constexpr bool kAux = MODE == MODE_DIST_LEN || MODE == MODE_SUB || MODE == MODE_PATHT;
+  constexpr bool kCodes = MODE == MODE_PATH || MODE == MODE_PATHT;
   // Y ring; slots kRing .. kRing+15 mirror slots 0 .. 15, so a group of 16
   // steps reads consecutive slots from one base without wrapping
   static_assert(!EUC || sizeof(TC) == 8, "the l2 cost is evaluated in float64 only");
@@ -233,7 +236,7 @@ void dtw_fwd_kernel(FwdArgs a) {
       const bool w = has_next && lane < 16 && j >= 0 && j < N;
       st_dev(rr_out, w ? (tg + lane) * kB : kDrop, stg_r[lane & 15]);
       if (kAux) st_dev(rx_out, w ? (tg + lane) * 4 : kDrop, stg_x[lane & 15]);
-      if (MODE == MODE_PATH) {
+      if (kCodes) {
         const int64_t cw = pd.code_base + (int64_t)(s * pd.WT + (tg >> 4)) * RHO * kWave + lane;
 #pragma unroll
         for (int r = 0; r < RHO; ++r) a.codes[cw + r * kWave] = acc[r];
@@ -306,7 +309,7 @@ void dtw_fwd_kernel(FwdArgs a) {
           if (MODE == MODE_DIST_LEN) {
             upinx = shr1_i32(botx, bxv);
             dgx0 = upprevx;
-          } else if (MODE == MODE_PATH) {
+          } else if (MODE == MODE_PATHT) {
             // top row of the strip (lane 0): entered from above at column j,
             // coded 2j (up) or 2j+1 (diagonal)
             upinx = shr1_i32(botx, 2 * t);
@@ -320,7 +323,7 @@ void dtw_fwd_kernel(FwdArgs a) {
           const TC dg0 = upprev;
           upprev = upin;
           upprevx = upinx;
-          bool isd_r[RHO], isu_r[RHO];   // argmin of each row's cell (PATH)
+          bool isd_r[RHO], isu_r[RHO];   // argmin of each row's cell (PATH, PATHT)
 #pragma unroll
           for (int r = 0; r < RHO; ++r) { isd_r[r] = false; isu_r[r] = false; }
           if (FULL || (j >= 0 && j < N)) {
@@ -338,10 +341,12 @@ void dtw_fwd_kernel(FwdArgs a) {
               if (MODE != MODE_DIST) {
                 const bool isd = dg <= m1;
                 const bool isu = up <= lf;
-                // keep these as lane selects (v_cndmask), not branches
-                const int t1 = __builtin_unpredictable(isu) ? upx : lx[r];
-                const int sel = __builtin_unpredictable(isd) ? dgx : t1;
-                rxv = MODE == MODE_DIST_LEN ? sel + 1 : sel;
+                if (kAux) {
+                  // keep these as lane selects (v_cndmask), not branches
+                  const int t1 = __builtin_unpredictable(isu) ? upx : lx[r];
+                  const int sel = __builtin_unpredictable(isd) ? dgx : t1;
+                  rxv = MODE == MODE_DIST_LEN ? sel + 1 : sel;
+                }
                 isd_r[r] = isd;
                 isu_r[r] = isu;
               }
@@ -368,7 +373,7 @@ void dtw_fwd_kernel(FwdArgs a) {
               sub_start = better ? vx : sub_start;
             }
           }
-          if (MODE == MODE_PATH) {
+          if (kCodes) {
             // every step of every lane shifts two bits into the row's code
             // word (cells outside the grid shift in don't-care bits)
 #pragma unroll
@@ -424,7 +429,7 @@ void dtw_fwd_kernel(FwdArgs a) {
         a.out_end[pd.out] = sub_end;
       } else {
         a.out_dist[pd.out] = v;
-        if (MODE != MODE_DIST) a.out_aux[pd.out] = vx;
+        if (kAux) a.out_aux[pd.out] = vx;
       }
     }
     wave_sync();
@@ -458,12 +463,13 @@ hipError_t launch_one(const FwdArgs& a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The four modes for one (X, Y, compute) type triple; the l2 cost is a
+// The modes for one (X, Y, compute) type triple; the l2 cost is a
 // float64 instance only.
 template <typename TX, typename TY, typename TC, int D, int RHO>
 hipError_t launch_fwd_t(int mode, bool euc, const FwdArgs& a, int grid, hipStream_t st) {
   if (mode == MODE_DIST) return launch_one<TX, TY, TC, D, RHO, MODE_DIST, false>(a, grid, st);
   if (mode == MODE_PATH) return launch_one<TX, TY, TC, D, RHO, MODE_PATH, false>(a, grid, st);
+  if (mode == MODE_PATHT) return launch_one<TX, TY, TC, D, RHO, MODE_PATHT, false>(a, grid, st);
   if (mode == MODE_SUB) {
     if (euc) return hipErrorInvalidValue;
     return launch_one<TX, TY, TC, D, RHO, MODE_SUB, false>(a, grid, st);

@@ -39,10 +39,13 @@ class WtsError(RuntimeError):
  E_DEVICE) = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 
 
+_WALKS = {"auto": 0, "strips": 1, "pairs": 2}
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [("cost", ctypes.c_int32), ("rho", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("decision", ctypes.c_int32),
-                ("band", ctypes.c_double), ("dense_e", ctypes.c_int32)]
+                ("band", ctypes.c_double), ("dense_e", ctypes.c_int32), ("walk", ctypes.c_int32)]
 
 
 def load():
@@ -70,6 +73,7 @@ def load():
         "wts_plan_timing": [P, I32],
         "wts_plan_sweep_ms": [P, ctypes.c_int, P, P],
         "wts_plan_bwd_tiles": [P, P, P],
+        "wts_plan_walk": [P],
         "wts_plan_rho": [P, ctypes.c_int],
         "wts_subdtw": [P, P, P, P, P, P, P, SZ, P],
         "wts_softdtw_grad_cycles": [P, P, P, D, P, P, P, SZ, P],
@@ -97,7 +101,7 @@ def exported_symbols():
             "wts_softdtw_backward", "wts_medoid", "wts_init_barycenter", "wts_precond_step",
             "wts_plan_timing", "wts_plan_sweep_ms", "wts_plan_rho", "wts_subdtw",
             "wts_softdtw_grad_cycles", "wts_plan_status", "wts_barycenter_objective",
-            "wts_anomaly_score_noalloc", "wts_plan_bwd_tiles"]
+            "wts_anomaly_score_noalloc", "wts_plan_bwd_tiles", "wts_plan_walk"]
 
 
 def _check(rc: int):
@@ -163,11 +167,14 @@ class Plan:
     restricts the Soft-DTW calls to a Sakoe-Chiba band of that fraction of
     the longer length (Table I).  dense_e=True makes the Soft-DTW backward
     sweep every tile, also those whose E entries are exactly zero (same
-    results, more time)."""
+    results, more time).  walk picks the path recovery of the DBA and
+    path calls: "strips" (entry tags, all strips walked at once), "pairs"
+    (no tags, each pair walks its strips in turn) or "auto" (the library
+    decides by the batch's size); the results are the same bits."""
 
     def __init__(self, offsets, d: int, dtype: str, L: int, device: int = 0, cost: str = "sq",
                  rho: int = 0, grid: int = 0, band: float = 0.0, validate: bool = False,
-                 decision: str = "fp64", dense_e: bool = False):
+                 decision: str = "fp64", dense_e: bool = False, walk: str = "auto"):
         lib = load()
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         self.offsets = off
@@ -180,10 +187,12 @@ class Plan:
             raise ValueError("dtype must be 'f32' or 'f64'")
         if decision not in ("fp64", "fp32"):
             raise ValueError("decision must be 'fp64' or 'fp32'")
+        if walk not in _WALKS:
+            raise ValueError("walk must be 'auto', 'strips' or 'pairs'")
         self.decision = decision
         opts = _Opts(COST_EUCLID if cost == "euclid" else COST_SQ, int(rho), int(grid),
                      1 if validate else 0, DECISION_FP32 if decision == "fp32" else DECISION_FP64,
-                     float(band), 1 if dense_e else 0)
+                     float(band), 1 if dense_e else 0, _WALKS[walk])
         h = ctypes.c_void_p()
         _check(lib.wts_plan_create(ctypes.byref(h), self.device, self.n, self.d,
                                    F32 if dtype == "f32" else F64,
@@ -231,6 +240,12 @@ class Plan:
         cnt = ctypes.c_int32(0)
         _check(load().wts_plan_sweep_ms(self._h, int(op), ctypes.byref(tot), ctypes.byref(cnt)))
         return tot.value, cnt.value
+
+    def walk(self) -> str:
+        """The path recovery of this plan's barycenter calls: "strips" or "pairs"."""
+        w = int(load().wts_plan_walk(self._h))
+        _check(min(w, 0))
+        return {1: "strips", 2: "pairs"}[w]
 
     def bwd_tiles(self):
         """(tiles swept, tiles in range) of the Soft-DTW backward kernels of this

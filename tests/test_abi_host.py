@@ -80,6 +80,8 @@ def test_plan_create_rejects_bad_shapes_before_any_gpu_call(lib):
     for band in (-0.5, float("nan"), float("inf")):   # Sakoe-Chiba bandwidth
         assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 0, band=band)))[0] == WTS_E_ARG
     assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 7)))[0] == WTS_E_ARG   # validate: 0 or 1
+    for wk in (-1, 3):                                                            # walk: 0, 1 or 2
+        assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 0, walk=wk)))[0] == WTS_E_ARG
     for de in (-1, 2):                                                            # dense_e: 0 or 1
         assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, 0, dense_e=de)))[0] == WTS_E_ARG
     assert _create(lib, opts=ctypes.byref(_Opts(0, 4, 0, -1)))[0] == WTS_E_ARG
