@@ -203,6 +203,14 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
     const double band_b = BAND ? band_halfwidth(M, N, a.band) : 0.0;
     int band_jlo = 0, band_jhi = N - 1;
     if (BAND) band_strip_cols(M, N, a.band, i0, min(i0 + H, M) - 1, &band_jlo, &band_jhi);
+    // columns inside the band on every row of the strip (from the last row's
+    // left edge to the first row's right edge; empty when they cross): a
+    // group whose columns all lie there needs no band test.  The rows past
+    // M - 1 of the last strip count too: the band test keeps them at +inf
+    // where the band's formula puts them outside, and the unbanded arithmetic
+    // would turn three +inf inputs into NaN.
+    int band_in_lo = 0, band_in_hi = -1;
+    if (BAND) band_strip_cols(M, N, a.band, i0 + H - 1, i0, &band_in_lo, &band_in_hi);
     const bool has_prev = s > 0;
     const bool has_next = s + 1 < pd.S;
     const int Tend = pd.WT * 16;
@@ -291,8 +299,12 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
       }
       __syncthreads();
 
-      auto group16 = [&](auto full_tag, int tb) {
+      // FULL: every lane is inside the grid (no masking); INSIDE: every cell
+      // is inside the band as well (the unbanded arithmetic, which gives an
+      // in-band cell the same bits as the band test's path)
+      auto group16 = [&](auto full_tag, auto inside_tag, int tb) {
         constexpr bool FULL = decltype(full_tag)::value;
+        constexpr bool TEST = BAND && !decltype(inside_tag)::value;
         const int tg = t0 + tb;
         {   // checkpoint: the sweep state at the start of these 16 steps
           double* p = st + (int64_t)(tg >> 4) * (RHO + 1) * kWave + lane;
@@ -321,7 +333,7 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
             for (int r = 0; r < RHO; ++r) {
               const double lf = left[r];
               double rv;
-              if constexpr (BAND) {
+              if constexpr (TEST) {
                 const bool inb = __builtin_fabs(bd0 + (double)r * (double)(N - 1)) <= band_b;
                 const SoftMin sm = softmin3_band(dg, up, lf, inb);
                 rv = inb ? sq_cost<D>(xr[r], xx[r], y, yy) + sm.v : INF;
@@ -362,9 +374,16 @@ __global__ __launch_bounds__(kWave) void soft_fwd_kernel(SoftArgs a) {
       };
       for (int tb = 0; tb < tcnt; tb += 16) {
         const int tg = t0 + tb;
-        if (BAND && (tg + 15 < band_jlo || tg - (kWave - 1) > band_jhi)) skip16(tb);
-        else if (tg >= kWave - 1 && tg + 16 <= N) group16(std::true_type{}, tb);
-        else group16(std::false_type{}, tb);
+        if (BAND && (tg + 15 < band_jlo || tg - (kWave - 1) > band_jhi)) {
+          skip16(tb);
+        } else if (tg >= kWave - 1 && tg + 16 <= N) {
+          if (BAND && tg - (kWave - 1) >= band_in_lo && tg + 15 <= band_in_hi)
+            group16(std::true_type{}, std::true_type{}, tb);
+          else
+            group16(std::true_type{}, std::false_type{}, tb);
+        } else {
+          group16(std::false_type{}, std::false_type{}, tb);
+        }
       }
       __syncthreads();
       if (has_next) {

@@ -220,15 +220,18 @@ def test_soft_band_matches_oracle(wts, w, L, lens):
         check_vec(h.cpu().numpy(), oh)
 
 
-def test_soft_wide_band_is_bitwise_unbanded(wts):
+@pytest.mark.parametrize("d,L,lens", [(2, 300, (280, 333)), (6, 1200, (1100, 1500, 640))])
+def test_soft_wide_band_is_bitwise_unbanded(wts, d, L, lens):
     """A band wider than every pair keeps every cell: the banded kernels then
-    compute exactly the unbanded bits."""
+    compute exactly the unbanded bits (the forward's groups inside the band
+    take the unbanded arithmetic, the others the band test's)."""
     import torch
-    r = rng(71)
-    B = r.standard_normal((300, 2))
-    cyc = [r.standard_normal((N, 2)).astype(np.float32) for N in (280, 333)]
+    r = rng(71 + d)
+    B = r.standard_normal((L, d))
+    cyc = [r.standard_normal((N, d)).astype(np.float32) for N in lens]
     outs = []
     for band in (0.0, 10.0):
+        say("soft wide band d=%d L=%d lens=%s band=%g" % (d, L, lens, band))
         plan, Bt, Y = setup(wts, B, cyc, band=band)
         v, ck = wts.softdtw_forward(plan, Bt, Y, 0.5)
         g, h = wts.softdtw_backward(plan, Bt, Y, 0.5, ck, with_mass=True)
@@ -236,6 +239,28 @@ def test_soft_wide_band_is_bitwise_unbanded(wts):
         outs.append((v.cpu().numpy(), g.cpu().numpy(), h.cpu().numpy()))
     for a, b in zip(*outs):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("w", [0.3, 0.05])
+def test_soft_band_six_channels_matches_oracle(wts, w):
+    """The six-channel banded instance over several strips, with groups
+    inside, across and outside the band: values, gradient and row mass
+    within 1e-4 of the oracle."""
+    import torch
+    r = rng(int(1000 * w) + 6)
+    B = r.standard_normal((900, 6))
+    cyc = [r.standard_normal((N, 6)).astype(np.float32) for N in (800, 1000, 450)]
+    wv = r.uniform(0.5, 1.5, 3)
+    say("soft band six channels w=%g" % w)
+    plan, Bt, Y = setup(wts, B, cyc, band=w)
+    val, ck = wts.softdtw_forward(plan, Bt, Y, 0.1)
+    g, h = wts.softdtw_backward(plan, Bt, Y, 0.1, ck, torch.from_numpy(wv).cuda(), with_mass=True)
+    torch.cuda.synchronize()
+    assert plan.status() == wts.OK
+    ov, og, oh = oracle.softdtw_batch(B, [np.asarray(c, np.float64) for c in cyc], 0.1, wv, band=w)
+    check_vec(val.cpu().numpy(), ov)
+    check_vec(g.cpu().numpy(), og)
+    check_vec(h.cpu().numpy(), oh)
 
 
 @pytest.mark.parametrize("offset", [1e3, 1e6])
